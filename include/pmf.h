@@ -1,0 +1,173 @@
+/*
+ * pmf.h -- C ABI of libpmf: exact parametric maximum flow / minimum s-t cut on
+ * 4- and 8-connected image grids, solved on one AMD Instinct MI355X (gfx950).
+ *
+ * The problem (paper Sec. 2 and 2.1): every pixel is a vertex linked to the
+ * source s and the sink t by terminal arcs (data terms) and to its neighbours
+ * by smoothness arcs.  Seeds are pixels frozen to a label: foreground seeds
+ * are tied to s, background seeds to t, both with capacity PMF_INF.  The sink
+ * capacity of a free pixel grows linearly with a parameter lambda (the
+ * monotone parametric case, whose optimal source sets are nested), and a
+ * preset, non-decreasing lambda schedule is solved (the "lambda-schedule" of
+ * Sec. 2.1).  For every lambda of every instance the library returns
+ *   - the maximum flow value F(lambda) (= minimum cut cost, Ford-Fulkerson),
+ *   - the inclusion-minimal minimum-cut source side S_min(lambda) as a mask.
+ * Results are exact integers and do not depend on launch configuration.
+ *
+ * Many instances of different sizes are solved in one call; they are packed
+ * into the same device launches (the device-side counterpart of the paper's
+ * lambda- and seed-supergraphs, Sec. 3.1).
+ *
+ * Conventions
+ *   - Direction k has offset (DX[k], DY[k]) with
+ *       DX = { 1,-1, 0, 0, 1,-1,-1, 1 },  DY = { 0, 0, 1,-1, 1,-1, 1,-1 };
+ *     k ^ 1 is the opposite direction.  K = 4 uses directions 0..3, K = 8 all.
+ *   - All planes are row-major, pixel p = y * W + x, no padding.
+ *   - "device" pointers are HIP device memory on the handle's device; the
+ *     caller owns them.  No function takes ownership of caller memory.
+ *   - Every function returns PMF_OK (0) or a positive PMF_E* code; no C++
+ *     exception crosses this interface.
+ */
+#ifndef PMF_H
+#define PMF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PMF_INF (1 << 30) /* capacity of the terminal arcs of seeds */
+
+enum pmf_status {
+    PMF_OK = 0,
+    PMF_EINVAL = 1,     /* bad argument or bad capacity value            */
+    PMF_EOVERFLOW = 2,  /* capacities exceed the int32 headroom (below)  */
+    PMF_ENOMEM = 3,     /* device memory or workspace too small          */
+    PMF_EDEVICE = 4,    /* HIP runtime error                             */
+    PMF_ETIMEOUT = 5,   /* superstep budget exhausted for an instance    */
+    PMF_ENOTSOLVED = 6, /* no completed solve to read from               */
+    PMF_ERANGE = 7,     /* instance or lambda index out of range         */
+    PMF_EBUSY = 8       /* no free slot; retry after results are released */
+};
+
+/* Solver options.  Fill with pmf_default_options(); every field is a tuning
+ * knob that changes speed, never results. */
+typedef struct pmf_options {
+    int32_t tile_w;             /* tile width in pixels: 32 or 64 (0 = default)     */
+    int32_t tile_h;             /* tile height: tile_w * tile_h = 1024 (0 = default) */
+    int32_t inner_iters;        /* push/relabel iterations per tile visit            */
+    int32_t sweeps_per_relabel; /* sweep supersteps between global relabels          */
+    int32_t local_bfs_iters;    /* bound on relaxation rounds per tile visit         */
+    int32_t steps_per_sync;     /* supersteps per host completion check              */
+    int64_t max_supersteps;     /* per-instance budget; exceeding it = PMF_ETIMEOUT  */
+    int32_t use_graph;          /* 1: replay supersteps from a captured hipGraph     */
+    int32_t order;              /* 0: FIFO packing order, 1: LPT (largest first)     */
+    int64_t mem_budget;         /* bytes the library may allocate (0 = no limit)     */
+    int32_t max_slots;          /* instance slots of a serving session (0 = 4096)    */
+    int32_t reserved[7];
+} pmf_options;
+
+/* One (image, seed) problem and its lambda schedule.  All pointers are device
+ * pointers that must stay valid until the solve that uses them has returned
+ * (pmf_solve_batch) or the instance has completed (serving calls).
+ *
+ *   nlink     int32 [K][H][W]  capacity of the arc p -> p + d_k, 0 <= c <= PMF_NLINK_MAX(K);
+ *                              must be 0 where the neighbour is off the grid.
+ *                              Instances of one image may share this pointer.
+ *   cap_src   int32 [H][W]     source capacity of free pixels, 0..PMF_INF
+ *   cap_snk0  int32 [H][W]     sink capacity of free pixels at lambda = 0, >= 0
+ *   snk_slope int32 [H][W]     d(sink capacity)/d(lambda) of free pixels, >= 0;
+ *                              NULL means 1 everywhere
+ *   seed      uint8 [H][W]     0 free, 1 foreground (cs = INF, ct = 0),
+ *                              2 background (cs = 0, ct = INF); NULL = all free
+ *   lambdas   int32 [L]        non-decreasing, >= 0; duplicates allowed
+ *
+ * Headroom: every per-pixel quantity of the solver is an int32.  The call
+ * fails with PMF_EOVERFLOW unless cap_snk0 + snk_slope * lambdas[L-1] <= INF
+ * and every n-link capacity is at most PMF_NLINK_MAX(K), which keeps excess
+ * (<= INF + K * max n-link) below 2^31. */
+typedef struct pmf_instance {
+    int32_t W, H, K, L;
+    const int32_t *nlink;
+    const int32_t *cap_src;
+    const int32_t *cap_snk0;
+    const int32_t *snk_slope;
+    const uint8_t *seed;
+    const int32_t *lambdas;
+} pmf_instance;
+
+#define PMF_NLINK_MAX(K) ((int32_t)(((1 << 30) - 1) / (K)))
+
+typedef struct pmf_handle pmf_handle;
+
+/* Per-handle counters of the last solve (or of the session so far). */
+typedef struct pmf_stats {
+    int64_t supersteps;       /* device launches of the superstep kernel            */
+    int64_t sweep_visits;     /* tile visits that ran push/relabel iterations       */
+    int64_t global_relabels;  /* completed global relabels (all instances)          */
+    int64_t bfs_passes;       /* tile-parallel relaxation passes (relabel + cut)    */
+    int64_t host_syncs;       /* host completion checks                             */
+    int64_t device_bytes;     /* bytes of device memory held by the handle          */
+} pmf_stats;
+
+/* Fill *opt with defaults. */
+void pmf_default_options(pmf_options *opt);
+
+/* Create a handle bound to the current HIP device and to `stream` (a
+ * hipStream_t; NULL = the default stream).  `workspace` (device memory of
+ * `ws_bytes` bytes, caller-owned) is used for all solver state when non-NULL;
+ * otherwise the library allocates with hipMalloc, within opt->mem_budget.
+ * opt may be NULL (defaults).  Errors: PMF_EINVAL (bad option or NULL out),
+ * PMF_EDEVICE. */
+int pmf_create(const pmf_options *opt, void *stream, void *workspace, size_t ws_bytes,
+               pmf_handle **out);
+
+/* Solve every lambda of n_inst instances (Sec. 2.1 schedule), packed into
+ * shared launches.  flows_out (device, int64 [sum of L_i]) receives F in
+ * (instance, lambda) order; status_out (device, int32 [n_inst], may be NULL)
+ * receives PMF_OK, PMF_EINVAL / PMF_EOVERFLOW (bad capacities found on the
+ * device; that instance's flows are -1) or PMF_ETIMEOUT (budget exhausted;
+ * flows of unfinished lambdas are -1).  Masks stay in library memory until
+ * the next solve or destroy (read them with pmf_extract_cut).
+ * The call enqueues work on the handle's stream and returns when every
+ * instance has finished; results are then complete in device memory.
+ * Host-side errors (returned before any launch): PMF_EINVAL (K not 4 or 8,
+ * W, H, L < 1, NULL pointers), PMF_ENOMEM, PMF_EDEVICE. */
+int pmf_solve_batch(pmf_handle *h, const pmf_instance *inst, int32_t n_inst, int64_t *flows_out,
+                    int32_t *status_out);
+
+/* Copy the minimal source side S_min of (instance inst, lambda index
+ * lambda_idx) of the last solve into mask_out (device, uint8 [H][W]):
+ * 1 = source side (foreground), 0 = sink side.  Enqueued on the handle's
+ * stream.  Errors: PMF_ENOTSOLVED (no solve yet, or that instance did not
+ * finish), PMF_ERANGE. */
+int pmf_extract_cut(pmf_handle *h, int32_t inst, int32_t lambda_idx, uint8_t *mask_out);
+
+/* Synchronise the stream and free everything the library allocated. */
+int pmf_destroy(pmf_handle *h);
+
+/* Static description of a status code. */
+const char *pmf_strerror(int code);
+
+/* Device bytes a solve of these instances needs (for admission by free
+ * memory).  opt may be NULL. */
+int pmf_query_bytes(const pmf_instance *inst, int32_t n_inst, const pmf_options *opt,
+                    size_t *bytes);
+
+/* The host-side checks pmf_solve_batch makes before any launch (K is 4 or 8;
+ * W, H, L >= 1; W * H <= 2^29; nlink, cap_src, cap_snk0, lambdas non-NULL).
+ * Reads no device memory, so it needs no GPU.  On failure *first_bad (may be
+ * NULL) receives the index of the first offending instance.  Returns PMF_OK
+ * or PMF_EINVAL. */
+int pmf_check_instances(const pmf_instance *inst, int32_t n_inst, int32_t *first_bad);
+
+/* Counters of the last solve. */
+int pmf_get_stats(pmf_handle *h, pmf_stats *out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PMF_H */

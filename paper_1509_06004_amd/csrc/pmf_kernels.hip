@@ -1,0 +1,773 @@
+// HIP kernels of libpmf for gfx950: exact push-relabel max-flow on grid graphs.
+//
+// Method (paper Sec. 2: s-t graph of an image, max flow = min cut; Sec. 2.1:
+// monotone parametric capacities solved over a lambda schedule, nested
+// optimal cuts; Sec. 3.1: many graphs solved together as one "supergraph").
+// The push-relabel algorithm the paper runs as a closed library is rebuilt
+// here from its textbook definition (Goldberg-Tarjan), with exact global
+// relabelling by breadth-first search (Cherkassky-Goldberg):
+//
+//   - every launch is one *superstep*: each workgroup takes one tile
+//     (TW x TH pixels) of one instance and performs that instance's current
+//     phase on it; the last workgroup to finish advances every instance's
+//     phase machine (no host round trip, no grid barrier);
+//   - kSweep: the tile's state is loaded into registers / LDS and
+//     `inner_iters` synchronous push/relabel iterations run against halo
+//     heights; pushes that leave the tile are accumulated and handed to the
+//     neighbour tile through an atomic inbox;
+//   - kRelabel: exact distances to t by tile-parallel Bellman-Ford relaxation
+//     (tile-local relaxation to a fixed point, repeated over the tiles whose
+//     neighbourhood changed).  A pass in which no label changes proves the
+//     distances exact; pixels that cannot reach t get H_INF (this subsumes the
+//     gap heuristic: every vertex above an empty level is unreachable).  If no
+//     pixel with excess can still reach t, the preflow is maximum;
+//   - kCut: the minimal source side is the set of pixels reachable in the
+//     residual graph from the pixels still holding excess (all source arcs
+//     stay saturated, so s itself reaches nothing else);
+//   - F = (total source capacity) - (total excess left on pixels);
+//   - warm start: after a lambda is finished the sink residuals grow by
+//     slope * (lambda' - lambda); the preflow stays feasible, so the next
+//     lambda continues from it after a fresh global relabel.
+//
+// Correctness never depends on labels being valid between global relabels:
+// the bookkeeping is exact integer arithmetic and termination is certified by
+// an exact relabel on a quiescent state.
+#include <hip/hip_runtime.h>
+
+#include "pmf.h"
+#include "pmf_internal.h"
+
+namespace pmf {
+
+__device__ constexpr int DXk(int k) {
+    return k == 0 ? 1 : k == 1 ? -1 : k == 2 ? 0 : k == 3 ? 0 : k == 4 ? 1 : k == 5 ? -1 : k == 6 ? -1 : 1;
+}
+__device__ constexpr int DYk(int k) {
+    return k == 0 ? 0 : k == 1 ? 0 : k == 2 ? 1 : k == 3 ? -1 : k == 4 ? 1 : k == 5 ? -1 : k == 6 ? 1 : -1;
+}
+
+template <typename T>
+__device__ __forceinline__ T ld_agent(const T *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <int TW, int TH>
+struct Geo {
+    static constexpr int NT = kThreads;
+    static constexpr int PPT = TW * TH / NT;  // pixels per thread
+    static constexpr int RPI = NT / TW;       // rows covered by one pass of the block
+    static constexpr int HW = TW + 2;
+    static constexpr int HH = TH + 2;
+    static constexpr int HALO = HW * HH;
+    static constexpr int RING = 2 * HW + 2 * TH;
+    static_assert(TW * TH % NT == 0, "tile must be a multiple of the block");
+    static_assert(NT % TW == 0, "tile width must divide the block");
+    __device__ static inline void ring(int i, int &hx, int &hy) {
+        if (i < HW) {
+            hx = i;
+            hy = 0;
+        } else if (i < 2 * HW) {
+            hx = i - HW;
+            hy = HH - 1;
+        } else if (i < 2 * HW + TH) {
+            hx = 0;
+            hy = 1 + (i - 2 * HW);
+        } else {
+            hx = HW - 1;
+            hy = 1 + (i - 2 * HW - TH);
+        }
+    }
+};
+
+// Shared by all phases: block-wide integer sum (returned to every thread).
+__device__ __forceinline__ int block_sum_int(int v, int *s_red) {
+    __syncthreads();
+    if (threadIdx.x == 0) s_red[0] = 0;
+    __syncthreads();
+    if (v) atomicAdd(&s_red[0], v);
+    __syncthreads();
+    return s_red[0];
+}
+
+__device__ __forceinline__ long long block_sum_i64(long long v, unsigned long long *s_sum) {
+    __syncthreads();
+    if (threadIdx.x == 0) *s_sum = 0ull;
+    __syncthreads();
+    if (v) atomicAdd(s_sum, (unsigned long long)v);
+    __syncthreads();
+    return (long long)*s_sum;
+}
+
+// ---------------------------------------------------------------------------
+// kInit: terminal-arc normalisation at lambda_0 and validation of the inputs.
+//   cs, ct per pixel from (seed, cap_src, cap_snk0, slope, lambda_0);
+//   the common part m = min(cs, ct) goes straight from s to t: e = cs - m,
+//   rt = ct - m; r_k = n-link capacity; inbox cleared.
+// ---------------------------------------------------------------------------
+template <int K, int TW, int TH>
+__device__ void init_tile(const StepParams &P, const InstDesc &D, InstState *S, int tg, int tl,
+                          int *s_red, unsigned long long *s_sum) {
+    using G = Geo<TW, TH>;
+    const int tid = threadIdx.x, lx = tid % TW, ly0 = tid / TW;
+    const int tx = tl % D.tiles_x, ty = tl / D.tiles_x;
+    const int x0 = tx * TW, y0 = ty * TH;
+    const int W = D.W, H = D.H, n = D.n;
+    const long long lam0 = D.lambdas[0];
+    const long long lamL = D.lambdas[D.L - 1];
+    const int32_t nlmax = ((1 << 30) - 1) / K;
+    int err = 0;
+    long long scs = 0;
+#pragma unroll
+    for (int j = 0; j < G::PPT; ++j) {
+        const int ly = ly0 + j * G::RPI;
+        const int gx = x0 + lx, gy = y0 + ly;
+        if (gx >= W || gy >= H) continue;
+        const int p = gy * W + gx;
+        const int sd = D.seed ? (int)D.seed[p] : 0;
+        long long cs, ct;
+        if (sd == 1) {
+            cs = kInf;
+            ct = 0;
+        } else if (sd == 2) {
+            cs = 0;
+            ct = kInf;
+        } else {
+            const long long c0 = D.cap_snk0[p];
+            const long long sl = D.slope ? D.slope[p] : 1;
+            cs = D.cap_src[p];
+            if (sd != 0) err |= 1;
+            if (cs < 0 || cs > kInf || c0 < 0 || sl < 0) err |= 1;
+            if (c0 + sl * lamL > kInf) err |= 2;
+            ct = c0 + sl * lam0;
+            cs = cs < 0 ? 0 : (cs > kInf ? kInf : cs);
+            ct = ct < 0 ? 0 : (ct > kInf ? kInf : ct);
+        }
+        const long long m = cs < ct ? cs : ct;
+        const int e = (int)(cs - m);
+        const int rt = (int)(ct - m);
+        scs += cs;
+        int rm = (rt > 0 ? kRtBit : 0) | (e > 0 ? kEBit : 0);
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const int qx = gx + DXk(k), qy = gy + DYk(k);
+            const bool on = qx >= 0 && qx < W && qy >= 0 && qy < H;
+            int c = D.nlink[(size_t)k * n + p];
+            if (c < 0 || (!on && c != 0)) err |= 1;
+            if (c > nlmax) err |= 2;
+            if (!on || c < 0) c = 0;
+            if (c > nlmax) c = nlmax;
+            D.r[(size_t)k * n + p] = c;
+            D.inbox[(size_t)k * n + p] = 0;
+            if (c > 0) rm |= 1 << k;
+        }
+        D.e[p] = e;
+        D.rt[p] = rt;
+        D.h[p] = rt > 0 ? 1 : kHInf;
+        D.rmask[p] = (uint16_t)rm;
+    }
+    if (tl == 0 && tid < 64) {
+        // the schedule: lambda_0 >= 0, non-decreasing
+        for (int i = tid; i < D.L; i += 64) {
+            const int li = D.lambdas[i];
+            if (li < 0 || (i > 0 && li < D.lambdas[i - 1])) err |= 1;
+        }
+    }
+    const long long tot = block_sum_i64(scs, s_sum);
+    if (tid == 0) {
+        if (tot) atomicAdd((unsigned long long *)&S->sum_cs, (unsigned long long)tot);
+        P.tile_act[tg] = 0;
+        P.tile_cnt[tg] = 0;
+        P.tile_chg[tg] = 1;
+        P.tile_chg[P.ntiles + tg] = 1;
+    }
+    if (err) atomicOr(&S->err, err);
+    (void)s_red;
+}
+
+// ---------------------------------------------------------------------------
+// kSweep: tile-local push/relabel iterations in registers + LDS.
+// ---------------------------------------------------------------------------
+template <int K, int TW, int TH>
+__device__ void sweep_tile(const StepParams &P, const InstDesc &D, InstState *S, int tg, int tl,
+                           int32_t *lds, int *s_red) {
+    using G = Geo<TW, TH>;
+    constexpr int PPT = G::PPT, RPI = G::RPI, HW = G::HW;
+    const int tid = threadIdx.x, lx = tid % TW, ly0 = tid / TW;
+    // neighbours may set the pending bit concurrently: one read, broadcast
+    if (tid == 0) s_red[1] = (int)(ld_agent(&P.tile_act[tg]) & 3u);
+    __syncthreads();
+    if (s_red[1] == 0) return;  // nothing to push here, nothing arrived
+    const int tx = tl % D.tiles_x, ty = tl / D.tiles_x;
+    const int x0 = tx * TW, y0 = ty * TH;
+    const int W = D.W, H = D.H, n = D.n;
+    const int hcap = n + 1;  // no exact distance to t exceeds n
+    int32_t *sh_h = lds;
+    int32_t *sh_out = lds + ((G::HALO + 3) & ~3);
+    __shared__ int s_nb[9];
+
+    if (tid < 9) s_nb[tid] = 0;
+    if (tid == 0) atomicAnd(&P.tile_act[tg], ~2u);  // about to drain the inbox
+    __syncthreads();
+
+    int r[PPT][K], e[PPT], rt[PPT], h[PPT], hacc[PPT][K];
+    bool valid[PPT];
+#pragma unroll
+    for (int j = 0; j < PPT; ++j) {
+        const int ly = ly0 + j * RPI;
+        const int gx = x0 + lx, gy = y0 + ly;
+        valid[j] = gx < W && gy < H;
+#pragma unroll
+        for (int k = 0; k < K; ++k) hacc[j][k] = 0;
+        if (valid[j]) {
+            const int p = gy * W + gx;
+#pragma unroll
+            for (int k = 0; k < K; ++k) r[j][k] = D.r[(size_t)k * n + p];
+            e[j] = D.e[p];
+            rt[j] = D.rt[p];
+            h[j] = D.h[p];
+            // drain flow pushed in by neighbour tiles
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                const int nx = lx + DXk(k), ny = ly + DYk(k);
+                if (nx >= 0 && nx < TW && ny >= 0 && ny < TH) continue;
+                const int qx = gx + DXk(k), qy = gy + DYk(k);
+                if (qx < 0 || qx >= W || qy < 0 || qy >= H) continue;
+                int32_t *slot = &D.inbox[(size_t)k * n + p];
+                int v = ld_agent(slot);
+                if (v) {
+                    v = atomicExch(slot, 0);
+                    e[j] += v;
+                    r[j][k] += v;
+                }
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < K; ++k) r[j][k] = 0;
+            e[j] = 0;
+            rt[j] = 0;
+            h[j] = kHInf;
+        }
+        sh_h[(ly + 1) * HW + lx + 1] = h[j];
+    }
+    for (int i = tid; i < G::RING; i += kThreads) {
+        int hx, hy;
+        G::ring(i, hx, hy);
+        const int gx = x0 + hx - 1, gy = y0 + hy - 1;
+        sh_h[hy * HW + hx] = (gx >= 0 && gx < W && gy >= 0 && gy < H) ? D.h[gy * W + gx] : kHInf;
+    }
+    __syncthreads();
+
+    for (int it = 0; it < P.inner_iters; ++it) {
+        // push: every active pixel sends as much as it can along admissible arcs
+#pragma unroll
+        for (int j = 0; j < PPT; ++j) {
+            const int ly = ly0 + j * RPI;
+            int o[K];
+#pragma unroll
+            for (int k = 0; k < K; ++k) o[k] = 0;
+            if (e[j] > 0 && h[j] < kHInf) {
+                if (rt[j] > 0) {
+                    const int d = e[j] < rt[j] ? e[j] : rt[j];
+                    e[j] -= d;
+                    rt[j] -= d;
+                }
+#pragma unroll
+                for (int k = 0; k < K; ++k) {
+                    if (e[j] > 0 && r[j][k] > 0) {
+                        const int hq = sh_h[(ly + 1 + DYk(k)) * HW + lx + 1 + DXk(k)];
+                        if (hq == h[j] - 1) {
+                            const int d = e[j] < r[j][k] ? e[j] : r[j][k];
+                            e[j] -= d;
+                            r[j][k] -= d;
+                            const int nx = lx + DXk(k), ny = ly + DYk(k);
+                            if (nx >= 0 && nx < TW && ny >= 0 && ny < TH)
+                                o[k] = d;
+                            else
+                                hacc[j][k] += d;
+                        }
+                    }
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < K; ++k) sh_out[k * (TW * TH) + ly * TW + lx] = o[k];
+        }
+        __syncthreads();
+        // gather pushes from in-tile neighbours, then relabel stuck pixels
+        int any = 0;
+#pragma unroll
+        for (int j = 0; j < PPT; ++j) {
+            const int ly = ly0 + j * RPI;
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                const int nx = lx + DXk(k), ny = ly + DYk(k);
+                if (nx >= 0 && nx < TW && ny >= 0 && ny < TH) {
+                    const int inc = sh_out[(k ^ 1) * (TW * TH) + ny * TW + nx];
+                    e[j] += inc;
+                    r[j][k] += inc;
+                }
+            }
+            if (e[j] > 0 && h[j] < kHInf) {
+                bool adm = rt[j] > 0;
+                int mn = kHInf;
+#pragma unroll
+                for (int k = 0; k < K; ++k) {
+                    if (r[j][k] > 0) {
+                        const int hq = sh_h[(ly + 1 + DYk(k)) * HW + lx + 1 + DXk(k)];
+                        if (hq == h[j] - 1) adm = true;
+                        if (hq < kHInf && hq + 1 < mn) mn = hq + 1;
+                    }
+                }
+                if (!adm) {
+                    h[j] = mn >= hcap ? kHInf : mn;
+                    sh_h[(ly + 1) * HW + lx + 1] = h[j];
+                }
+                any |= h[j] < kHInf;
+            }
+        }
+        if (!__syncthreads_or(any)) break;
+    }
+
+    // write back and hand cross-tile pushes to the neighbours' inboxes
+    int active = 0;
+#pragma unroll
+    for (int j = 0; j < PPT; ++j) {
+        if (!valid[j]) continue;
+        const int ly = ly0 + j * RPI;
+        const int gx = x0 + lx, gy = y0 + ly;
+        const int p = gy * W + gx;
+        int rm = (rt[j] > 0 ? kRtBit : 0) | (e[j] > 0 ? kEBit : 0);
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            D.r[(size_t)k * n + p] = r[j][k];
+            if (r[j][k] > 0) rm |= 1 << k;
+            if (hacc[j][k] > 0) {
+                const int q = (gy + DYk(k)) * W + gx + DXk(k);
+                atomicAdd(&D.inbox[(size_t)(k ^ 1) * n + q], hacc[j][k]);
+                const int nx = lx + DXk(k), ny = ly + DYk(k);
+                const int dtx = nx < 0 ? 0 : (nx >= TW ? 2 : 1);
+                const int dty = ny < 0 ? 0 : (ny >= TH ? 2 : 1);
+                s_nb[dty * 3 + dtx] = 1;
+            }
+        }
+        D.e[p] = e[j];
+        D.rt[p] = rt[j];
+        D.h[p] = h[j];
+        D.rmask[p] = (uint16_t)rm;
+        active |= e[j] > 0 && h[j] < kHInf;
+    }
+    const int tile_active = __syncthreads_or(active);
+    if (tid < 9 && tid != 4 && s_nb[tid]) {
+        const int ntx = tx + (tid % 3) - 1, nty = ty + (tid / 3) - 1;
+        if (ntx >= 0 && ntx < D.tiles_x && nty >= 0 && nty < D.tiles_y)
+            atomicOr(&P.tile_act[D.tile0 + nty * D.tiles_x + ntx], 2u);
+    }
+    if (tid == 0) {
+        if (tile_active)
+            atomicOr(&P.tile_act[tg], 1u);
+        else
+            atomicAnd(&P.tile_act[tg], ~1u);
+    }
+    (void)S;
+}
+
+// Whether this tile or one of its neighbours changed a label in the previous pass.
+__device__ __forceinline__ bool frontier_needs(const StepParams &P, const InstDesc &D, int tx, int ty,
+                                               int prev) {
+    const uint8_t *chg = P.tile_chg + (size_t)prev * P.ntiles;
+    bool need = false;
+#pragma unroll
+    for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
+        for (int dx = -1; dx <= 1; ++dx) {
+            const int ntx = tx + dx, nty = ty + dy;
+            if (ntx >= 0 && ntx < D.tiles_x && nty >= 0 && nty < D.tiles_y)
+                need |= chg[D.tile0 + nty * D.tiles_x + ntx] != 0;
+        }
+    return need;
+}
+
+// ---------------------------------------------------------------------------
+// kRelabel: one pass of the exact global relabel (distance to t).
+// ---------------------------------------------------------------------------
+template <int K, int TW, int TH>
+__device__ void relabel_tile(const StepParams &P, const InstDesc &D, InstState *S, int tg, int tl,
+                             int sub, int32_t *lds, int *s_red) {
+    using G = Geo<TW, TH>;
+    constexpr int PPT = G::PPT, RPI = G::RPI, HW = G::HW;
+    const int tid = threadIdx.x, lx = tid % TW, ly0 = tid / TW;
+    const int tx = tl % D.tiles_x, ty = tl / D.tiles_x;
+    const int x0 = tx * TW, y0 = ty * TH;
+    const int W = D.W, H = D.H, n = D.n;
+    const bool first = sub == 0;
+    const int cur = sub & 1, prev = cur ^ 1;
+    if (!first && !frontier_needs(P, D, tx, ty, prev)) {
+        if (tid == 0) P.tile_chg[(size_t)cur * P.ntiles + tg] = 0;
+        return;
+    }
+    int32_t *sh_d = lds;
+    int d[PPT], d0[PPT];
+    uint32_t rm[PPT];
+#pragma unroll
+    for (int j = 0; j < PPT; ++j) {
+        const int ly = ly0 + j * RPI;
+        const int gx = x0 + lx, gy = y0 + ly;
+        rm[j] = 0;
+        d[j] = kHInf;
+        if (gx < W && gy < H) {
+            const int p = gy * W + gx;
+            rm[j] = D.rmask[p];
+            if (first) {
+                // fold flow that neighbour tiles pushed into this pixel
+                int ein = 0;
+                uint32_t radd = 0;
+#pragma unroll
+                for (int k = 0; k < K; ++k) {
+                    const int nx = lx + DXk(k), ny = ly + DYk(k);
+                    if (nx >= 0 && nx < TW && ny >= 0 && ny < TH) continue;
+                    const int qx = gx + DXk(k), qy = gy + DYk(k);
+                    if (qx < 0 || qx >= W || qy < 0 || qy >= H) continue;
+                    const int v = D.inbox[(size_t)k * n + p];
+                    if (v) {
+                        D.inbox[(size_t)k * n + p] = 0;
+                        D.r[(size_t)k * n + p] += v;
+                        ein += v;
+                        radd |= 1u << k;
+                    }
+                }
+                if (ein) {
+                    D.e[p] += ein;
+                    rm[j] |= radd | kEBit;
+                    D.rmask[p] = (uint16_t)rm[j];
+                }
+                d[j] = (rm[j] & kRtBit) ? 1 : kHInf;
+            } else {
+                d[j] = D.h[p];
+            }
+        }
+        d0[j] = d[j];
+        sh_d[(ly + 1) * HW + lx + 1] = d[j];
+    }
+    for (int i = tid; i < G::RING; i += kThreads) {
+        int hx, hy;
+        G::ring(i, hx, hy);
+        const int gx = x0 + hx - 1, gy = y0 + hy - 1;
+        int v = kHInf;
+        if (gx >= 0 && gx < W && gy >= 0 && gy < H) {
+            const int q = gy * W + gx;
+            v = first ? ((D.rmask[q] & kRtBit) ? 1 : kHInf) : D.h[q];
+        }
+        sh_d[hy * HW + hx] = v;
+    }
+    __syncthreads();
+    for (int it = 0; it < P.local_bfs_iters; ++it) {
+        int ch = 0;
+#pragma unroll
+        for (int j = 0; j < PPT; ++j) {
+            if (d[j] <= 1) continue;
+            const int ly = ly0 + j * RPI;
+            int nd = d[j];
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                if (rm[j] & (1u << k)) {
+                    const int v = sh_d[(ly + 1 + DYk(k)) * HW + lx + 1 + DXk(k)];
+                    if (v < kHInf && v + 1 < nd) nd = v + 1;
+                }
+            }
+            if (nd < d[j]) {
+                d[j] = nd;
+                sh_d[(ly + 1) * HW + lx + 1] = nd;
+                ch = 1;
+            }
+        }
+        if (!__syncthreads_or(ch)) break;
+    }
+    int changed = first ? 1 : 0, cnt = 0;
+#pragma unroll
+    for (int j = 0; j < PPT; ++j) {
+        const int ly = ly0 + j * RPI;
+        const int gx = x0 + lx, gy = y0 + ly;
+        if (gx >= W || gy >= H) continue;
+        if (first || d[j] != d0[j]) {
+            D.h[gy * W + gx] = d[j];
+            changed = 1;
+        }
+        cnt += (rm[j] & kEBit) && d[j] < kHInf;
+    }
+    const int tchg = __syncthreads_or(changed);
+    const int tcnt = block_sum_int(cnt, s_red);
+    if (tid == 0) {
+        P.tile_chg[(size_t)cur * P.ntiles + tg] = (uint8_t)(tchg ? 1 : 0);
+        const int delta = first ? tcnt : tcnt - P.tile_cnt[tg];
+        P.tile_cnt[tg] = tcnt;
+        if (delta) atomicAdd(&S->active, delta);
+        if (tchg) atomicOr(&S->changed, 1);
+        P.tile_act[tg] = tcnt > 0 ? 1u : 0u;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// kCut: one pass of the forward residual reachability from excess pixels.
+// The first pass also sums the excess (for F) and raises the sink residuals
+// to the next lambda (warm start).
+// ---------------------------------------------------------------------------
+template <int K, int TW, int TH>
+__device__ void cut_tile(const StepParams &P, const InstDesc &D, InstState *S, int tg, int tl, int sub,
+                         int kk, int32_t *lds, int *s_red, unsigned long long *s_sum) {
+    using G = Geo<TW, TH>;
+    constexpr int PPT = G::PPT, RPI = G::RPI, HW = G::HW;
+    const int tid = threadIdx.x, lx = tid % TW, ly0 = tid / TW;
+    const int tx = tl % D.tiles_x, ty = tl / D.tiles_x;
+    const int x0 = tx * TW, y0 = ty * TH;
+    const int W = D.W, H = D.H, n = D.n;
+    const bool first = sub == 0;
+    const int cur = sub & 1, prev = cur ^ 1;
+    if (!first && !frontier_needs(P, D, tx, ty, prev)) {
+        if (tid == 0) P.tile_chg[(size_t)cur * P.ntiles + tg] = 0;
+        return;
+    }
+    uint8_t *mask = D.masks + (size_t)kk * n;
+    int32_t *sh_m = lds;
+    int32_t *sh_rm = lds + G::HALO;
+    const bool raise = first && kk + 1 < D.L;
+    const int dlam = raise ? D.lambdas[kk + 1] - D.lambdas[kk] : 0;
+    int m[PPT], m0[PPT];
+    long long se = 0;
+#pragma unroll
+    for (int j = 0; j < PPT; ++j) {
+        const int ly = ly0 + j * RPI;
+        const int gx = x0 + lx, gy = y0 + ly;
+        int rmv = 0;
+        m[j] = 0;
+        if (gx < W && gy < H) {
+            const int p = gy * W + gx;
+            rmv = D.rmask[p];
+            if (first) {
+                m[j] = (rmv & kEBit) ? 1 : 0;
+                if (m[j]) se += D.e[p];
+                if (dlam > 0) {
+                    const int sd = D.seed ? (int)D.seed[p] : 0;
+                    const int sl = sd == 0 ? (D.slope ? D.slope[p] : 1) : 0;
+                    if (sl > 0) {
+                        const int nrt = D.rt[p] + sl * dlam;
+                        D.rt[p] = nrt;
+                        if (nrt > 0 && !(rmv & kRtBit)) D.rmask[p] = (uint16_t)(rmv | kRtBit);
+                    }
+                }
+            } else {
+                m[j] = mask[p];
+            }
+        }
+        m0[j] = m[j];
+        sh_m[(ly + 1) * HW + lx + 1] = m[j];
+        sh_rm[(ly + 1) * HW + lx + 1] = rmv;
+    }
+    for (int i = tid; i < G::RING; i += kThreads) {
+        int hx, hy;
+        G::ring(i, hx, hy);
+        const int gx = x0 + hx - 1, gy = y0 + hy - 1;
+        int mv = 0, rmv = 0;
+        if (gx >= 0 && gx < W && gy >= 0 && gy < H) {
+            const int q = gy * W + gx;
+            rmv = D.rmask[q];
+            mv = first ? ((rmv & kEBit) ? 1 : 0) : mask[q];
+        }
+        sh_m[hy * HW + hx] = mv;
+        sh_rm[hy * HW + hx] = rmv;
+    }
+    __syncthreads();
+    for (int it = 0; it < P.local_bfs_iters; ++it) {
+        int ch = 0;
+#pragma unroll
+        for (int j = 0; j < PPT; ++j) {
+            if (m[j]) continue;
+            const int ly = ly0 + j * RPI;
+            const int gx = x0 + lx, gy = y0 + ly;
+            if (gx >= W || gy >= H) continue;
+            bool reach = false;
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                const int a = (ly + 1 + DYk(k)) * HW + lx + 1 + DXk(k);
+                // q = p + d_k reaches p if q is reached and r(q -> p) > 0
+                reach |= sh_m[a] != 0 && ((sh_rm[a] >> (k ^ 1)) & 1);
+            }
+            if (reach) {
+                m[j] = 1;
+                sh_m[(ly + 1) * HW + lx + 1] = 1;
+                ch = 1;
+            }
+        }
+        if (!__syncthreads_or(ch)) break;
+    }
+    int changed = first ? 1 : 0;
+#pragma unroll
+    for (int j = 0; j < PPT; ++j) {
+        const int ly = ly0 + j * RPI;
+        const int gx = x0 + lx, gy = y0 + ly;
+        if (gx >= W || gy >= H) continue;
+        if (first || m[j] != m0[j]) {
+            mask[gy * W + gx] = (uint8_t)m[j];
+            changed = 1;
+        }
+    }
+    const int tchg = __syncthreads_or(changed);
+    long long tse = 0;
+    if (first) tse = block_sum_i64(se, s_sum);
+    if (tid == 0) {
+        P.tile_chg[(size_t)cur * P.ntiles + tg] = (uint8_t)(tchg ? 1 : 0);
+        if (tchg) atomicOr(&S->changed, 1);
+        if (tse) atomicAdd((unsigned long long *)&S->sum_e, (unsigned long long)tse);
+    }
+    (void)s_red;
+}
+
+// ---------------------------------------------------------------------------
+// Phase machine, run by the last workgroup of every superstep.
+// ---------------------------------------------------------------------------
+__device__ void control(const StepParams &P) {
+    for (int i = threadIdx.x; i < P.nslots; i += kThreads) {
+        InstState *S = &P.st[i];
+        int ph = ld_agent(&S->phase);
+        if (ph == kIdle || ph == kDone) continue;
+        const InstDesc *D = &P.desc[i];
+        S->steps += 1;
+        bool done = false;
+        int status = PMF_OK;
+        const int changed = ld_agent(&S->changed);
+        switch (ph) {
+            case kInit: {
+                const int err = ld_agent(&S->err);
+                if (err) {
+                    done = true;
+                    status = (err & 1) ? PMF_EINVAL : PMF_EOVERFLOW;
+                } else {
+                    ph = kRelabel;
+                    S->sub = 0;
+                    S->active = 0;
+                }
+                break;
+            }
+            case kRelabel:
+                S->passes += 1;
+                if (S->sub > 0 && !changed) {
+                    S->relabels += 1;
+                    ph = ld_agent(&S->active) == 0 ? kCut : kSweep;
+                    S->sub = 0;
+                } else {
+                    S->sub += 1;
+                }
+                break;
+            case kSweep:
+                S->sweeps += 1;
+                if (++S->sub >= P.sweeps_per_relabel) {
+                    ph = kRelabel;
+                    S->sub = 0;
+                    S->active = 0;
+                }
+                break;
+            case kCut:
+                S->passes += 1;
+                if (S->sub > 0 && !changed) {
+                    const int k = S->k;
+                    D->flows[k] = ld_agent(&S->sum_cs) - ld_agent(&S->sum_e);
+                    S->sum_e = 0;
+                    S->k = k + 1;
+                    if (k + 1 >= D->L) {
+                        done = true;
+                    } else {
+                        ph = kRelabel;
+                        S->sub = 0;
+                        S->active = 0;
+                    }
+                } else {
+                    S->sub += 1;
+                }
+                break;
+        }
+        S->changed = 0;
+        if (!done && S->steps >= P.max_steps) {
+            done = true;
+            status = PMF_ETIMEOUT;
+        }
+        if (done) {
+            if (status != PMF_OK) {
+                const int from = status == PMF_ETIMEOUT ? S->k : 0;
+                for (int k = from; k < D->L; ++k) D->flows[k] = -1;
+            }
+            if (D->status) *D->status = status;
+            ph = kDone;
+            atomicAdd(P.ndone, 1);
+        }
+        S->phase = ph;
+    }
+}
+
+template <int TW, int TH>
+__global__ __launch_bounds__(kThreads) void k_superstep(StepParams P) {
+    __shared__ int32_t lds[((TW + 2) * (TH + 2) + 3) / 4 * 4 + 8 * TW * TH];
+    __shared__ int s_red[4];
+    __shared__ unsigned long long s_sum;
+    __shared__ int s_last;
+    // XCD-aware mapping: consecutive tiles (neighbours in one image) land on
+    // the same XCD, whose L2 then holds their shared halos.
+    const int b = blockIdx.x;
+    const int t = (b & 7) * P.per_xcd + (b >> 3);
+    if (t < P.ntiles) {
+        const int slot = P.tile_slot[t];
+        const int tl = P.tile_local[t];
+        InstState *S = &P.st[slot];
+        const int phase = S->phase;
+        if (phase != kIdle && phase != kDone) {
+            const InstDesc D = P.desc[slot];
+            if (tl < D.ntiles) {
+                const int sub = S->sub, kk = S->k;
+                if (D.K == 4) {
+                    switch (phase) {
+                        case kInit: init_tile<4, TW, TH>(P, D, S, t, tl, s_red, &s_sum); break;
+                        case kRelabel: relabel_tile<4, TW, TH>(P, D, S, t, tl, sub, lds, s_red); break;
+                        case kSweep: sweep_tile<4, TW, TH>(P, D, S, t, tl, lds, s_red); break;
+                        case kCut: cut_tile<4, TW, TH>(P, D, S, t, tl, sub, kk, lds, s_red, &s_sum); break;
+                    }
+                } else {
+                    switch (phase) {
+                        case kInit: init_tile<8, TW, TH>(P, D, S, t, tl, s_red, &s_sum); break;
+                        case kRelabel: relabel_tile<8, TW, TH>(P, D, S, t, tl, sub, lds, s_red); break;
+                        case kSweep: sweep_tile<8, TW, TH>(P, D, S, t, tl, lds, s_red); break;
+                        case kCut: cut_tile<8, TW, TH>(P, D, S, t, tl, sub, kk, lds, s_red, &s_sum); break;
+                    }
+                }
+            }
+        }
+    }
+    // last-workgroup pattern: the final arrival runs the phase machine
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        const unsigned prev = atomicAdd(P.arrive, 1u);
+        s_last = prev == gridDim.x - 1;
+    }
+    __syncthreads();
+    if (s_last) {
+        __threadfence();
+        control(P);
+        __threadfence();
+        __syncthreads();
+        if (threadIdx.x == 0) atomicExch(P.arrive, 0u);
+    }
+}
+
+int launch_superstep(const StepParams &p, int tile_w, void *stream) {
+    const dim3 grid(8 * p.per_xcd), block(kThreads);
+    hipStream_t s = (hipStream_t)stream;
+    if (tile_w == 64)
+        hipLaunchKernelGGL((k_superstep<64, 16>), grid, block, 0, s, p);
+    else
+        hipLaunchKernelGGL((k_superstep<32, 32>), grid, block, 0, s, p);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int max_lds_bytes(int tile_w) {
+    (void)tile_w;
+    return (int)sizeof(int32_t) * ((66 * 18 + 3) / 4 * 4 + 8 * 1024);
+}
+
+}  // namespace pmf

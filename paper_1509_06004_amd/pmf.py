@@ -1,0 +1,263 @@
+"""Python binding of libpmf (C ABI in ``include/pmf.h``): argument marshalling only.
+
+Every step of the solve runs in the HIP library; PyTorch provides device
+memory and the stream.  The library must be built (``python -m
+paper_1509_06004_amd.build``); importing this module fails loudly otherwise.
+
+Functions with the C names (``pmf_create``, ``pmf_solve_batch``,
+``pmf_extract_cut``, ``pmf_destroy``, ...) wrap the ABI one to one;
+:class:`Solver` is a small convenience layer over them.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Dict, List, Optional, Sequence, Tuple
+
+import numpy as np
+import torch  # loads the HIP runtime that libpmf then shares
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpmf.so")
+
+PMF_OK, PMF_EINVAL, PMF_EOVERFLOW, PMF_ENOMEM, PMF_EDEVICE = 0, 1, 2, 3, 4
+PMF_ETIMEOUT, PMF_ENOTSOLVED, PMF_ERANGE, PMF_EBUSY = 5, 6, 7, 8
+INF = 1 << 30
+
+
+class PmfError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        super().__init__("%s: %s (code %d)" % (where, pmf_strerror(code), code))
+        self.code = code
+
+
+class Options(ctypes.Structure):
+    _fields_ = [
+        ("tile_w", ctypes.c_int32),
+        ("tile_h", ctypes.c_int32),
+        ("inner_iters", ctypes.c_int32),
+        ("sweeps_per_relabel", ctypes.c_int32),
+        ("local_bfs_iters", ctypes.c_int32),
+        ("steps_per_sync", ctypes.c_int32),
+        ("max_supersteps", ctypes.c_int64),
+        ("use_graph", ctypes.c_int32),
+        ("order", ctypes.c_int32),
+        ("mem_budget", ctypes.c_int64),
+        ("max_slots", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 7),
+    ]
+
+
+class InstanceC(ctypes.Structure):
+    _fields_ = [
+        ("W", ctypes.c_int32),
+        ("H", ctypes.c_int32),
+        ("K", ctypes.c_int32),
+        ("L", ctypes.c_int32),
+        ("nlink", ctypes.c_void_p),
+        ("cap_src", ctypes.c_void_p),
+        ("cap_snk0", ctypes.c_void_p),
+        ("snk_slope", ctypes.c_void_p),
+        ("seed", ctypes.c_void_p),
+        ("lambdas", ctypes.c_void_p),
+    ]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [
+        ("supersteps", ctypes.c_int64),
+        ("sweep_visits", ctypes.c_int64),
+        ("global_relabels", ctypes.c_int64),
+        ("bfs_passes", ctypes.c_int64),
+        ("host_syncs", ctypes.c_int64),
+        ("device_bytes", ctypes.c_int64),
+    ]
+
+
+_lib = None
+
+
+def load_library() -> ctypes.CDLL:
+    """Load libpmf.so; raise if it has not been built (there is no fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError("libpmf.so is not built: run `python -m paper_1509_06004_amd.build`")
+    lib = ctypes.CDLL(LIB_PATH)
+    P = ctypes.c_void_p
+    sig = {
+        "pmf_default_options": (None, [ctypes.POINTER(Options)]),
+        "pmf_create": (ctypes.c_int, [ctypes.POINTER(Options), P, P, ctypes.c_size_t,
+                                      ctypes.POINTER(P)]),
+        "pmf_solve_batch": (ctypes.c_int, [P, ctypes.POINTER(InstanceC), ctypes.c_int32, P, P]),
+        "pmf_extract_cut": (ctypes.c_int, [P, ctypes.c_int32, ctypes.c_int32, P]),
+        "pmf_destroy": (ctypes.c_int, [P]),
+        "pmf_strerror": (ctypes.c_char_p, [ctypes.c_int]),
+        "pmf_query_bytes": (ctypes.c_int, [ctypes.POINTER(InstanceC), ctypes.c_int32,
+                                           ctypes.POINTER(Options), ctypes.POINTER(ctypes.c_size_t)]),
+        "pmf_check_instances": (ctypes.c_int, [ctypes.POINTER(InstanceC), ctypes.c_int32,
+                                               ctypes.POINTER(ctypes.c_int32)]),
+        "pmf_get_stats": (ctypes.c_int, [P, ctypes.POINTER(Stats)]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+# ---------------------------------------------------------------------------
+# One-to-one wrappers of the C ABI.
+# ---------------------------------------------------------------------------
+
+def pmf_strerror(code: int) -> str:
+    return load_library().pmf_strerror(int(code)).decode()
+
+
+def pmf_default_options() -> Options:
+    o = Options()
+    load_library().pmf_default_options(ctypes.byref(o))
+    return o
+
+
+def pmf_create(options: Optional[Options] = None, stream: int = 0, workspace: int = 0,
+               ws_bytes: int = 0) -> ctypes.c_void_p:
+    h = ctypes.c_void_p()
+    rc = load_library().pmf_create(ctypes.byref(options) if options is not None else None,
+                                   ctypes.c_void_p(stream), ctypes.c_void_p(workspace),
+                                   ctypes.c_size_t(ws_bytes), ctypes.byref(h))
+    if rc != PMF_OK:
+        raise PmfError(rc, "pmf_create")
+    return h
+
+
+def pmf_solve_batch(handle, instances: Sequence[InstanceC], flows_ptr: int, status_ptr: int) -> int:
+    arr = (InstanceC * len(instances))(*instances)
+    return load_library().pmf_solve_batch(handle, arr, len(instances), ctypes.c_void_p(flows_ptr),
+                                          ctypes.c_void_p(status_ptr))
+
+
+def pmf_extract_cut(handle, inst: int, lambda_idx: int, mask_ptr: int) -> int:
+    return load_library().pmf_extract_cut(handle, int(inst), int(lambda_idx), ctypes.c_void_p(mask_ptr))
+
+
+def pmf_destroy(handle) -> int:
+    return load_library().pmf_destroy(handle)
+
+
+def pmf_query_bytes(instances: Sequence[InstanceC], options: Optional[Options] = None) -> int:
+    arr = (InstanceC * len(instances))(*instances)
+    out = ctypes.c_size_t(0)
+    rc = load_library().pmf_query_bytes(arr, len(instances),
+                                        ctypes.byref(options) if options is not None else None,
+                                        ctypes.byref(out))
+    if rc != PMF_OK:
+        raise PmfError(rc, "pmf_query_bytes")
+    return int(out.value)
+
+
+def pmf_check_instances(instances: Sequence[InstanceC]) -> Tuple[int, int]:
+    arr = (InstanceC * len(instances))(*instances)
+    bad = ctypes.c_int32(-1)
+    rc = load_library().pmf_check_instances(arr, len(instances), ctypes.byref(bad))
+    return rc, int(bad.value)
+
+
+def pmf_get_stats(handle) -> Dict[str, int]:
+    s = Stats()
+    rc = load_library().pmf_get_stats(handle, ctypes.byref(s))
+    if rc != PMF_OK:
+        raise PmfError(rc, "pmf_get_stats")
+    return {f: int(getattr(s, f)) for f, _ in Stats._fields_}
+
+
+# ---------------------------------------------------------------------------
+# Device-resident instances (torch tensors) and a convenience solver.
+# ---------------------------------------------------------------------------
+
+class DeviceInstance:
+    """Device copies of one instance's arrays; keeps the tensors alive."""
+
+    def __init__(self, W, H, K, nlink, cap_src, cap_snk0, snk_slope, seed, lambdas):
+        self.W, self.H, self.K = int(W), int(H), int(K)
+        self.nlink, self.cap_src, self.cap_snk0 = nlink, cap_src, cap_snk0
+        self.snk_slope, self.seed, self.lambdas = snk_slope, seed, lambdas
+        self.L = int(lambdas.numel())
+
+    def c_struct(self) -> InstanceC:
+        def ptr(t):
+            return 0 if t is None else int(t.data_ptr())
+        return InstanceC(self.W, self.H, self.K, self.L, ptr(self.nlink), ptr(self.cap_src),
+                         ptr(self.cap_snk0), ptr(self.snk_slope), ptr(self.seed), ptr(self.lambdas))
+
+
+def to_device(insts, device="cuda", share: Optional[Dict[int, torch.Tensor]] = None) -> List[DeviceInstance]:
+    """Upload host instances (objects with the fields of ``workload.Instance``).
+    Instances whose ``nlink`` is the same numpy array share one device copy."""
+    share = {} if share is None else share
+    out = []
+    for inst in insts:
+        key = id(inst.nlink)
+        if key not in share:
+            share[key] = torch.from_numpy(np.ascontiguousarray(inst.nlink, dtype=np.int32)).to(device)
+        t = lambda a, dt: torch.from_numpy(np.ascontiguousarray(a, dtype=dt)).to(device)
+        out.append(DeviceInstance(inst.W, inst.H, inst.K, share[key], t(inst.cap_src, np.int32),
+                                  t(inst.cap_snk0, np.int32), t(inst.snk_slope, np.int32),
+                                  t(inst.seed, np.uint8), t(inst.lambdas, np.int32)))
+    return out
+
+
+class Solver:
+    """Owns a pmf handle bound to a torch stream."""
+
+    def __init__(self, options: Optional[Options] = None, stream: Optional[torch.cuda.Stream] = None,
+                 workspace: Optional[torch.Tensor] = None, **overrides):
+        if options is None:
+            options = pmf_default_options()
+        for k, v in overrides.items():
+            setattr(options, k, v)
+        self.options = options
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        self.workspace = workspace
+        ws_ptr = int(workspace.data_ptr()) if workspace is not None else 0
+        ws_bytes = workspace.numel() * workspace.element_size() if workspace is not None else 0
+        self.handle = pmf_create(options, int(self.stream.cuda_stream), ws_ptr, ws_bytes)
+        self.last = []
+
+    def solve(self, dev_insts: Sequence[DeviceInstance]) -> Tuple[torch.Tensor, torch.Tensor]:
+        """Returns (flows int64 [sum L], status int32 [n]) on the device."""
+        total = sum(d.L for d in dev_insts)
+        dev = dev_insts[0].lambdas.device if dev_insts else torch.device("cuda")
+        flows = torch.empty(total, dtype=torch.int64, device=dev)
+        status = torch.empty(len(dev_insts), dtype=torch.int32, device=dev)
+        rc = pmf_solve_batch(self.handle, [d.c_struct() for d in dev_insts], int(flows.data_ptr()),
+                             int(status.data_ptr()))
+        if rc != PMF_OK:
+            raise PmfError(rc, "pmf_solve_batch")
+        self.last = list(dev_insts)
+        return flows, status
+
+    def extract_cut(self, inst: int, lambda_idx: int) -> torch.Tensor:
+        d = self.last[inst]
+        out = torch.empty((d.H, d.W), dtype=torch.uint8, device=d.lambdas.device)
+        rc = pmf_extract_cut(self.handle, inst, lambda_idx, int(out.data_ptr()))
+        if rc != PMF_OK:
+            raise PmfError(rc, "pmf_extract_cut")
+        return out
+
+    def stats(self) -> Dict[str, int]:
+        return pmf_get_stats(self.handle)
+
+    def close(self):
+        if self.handle is not None:
+            pmf_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
