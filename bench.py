@@ -1,0 +1,266 @@
+#!/usr/bin/env python3
+"""Throughput benchmark: exact max-flow solves/s on 500x375 4-connected grids.
+
+One *step* solves one batch of the headline workload on the GPU through the C
+ABI: 25 seeds (7x7 squares on a 5x5 lattice) of one synthetic 500x375 image,
+each with the 20-point lambda schedule 1..2000, i.e. 500 (seed, lambda)
+solves, packed into one call (warm-started chains).  Inputs are resident in
+HBM before timing starts.  The same run also times
+
+* the plain form: the same 25 chains solved one instance per call,
+* the 8-connected variant of the same workload,
+* the CPU oracle on a bounded sample of the same solves (host cores),
+
+verifies a sample of the GPU results against the oracle (bit-exact flows and
+masks) and all of them against the max-flow/min-cut certificate and nesting,
+and prints one JSON line.
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+from concurrent.futures import ThreadPoolExecutor
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "exact max-flow solves/s (500×375 4-conn) batched vs plain; p50/p99 latency"
+HBM_PEAK_GBS = 8000.0
+
+
+def bytes_per_px(K: int) -> dict:
+    """Algorithmic bytes per pixel visit of each phase (the solver's own state):
+    sweep: read + write r_k, e, rt, h (int32) + write the residual bit word;
+    relabel pass: read bit word + read/write h; cut pass: bit word + mask r/w;
+    init: read n-links and terminal inputs, write the whole state."""
+    return {"sweep": 2 * (K + 3) * 4 + 2, "relabel": 2 + 4 + 4, "cut": 2 + 1 + 1,
+            "init": K * 4 + 13 + K * 4 + K * 4 + 12 + 2}
+
+
+def alg_bytes(st: dict, K: int) -> float:
+    b = bytes_per_px(K)
+    return (st["px_sweep"] * b["sweep"] + st["px_relabel"] * b["relabel"] + st["px_cut"] * b["cut"]
+            + st["px_init"] * b["init"])
+
+
+def add_stats(acc: dict, st: dict):
+    for k, v in st.items():
+        acc[k] = acc.get(k, 0) + v
+
+
+def gpu_masks(solver, insts):
+    out = []
+    for i, inst in enumerate(insts):
+        out.append(np.stack([solver.extract_cut(i, k).cpu().numpy().astype(bool) for k in range(inst.L)]))
+    return out
+
+
+def verify(insts, flows, masks, sample_pairs, oracle_results):
+    """Bit-exact against the oracle on the sample; certificate + nesting on all."""
+    from oracle import oracle as O
+    off = np.cumsum([0] + [i.L for i in insts])
+    bad = 0
+    for (i, k), (f, m) in zip(sample_pairs, oracle_results):
+        bad += int(flows[off[i] + k]) != f or not (masks[i][k] == m).all()
+    cert = 0
+    for i, inst in enumerate(insts):
+        for k in range(inst.L):
+            cert += O.cut_cost_c(inst, int(inst.lambdas[k]), masks[i][k]) != int(flows[off[i] + k])
+            if k:
+                cert += bool((masks[i][k] & ~masks[i][k - 1]).any())
+    return bad, cert
+
+
+def cpu_baseline(insts, n_sample: int, threads: int):
+    """The oracle (cold, one single-threaded solve per task) on a thread pool."""
+    from oracle import oracle as O
+    O.build()
+    pairs = []
+    L = insts[0].L
+    total = len(insts) * L
+    for j in range(n_sample):
+        idx = (j * total) // n_sample
+        pairs.append((idx // L, idx % L))
+    tasks = [(insts[i], int(insts[i].lambdas[k])) for i, k in pairs]
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(max_workers=threads) as ex:
+        res = list(ex.map(lambda t: O.fifo_pr(t[0], t[1]), tasks))
+    wall = time.perf_counter() - t0
+    return pairs, res, wall
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--tile-w", type=int, default=0)
+    ap.add_argument("--inner-iters", type=int, default=0)
+    ap.add_argument("--sweeps-per-relabel", type=int, default=0)
+    ap.add_argument("--local-bfs-iters", type=int, default=0)
+    ap.add_argument("--steps-per-sync", type=int, default=0)
+    ap.add_argument("--cpu-sample", type=int, default=48)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-8conn", action="store_true")
+    ap.add_argument("--no-verify", action="store_true")
+    ap.add_argument("--no-roofline", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: instances are independent, so more GPUs would each "
+              "run their own copy of this workload (see the sharding note in DESIGN.md); "
+              "--gpus %d is not supported" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1509_06004_amd import pmf, workload
+
+    torch.cuda.set_device(0)
+    overrides = {}
+    if args.tile_w:
+        overrides.update(tile_w=args.tile_w, tile_h=1024 // args.tile_w)
+    for a, f in (("inner_iters", args.inner_iters), ("sweeps_per_relabel", args.sweeps_per_relabel),
+                 ("local_bfs_iters", args.local_bfs_iters), ("steps_per_sync", args.steps_per_sync)):
+        if f:
+            overrides[a] = f
+
+    def log(*a):
+        print("[bench]", *a, file=sys.stderr, flush=True)
+
+    insts = workload.config2(K=4)
+    n_solves = sum(i.L for i in insts)
+    dev = pmf.to_device(insts)
+    solver = pmf.Solver(**overrides)
+    torch.cuda.synchronize()
+    log("workload: %d instances, %d solves; warmup %d" % (len(insts), n_solves, args.warmup))
+    for _ in range(args.warmup):
+        solver.solve(dev)
+    torch.cuda.synchronize()
+
+    times, acc = [], {}
+    flows = status = None
+    torch.cuda.synchronize()
+    t_all = time.perf_counter()
+    for s in range(args.steps):
+        t0 = time.perf_counter()
+        flows, status = solver.solve(dev)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+        add_stats(acc, solver.stats())
+        log("step %d: %.1f ms" % (s, times[-1] * 1e3))
+    torch.cuda.synchronize()
+    total = time.perf_counter() - t_all
+    value = n_solves * args.steps / total
+    flows_np = flows.cpu().numpy()
+    status_np = status.cpu().numpy()
+    assert (status_np == 0).all(), status_np
+
+    # roofline of the dominant kernel (the push/relabel sweep): one extra solve
+    # in the library's timing mode, which brackets every kernel with HIP events
+    # on the solver's stream
+    tsolver = pmf.Solver(timing=1, **overrides)
+    tsolver.solve(dev)
+    torch.cuda.synchronize()
+    ts = tsolver.stats()
+    tsolver.close()
+    bpx = bytes_per_px(4)
+    sweep_s = ts["sweep_ns"] * 1e-9
+    n_sweep = max(ts["sweep_launches"], 1)
+    per_launch_bytes = ts["px_sweep"] * bpx["sweep"] / n_sweep
+    avg_launch_s = sweep_s / n_sweep
+    achieved = per_launch_bytes / avg_launch_s / 1e9
+    bfs_bytes = ts["px_relabel"] * bpx["relabel"] + ts["px_cut"] * bpx["cut"] + ts["px_init"] * bpx["init"]
+    tw = solver.options.tile_w
+    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "kernel": "k_sweep<4, %d, %d>" % (tw, 1024 // tw), "avg_launch_us": round(avg_launch_s * 1e6, 2),
+            "alg_bytes_per_launch": int(per_launch_bytes), "launches": int(n_sweep),
+            "bytes_per_px": bpx,
+            "other_kernels": {"k_bfs_GBs": round(bfs_bytes / max(ts["bfs_ns"], 1), 1),
+                              "k_bfs_share": round(ts["bfs_ns"] / max(ts["sweep_ns"] + ts["bfs_ns"] + ts["control_ns"], 1), 3),
+                              "k_sweep_share": round(ts["sweep_ns"] / max(ts["sweep_ns"] + ts["bfs_ns"] + ts["control_ns"], 1), 3)}}
+
+    out = {"metric": METRIC, "value": round(value, 2), "unit": "solves/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(total / args.steps * 1e3, 2),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int32",
+           "data": "synthetic",
+           "config": {"workload": "500x375 4-connected grid, 24-region synthetic image, 25 seeds "
+                                  "(7x7, 5x5 lattice) x 20 geometric lambdas 1..2000 = 500 solves per "
+                                  "step, warm-started chains packed in one call",
+                      "options": {k: getattr(solver.options, k) for k in
+                                  ("tile_w", "tile_h", "inner_iters", "sweeps_per_relabel",
+                                   "local_bfs_iters", "steps_per_sync", "use_graph", "order")}},
+           "latency_ms": {"p50": round(float(np.percentile(times, 50)) * 1e3, 2),
+                          "p99": round(float(np.percentile(times, 99)) * 1e3, 2),
+                          "what": "per batched step of 500 solves"},
+           "device_time_frac": round(acc["device_ns"] * 1e-9 / sum(times), 3),
+           "roofline": roof}
+
+    # plain: one instance (one seed's 20-lambda chain) per call, same GPU, same run
+    if not args.no_plain:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        plain_lat = []
+        for d in dev:
+            t1 = time.perf_counter()
+            solver.solve([d])
+            torch.cuda.synchronize()
+            plain_lat.append(time.perf_counter() - t1)
+        pt = time.perf_counter() - t0
+        plain = n_solves / pt
+        out["plain"] = {"value": round(plain, 2), "unit": "solves/s",
+                        "chain_latency_ms": {"p50": round(float(np.percentile(plain_lat, 50)) * 1e3, 2),
+                                             "p99": round(float(np.percentile(plain_lat, 99)) * 1e3, 2)}}
+        out["batched_over_plain"] = round(value / plain, 2)
+        log("plain %.1f solves/s" % plain)
+        flows, status = solver.solve(dev)  # restore the batched results for verification
+        torch.cuda.synchronize()
+        flows_np = flows.cpu().numpy()
+
+    masks = gpu_masks(solver, insts) if not args.no_verify else None
+
+    if not args.no_8conn:
+        insts8 = workload.config2(K=8)
+        dev8 = pmf.to_device(insts8)
+        solver.solve(dev8)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        solver.solve(dev8)
+        torch.cuda.synchronize()
+        t8 = time.perf_counter() - t0
+        st8 = solver.stats()
+        out["config_8conn"] = {"value": round(n_solves / t8, 2), "unit": "solves/s",
+                               "workload": "same, 8-connected (diagonals / sqrt 2)",
+                               "achieved_GBs": round(alg_bytes(st8, 8) / (st8["device_ns"] * 1e-9) / 1e9, 1)}
+        del dev8
+        log("8-conn %.1f solves/s" % (n_solves / t8))
+
+    if not args.no_cpu:
+        threads = min(os.cpu_count() or 1, 16)
+        pairs, res, wall = cpu_baseline(insts, args.cpu_sample, threads)
+        out["cpu_baseline"] = {"value": round(len(pairs) / wall, 2), "unit": "solves/s", "cores": threads,
+                               "kind": "oracle",
+                               "sample": "%d of the %d (seed, lambda) solves, evenly spaced, each solved "
+                                         "from scratch by FIFO push-relabel (int64), one per thread"
+                                         % (len(pairs), n_solves)}
+        log("cpu %.2f solves/s on %d threads" % (len(pairs) / wall, threads))
+        if masks is not None:
+            bad, cert = verify(insts, flows_np, masks, pairs, res)
+            out["verified"] = {"oracle_sample_mismatches": bad, "certificate_or_nesting_failures": cert,
+                               "sampled": len(pairs), "checked_by_certificate": n_solves}
+            if bad or cert:
+                print(json.dumps(out))
+                raise SystemExit("verification failed")
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

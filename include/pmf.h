@@ -66,7 +66,8 @@ typedef struct pmf_options {
     int32_t order;              /* 0: FIFO packing order, 1: LPT (largest first)     */
     int64_t mem_budget;         /* bytes the library may allocate (0 = no limit)     */
     int32_t max_slots;          /* instance slots of a serving session (0 = 4096)    */
-    int32_t reserved[7];
+    int32_t timing;             /* 1: no graph; time every kernel with HIP events    */
+    int32_t reserved[6];
 } pmf_options;
 
 /* One (image, seed) problem and its lambda schedule.  All pointers are device
@@ -110,6 +111,15 @@ typedef struct pmf_stats {
     int64_t bfs_passes;       /* tile-parallel relaxation passes (relabel + cut)    */
     int64_t host_syncs;       /* host completion checks                             */
     int64_t device_bytes;     /* bytes of device memory held by the handle          */
+    int64_t device_ns;        /* GPU time of the superstep launches (HIP events)    */
+    int64_t px_init;          /* pixel visits per phase, summed over tiles:         */
+    int64_t px_sweep;         /*   init, push/relabel sweeps, global-relabel passes */
+    int64_t px_relabel;       /*   and cut passes (the unit of the algorithmic      */
+    int64_t px_cut;           /*   byte counts)                                     */
+    int64_t sweep_ns;         /* with opt.timing: GPU time of the sweep kernels,    */
+    int64_t bfs_ns;           /*   of the init/relabel/cut kernels and of the       */
+    int64_t control_ns;       /*   phase-machine kernel                             */
+    int64_t sweep_launches;   /* launches of the sweep kernels                      */
 } pmf_stats;
 
 /* Fill *opt with defaults. */
@@ -139,11 +149,20 @@ int pmf_solve_batch(pmf_handle *h, const pmf_instance *inst, int32_t n_inst, int
                     int32_t *status_out);
 
 /* Copy the minimal source side S_min of (instance inst, lambda index
- * lambda_idx) of the last solve into mask_out (device, uint8 [H][W]):
+ * lambda_idx) of the last solve -- inst is the index in the batch, or a
+ * session slot id -- into mask_out (device, uint8 [H][W]):
  * 1 = source side (foreground), 0 = sink side.  Enqueued on the handle's
  * stream.  Errors: PMF_ENOTSOLVED (no solve yet, or that instance did not
  * finish), PMF_ERANGE. */
 int pmf_extract_cut(pmf_handle *h, int32_t inst, int32_t lambda_idx, uint8_t *mask_out);
+
+/* The masks of every lambda of a finished instance as one byte per pixel
+ * (device, uint8 [H][W], caller-owned): the number of lambdas whose minimal
+ * source side contains the pixel.  Because these sets are nested (they shrink
+ * as lambda grows, Sec. 2.1), the mask of lambda index k is levels > k.
+ * Enqueued on the handle's stream.  Errors: PMF_ENOTSOLVED (not finished),
+ * PMF_ERANGE (bad id, or more than 255 lambdas). */
+int pmf_extract_levels(pmf_handle *h, int32_t inst, uint8_t *levels_out);
 
 /* Synchronise the stream and free everything the library allocated. */
 int pmf_destroy(pmf_handle *h);
@@ -155,6 +174,52 @@ const char *pmf_strerror(int code);
  * memory).  opt may be NULL. */
 int pmf_query_bytes(const pmf_instance *inst, int32_t n_inst, const pmf_options *opt,
                     size_t *bytes);
+
+/* ---- Serving: a resident session that instances join and leave ---------
+ * Instance state stays in device memory between calls.  Requests are admitted
+ * while earlier ones are still being solved and join the same launches at the
+ * next superstep (continuous batching); every instance's result is the same
+ * as when it is solved alone.  A handle is either in a session or used with
+ * pmf_solve_batch (which opens a fresh session sized for its batch). */
+
+typedef struct pmf_session_info {
+    int64_t free_bytes;    /* free pool bytes                        */
+    int64_t largest_free;  /* largest admissible instance block      */
+    int32_t free_slots;    /* instance slots not in use              */
+    int32_t admitted;      /* slots in use (running or finished)     */
+    int32_t running;       /* admitted instances not yet finished    */
+    int32_t reserved;
+} pmf_session_info;
+
+/* (Re)open the handle as a session with max_slots instance slots and a pool of
+ * pool_bytes device bytes for instance state.  pool_bytes = 0 takes the whole
+ * workspace, else opt->mem_budget, else half of the free device memory.
+ * Discards earlier results.  Errors: PMF_EINVAL, PMF_ENOMEM, PMF_EDEVICE. */
+int pmf_session_open(pmf_handle *h, int32_t max_slots, size_t pool_bytes);
+
+/* Admit n_inst instances, all or none.  flows_out / status_out are as in
+ * pmf_solve_batch (device memory owned by the caller; written when each
+ * instance finishes).  ids_out (host int32 [n_inst], may be NULL) receives
+ * the slot ids used by pmf_extract_cut and pmf_session_release.  Returns
+ * PMF_EBUSY, admitting nothing, when slots or pool memory are short (the
+ * caller retries after releasing finished instances). */
+int pmf_session_submit(pmf_handle *h, const pmf_instance *inst, int32_t n_inst, int64_t *flows_out,
+                       int32_t *status_out, int32_t *ids_out);
+
+/* Run `supersteps` supersteps (1..65536) over every admitted, unfinished
+ * instance, wait for them, and report the ids of the instances that finished
+ * during this call in done_ids (host, room for max_ids; *n_done = how many
+ * finished, which may exceed max_ids).  Their flows, status and masks are then
+ * complete in device memory. */
+int pmf_session_step(pmf_handle *h, int32_t supersteps, int32_t *done_ids, int32_t max_ids,
+                     int32_t *n_done);
+
+/* Return instance `id`'s slot and pool memory (an unfinished instance is
+ * cancelled).  Its masks can no longer be read.  Errors: PMF_ERANGE. */
+int pmf_session_release(pmf_handle *h, int32_t id);
+
+/* Pool and slot occupancy, for admission by free memory. */
+int pmf_session_query(pmf_handle *h, pmf_session_info *out);
 
 /* The host-side checks pmf_solve_batch makes before any launch (K is 4 or 8;
  * W, H, L >= 1; W * H <= 2^29; nlink, cap_src, cap_snk0, lambdas non-NULL).

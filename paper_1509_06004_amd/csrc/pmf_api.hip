@@ -1,9 +1,14 @@
-// Host side of libpmf: argument validation, device memory layout, packing of
-// instances into one tile space, and the superstep launch loop.
+// Host side of libpmf: argument validation, device memory (a pool of
+// per-instance blocks), the tile work list that packs all admitted instances
+// into shared launches, and the superstep loop (direct launches or hipGraph
+// replay).  pmf_solve_batch is a session that admits a whole batch at once
+// and runs it to completion.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <cstring>
+#include <functional>
+#include <map>
 #include <new>
 #include <numeric>
 #include <vector>
@@ -19,16 +24,8 @@ constexpr size_t kAlign = 256;
 
 inline size_t align_up(size_t v) { return (v + kAlign - 1) & ~(kAlign - 1); }
 
-struct Layout {
-    size_t desc, st, tile_slot, tile_local, tile_act, tile_chg, tile_cnt, ctl;
-    std::vector<size_t> r, e, rt, h, inbox, rmask, masks;
-    size_t total = 0;
-    int32_t ntiles = 0;
-    std::vector<int32_t> tiles_x, tiles_y, tile0;
-};
-
 void tile_dims(const pmf_options &o, int *tw, int *th) {
-    *tw = o.tile_w == 32 ? 32 : 64;
+    *tw = o.tile_w == 64 ? 64 : 32;
     *th = 1024 / *tw;
 }
 
@@ -53,86 +50,147 @@ int check_instance(const pmf_instance &I) {
     return PMF_OK;
 }
 
-// Packing order: FIFO keeps the caller's order; LPT puts the instances with
-// the most pixel-lambdas first so that the largest work is dispatched first
-// (the "largest processing time first" rule, Sec. 3.3.1).
-std::vector<int> packing_order(const pmf_instance *inst, int n, int order) {
-    std::vector<int> idx(n);
-    std::iota(idx.begin(), idx.end(), 0);
-    if (order == 1) {
-        std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) {
-            return (int64_t)inst[a].W * inst[a].H * inst[a].L > (int64_t)inst[b].W * inst[b].H * inst[b].L;
-        });
-    }
-    return idx;
-}
+// Byte offsets of one instance's planes inside its block.
+struct BlockLayout {
+    size_t r, e, rt, h, inbox, rmask, masks, tile_act, tile_chg, tile_cnt, total;
+    int tiles_x, tiles_y;
+};
 
-Layout plan(const pmf_instance *inst, int n, const pmf_options &o) {
-    int tw, th;
-    tile_dims(o, &tw, &th);
-    Layout L;
-    L.tiles_x.resize(n);
-    L.tiles_y.resize(n);
-    L.tile0.resize(n);
-    std::vector<int> ord = packing_order(inst, n, o.order);
-    int64_t t = 0;
-    for (int i : ord) {
-        L.tiles_x[i] = (inst[i].W + tw - 1) / tw;
-        L.tiles_y[i] = (inst[i].H + th - 1) / th;
-        L.tile0[i] = (int32_t)t;
-        t += (int64_t)L.tiles_x[i] * L.tiles_y[i];
-    }
-    L.ntiles = (int32_t)t;
+BlockLayout block_layout(const pmf_instance &I, int tw, int th) {
+    BlockLayout b;
+    b.tiles_x = (I.W + tw - 1) / tw;
+    b.tiles_y = (I.H + th - 1) / th;
+    const size_t px = (size_t)I.W * I.H, K = (size_t)I.K, nt = (size_t)b.tiles_x * b.tiles_y;
     size_t off = 0;
     auto take = [&](size_t bytes) {
         size_t at = off;
         off = align_up(off + bytes);
         return at;
     };
-    L.desc = take(sizeof(InstDesc) * (size_t)n);
-    L.st = take(sizeof(InstState) * (size_t)n);
-    L.tile_slot = take(sizeof(int32_t) * (size_t)t);
-    L.tile_local = take(sizeof(int32_t) * (size_t)t);
-    L.tile_act = take(sizeof(uint32_t) * (size_t)t);
-    L.tile_chg = take(2 * (size_t)t);
-    L.tile_cnt = take(sizeof(int32_t) * (size_t)t);
-    L.ctl = take(64);
-    for (int i = 0; i < n; ++i) {
-        const size_t px = (size_t)inst[i].W * inst[i].H, K = (size_t)inst[i].K;
-        L.r.push_back(take(4 * K * px));
-        L.e.push_back(take(4 * px));
-        L.rt.push_back(take(4 * px));
-        L.h.push_back(take(4 * px));
-        L.inbox.push_back(take(4 * K * px));
-        L.rmask.push_back(take(2 * px));
-        L.masks.push_back(take((size_t)inst[i].L * px));
-    }
-    L.total = off;
-    return L;
+    b.r = take(4 * K * px);
+    b.e = take(4 * px);
+    b.rt = take(4 * px);
+    b.h = take(4 * px);
+    b.inbox = take(4 * K * px);
+    b.rmask = take(2 * px);
+    b.masks = take((size_t)I.L * px);
+    b.tile_act = take(4 * nt);
+    b.tile_chg = take(2 * nt);
+    b.tile_cnt = take(4 * nt);
+    b.total = off;
+    return b;
 }
+
+// Work-list capacity for a pool: every tile's share of its instance block is
+// at least 512 bytes, so the pool can never hold more tiles than this.
+size_t worklist_cap(int slots, size_t pool_bytes) { return pool_bytes / 512 + (size_t)slots; }
+
+// Device bytes of the control area for `slots` slots and a work list of `wl` tiles.
+size_t control_bytes(int slots, size_t wl) {
+    return align_up(sizeof(InstDesc) * (size_t)slots) + align_up(sizeof(InstState) * (size_t)slots) +
+           align_up(4 * (size_t)slots) + align_up(64) + 2 * align_up(4 * wl);
+}
+
+// First-fit allocator over [0, cap) with coalescing of freed ranges.
+class Pool {
+   public:
+    void reset(size_t cap) {
+        free_.clear();
+        if (cap) free_[0] = cap;
+    }
+    bool alloc(size_t sz, size_t *off) {
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second >= sz) {
+                *off = it->first;
+                const size_t rest = it->second - sz;
+                const size_t at = it->first + sz;
+                free_.erase(it);
+                if (rest) free_[at] = rest;
+                return true;
+            }
+        }
+        return false;
+    }
+    void release(size_t off, size_t sz) {
+        auto it = free_.emplace(off, sz).first;
+        auto nx = std::next(it);
+        if (nx != free_.end() && it->first + it->second == nx->first) {
+            it->second += nx->second;
+            free_.erase(nx);
+        }
+        if (it != free_.begin()) {
+            auto pv = std::prev(it);
+            if (pv->first + pv->second == it->first) {
+                pv->second += it->second;
+                free_.erase(it);
+            }
+        }
+    }
+    size_t free_bytes() const {
+        size_t s = 0;
+        for (auto &kv : free_) s += kv.second;
+        return s;
+    }
+    size_t largest() const {
+        size_t m = 0;
+        for (auto &kv : free_) m = std::max(m, kv.second);
+        return m;
+    }
+
+   private:
+    std::map<size_t, size_t> free_;
+};
+
+struct Slot {
+    bool live = false;      // admitted and not released
+    bool finished = false;  // completion seen by the host
+    int32_t W = 0, H = 0, K = 0, L = 0, ntiles = 0, done_k = 0;
+    int64_t work = 0;       // pixels x lambdas (packing order)
+    size_t off = 0, bytes = 0;
+    size_t masks = 0;       // arena offset of the masks
+};
 
 }  // namespace
 
 struct pmf_handle {
     pmf_options opt;
+    int tw = 32, th = 32;
     hipStream_t stream = nullptr;
     hipStream_t capture = nullptr;
     int device = 0;
     char *arena = nullptr;
     size_t arena_bytes = 0;
     bool own_arena = true;
-    int32_t *pinned = nullptr;  // host-visible completion counter
-    // last solve
-    bool solved = false;
-    int n_inst = 0;
-    std::vector<int32_t> W, H, L;
-    std::vector<size_t> masks_off;
-    std::vector<InstState> final_state;
-    pmf_stats stats;
+    int32_t *pinned = nullptr;  // host-visible copy of the completion counter
+    int32_t *pinned_ring = nullptr;
+    InstState *pinned_state = nullptr;
+    // session
+    bool open = false;
+    int max_slots = 0;
+    size_t wl_cap = 0;
+    size_t pool_base = 0;
+    Pool pool;
+    std::vector<Slot> slots;
+    std::vector<int> free_slots;  // stack, lowest id on top
+    int32_t ring_seen = 0;
+    bool wl_dirty = true;
+    int64_t epoch_steps = 0;  // steps run since the work list last changed
+    StepParams P;
     hipGraphExec_t graph = nullptr;
+    int graph_S = 0;
+    pmf_stats stats;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;  // bracket every launch group (device time)
+    hipEvent_t kev[4] = {nullptr, nullptr, nullptr, nullptr};  // per-kernel timing mode
 };
 
 namespace {
+
+void drop_graph(pmf_handle *h) {
+    if (h->graph) {
+        (void)hipGraphExecDestroy(h->graph);
+        h->graph = nullptr;
+    }
+}
 
 int ensure_arena(pmf_handle *h, size_t need) {
     if (need <= h->arena_bytes) return PMF_OK;
@@ -155,11 +213,307 @@ int ensure_arena(pmf_handle *h, size_t need) {
     return PMF_OK;
 }
 
-void drop_graph(pmf_handle *h) {
-    if (h->graph) {
-        (void)hipGraphExecDestroy(h->graph);
-        h->graph = nullptr;
+// Lay out the control area at the start of the arena and the pool after it.
+int open_session(pmf_handle *h, int slots, size_t pool_bytes) {
+    if (slots < 1) return PMF_EINVAL;
+    drop_graph(h);
+    h->open = false;
+    (void)hipStreamSynchronize(h->stream);
+    const size_t wl = worklist_cap(slots, pool_bytes);
+    const size_t ctl = control_bytes(slots, wl);
+    int rc = ensure_arena(h, ctl + pool_bytes);
+    if (rc != PMF_OK) return rc;
+    if ((int)h->slots.size() < slots || !h->pinned_ring) {
+        if (h->pinned_state) (void)hipHostFree(h->pinned_state);
+        if (h->pinned_ring) (void)hipHostFree(h->pinned_ring);
+        h->pinned_state = nullptr;
+        h->pinned_ring = nullptr;
+        if (hipHostMalloc((void **)&h->pinned_ring, 4 * (size_t)slots, hipHostMallocDefault) != hipSuccess ||
+            hipHostMalloc((void **)&h->pinned_state, sizeof(InstState) * (size_t)slots, hipHostMallocDefault) !=
+                hipSuccess) {
+            (void)hipGetLastError();
+            return PMF_ENOMEM;
+        }
     }
+    char *A = h->arena;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t at = off;
+        off += align_up(bytes);
+        return A + at;
+    };
+    StepParams &P = h->P;
+    std::memset(&P, 0, sizeof(P));
+    P.desc = (InstDesc *)take(sizeof(InstDesc) * (size_t)slots);
+    P.st = (InstState *)take(sizeof(InstState) * (size_t)slots);
+    P.ring = (int32_t *)take(4 * (size_t)slots);
+    P.ring_count = (int32_t *)take(64);
+    P.tile_slot = (const int32_t *)take(4 * wl);
+    P.tile_local = (const int32_t *)take(4 * wl);
+    P.ring_cap = slots;
+    P.nslots = slots;
+    P.inner_iters = h->opt.inner_iters;
+    P.sweeps_per_relabel = h->opt.sweeps_per_relabel;
+    P.local_bfs_iters = h->opt.local_bfs_iters;
+    P.max_steps = h->opt.max_supersteps;
+    h->pool_base = off;
+    // the work list is sized for pool_bytes, so the pool must not exceed it
+    h->pool.reset(std::min(h->arena_bytes - off, pool_bytes));
+    h->max_slots = slots;
+    h->wl_cap = wl;
+    h->slots.assign(slots, Slot());
+    h->free_slots.clear();
+    for (int i = slots - 1; i >= 0; --i) h->free_slots.push_back(i);
+    h->ring_seen = 0;
+    h->wl_dirty = true;
+    h->epoch_steps = 0;
+    std::memset(&h->stats, 0, sizeof(h->stats));
+    h->stats.device_bytes = (int64_t)h->arena_bytes;
+    // every slot starts idle; the completion counter at zero
+    if (hipMemsetAsync(P.st, 0, sizeof(InstState) * (size_t)slots, h->stream) != hipSuccess ||
+        hipMemsetAsync(P.ring_count, 0, 64, h->stream) != hipSuccess)
+        return PMF_EDEVICE;
+    h->open = true;
+    return PMF_OK;
+}
+
+// Rebuild the work list: every tile of every admitted, unfinished instance,
+// 4-connected instances first, each group in FIFO or LPT (largest first)
+// order (the "largest processing time first" rule of Sec. 3.3.1).
+int rebuild_worklist(pmf_handle *h) {
+    std::vector<int> ids;
+    for (int i = 0; i < h->max_slots; ++i)
+        if (h->slots[i].live && !h->slots[i].finished) ids.push_back(i);
+    const bool lpt = h->opt.order == 1;
+    std::stable_sort(ids.begin(), ids.end(), [&](int a, int b) {
+        const Slot &x = h->slots[a], &y = h->slots[b];
+        if (x.K != y.K) return x.K < y.K;
+        return lpt ? x.work > y.work : false;
+    });
+    std::vector<int32_t> ts, tl;
+    int32_t t4 = 0;
+    for (int i : ids) {
+        const Slot &s = h->slots[i];
+        for (int t = 0; t < s.ntiles; ++t) {
+            ts.push_back(i);
+            tl.push_back(t);
+        }
+        if (s.K == 4) t4 += s.ntiles;
+    }
+    if (ts.size() > h->wl_cap) return PMF_ENOMEM;
+    StepParams &P = h->P;
+    P.ntiles = (int32_t)ts.size();
+    P.t4_begin = 0;
+    P.t4_count = t4;
+    P.t8_begin = t4;
+    P.t8_count = P.ntiles - t4;
+    if (!ts.empty()) {
+        if (hipMemcpyAsync((void *)P.tile_slot, ts.data(), 4 * ts.size(), hipMemcpyHostToDevice, h->stream) !=
+                hipSuccess ||
+            hipMemcpyAsync((void *)P.tile_local, tl.data(), 4 * tl.size(), hipMemcpyHostToDevice, h->stream) !=
+                hipSuccess)
+            return PMF_EDEVICE;
+        // pageable sources: the copies must finish before the vectors go
+        if (hipStreamSynchronize(h->stream) != hipSuccess) return PMF_EDEVICE;
+    }
+    drop_graph(h);
+    h->wl_dirty = false;
+    h->epoch_steps = 0;
+    return PMF_OK;
+}
+
+int submit(pmf_handle *h, const pmf_instance *inst, int n, int64_t *flows_out, int32_t *status_out,
+           int32_t *ids_out) {
+    if (!h->open) return PMF_EINVAL;
+    if (n < 0 || (n > 0 && (!inst || !flows_out))) return PMF_EINVAL;
+    for (int i = 0; i < n; ++i) {
+        const int rc = check_instance(inst[i]);
+        if (rc != PMF_OK) return rc;
+    }
+    if ((size_t)n > h->free_slots.size()) return PMF_EBUSY;
+    // all or nothing: allocate every block first
+    std::vector<size_t> offs(n);
+    std::vector<BlockLayout> lay(n);
+    int got = 0;
+    for (; got < n; ++got) {
+        lay[got] = block_layout(inst[got], h->tw, h->th);
+        if (!h->pool.alloc(lay[got].total, &offs[got])) break;
+    }
+    if (got < n) {
+        for (int i = 0; i < got; ++i) h->pool.release(offs[i], lay[i].total);
+        return PMF_EBUSY;
+    }
+    std::vector<InstDesc> desc(n);
+    std::vector<InstState> st(n);
+    std::vector<int> ids(n);
+    int64_t lam_base = 0;
+    for (int i = 0; i < n; ++i) {
+        const pmf_instance &I = inst[i];
+        const BlockLayout &B = lay[i];
+        char *base = h->arena + h->pool_base + offs[i];
+        const int id = h->free_slots.back();
+        h->free_slots.pop_back();
+        ids[i] = id;
+        InstDesc &D = desc[i];
+        std::memset(&D, 0, sizeof(D));
+        D.W = I.W;
+        D.H = I.H;
+        D.K = I.K;
+        D.n = I.W * I.H;
+        D.tiles_x = B.tiles_x;
+        D.tiles_y = B.tiles_y;
+        D.ntiles = B.tiles_x * B.tiles_y;
+        D.tile0 = 0;
+        D.L = I.L;
+        D.slot_id = id;
+        D.lambdas = I.lambdas;
+        D.nlink = I.nlink;
+        D.cap_src = I.cap_src;
+        D.cap_snk0 = I.cap_snk0;
+        D.slope = I.snk_slope;
+        D.seed = I.seed;
+        D.r = (int32_t *)(base + B.r);
+        D.e = (int32_t *)(base + B.e);
+        D.rt = (int32_t *)(base + B.rt);
+        D.h = (int32_t *)(base + B.h);
+        D.inbox = (int32_t *)(base + B.inbox);
+        D.rmask = (uint16_t *)(base + B.rmask);
+        D.masks = (uint8_t *)(base + B.masks);
+        D.tile_act = (uint32_t *)(base + B.tile_act);
+        D.tile_chg = (uint8_t *)(base + B.tile_chg);
+        D.tile_cnt = (int32_t *)(base + B.tile_cnt);
+        D.flows = flows_out + lam_base;
+        D.status = status_out ? status_out + i : nullptr;
+        lam_base += I.L;
+        std::memset(&st[i], 0, sizeof(InstState));
+        st[i].phase = kInit;
+        Slot &s = h->slots[id];
+        s = Slot();
+        s.live = true;
+        s.W = I.W;
+        s.H = I.H;
+        s.K = I.K;
+        s.L = I.L;
+        s.ntiles = D.ntiles;
+        s.work = (int64_t)I.W * I.H * I.L;
+        s.off = offs[i];
+        s.bytes = B.total;
+        s.masks = h->pool_base + offs[i] + B.masks;
+        if (ids_out) ids_out[i] = id;
+    }
+    // descriptors and states go to their slots (ids need not be contiguous)
+    for (int i = 0; i < n; ++i) {
+        if (hipMemcpyAsync(h->P.desc + ids[i], &desc[i], sizeof(InstDesc), hipMemcpyHostToDevice, h->stream) !=
+                hipSuccess ||
+            hipMemcpyAsync(h->P.st + ids[i], &st[i], sizeof(InstState), hipMemcpyHostToDevice, h->stream) !=
+                hipSuccess)
+            return PMF_EDEVICE;
+    }
+    if (hipStreamSynchronize(h->stream) != hipSuccess) return PMF_EDEVICE;
+    if (n) h->wl_dirty = true;
+    return PMF_OK;
+}
+
+void read_kernel_events(pmf_handle *h) {
+    float a = 0.f, b = 0.f, c = 0.f;
+    if (hipEventElapsedTime(&a, h->kev[0], h->kev[1]) == hipSuccess) h->stats.sweep_ns += (int64_t)(a * 1e6);
+    if (hipEventElapsedTime(&b, h->kev[1], h->kev[2]) == hipSuccess) h->stats.bfs_ns += (int64_t)(b * 1e6);
+    if (hipEventElapsedTime(&c, h->kev[2], h->kev[3]) == hipSuccess) h->stats.control_ns += (int64_t)(c * 1e6);
+}
+
+// Launch `steps` supersteps, wait, and collect the slots that finished.
+int run_steps(pmf_handle *h, int steps, std::vector<int> *finished) {
+    if (h->wl_dirty) {
+        const int rc = rebuild_worklist(h);
+        if (rc != PMF_OK) return rc;
+    }
+    StepParams &P = h->P;
+    hipStream_t s = h->stream;
+    const bool timing = h->opt.timing != 0;
+    if (P.ntiles > 0) {
+        // replay a captured graph once the work list has been used once
+        const bool use_graph = h->opt.use_graph && !timing && h->epoch_steps > 0;
+        if (use_graph && (!h->graph || h->graph_S != steps)) {
+            drop_graph(h);
+            hipGraph_t g = nullptr;
+            bool ok = hipStreamBeginCapture(h->capture, hipStreamCaptureModeThreadLocal) == hipSuccess;
+            for (int i = 0; ok && i < steps; ++i) ok = launch_superstep(P, h->tw, h->capture) >= 0;
+            const bool ended = hipStreamEndCapture(h->capture, &g) == hipSuccess;
+            ok = ok && ended && hipGraphInstantiate(&h->graph, g, nullptr, nullptr, 0) == hipSuccess;
+            if (g) (void)hipGraphDestroy(g);
+            if (!ok) {
+                (void)hipGetLastError();
+                drop_graph(h);
+                return PMF_EDEVICE;
+            }
+            h->graph_S = steps;
+        }
+        if (hipEventRecord(h->ev0, s) != hipSuccess) return PMF_EDEVICE;
+        if (use_graph) {
+            if (hipGraphLaunch(h->graph, s) != hipSuccess) return PMF_EDEVICE;
+            h->stats.sweep_launches += (int64_t)steps * ((P.t4_count > 0) + (P.t8_count > 0));
+        } else {
+            for (int i = 0; i < steps; ++i) {
+                const int ns = launch_superstep(P, h->tw, s, timing ? (void *const *)h->kev : nullptr);
+                if (ns < 0) return PMF_EDEVICE;
+                h->stats.sweep_launches += ns;
+                if (timing && i + 1 < steps) {
+                    // the per-kernel events are reused: read them before the next superstep
+                    if (hipStreamSynchronize(s) != hipSuccess) return PMF_EDEVICE;
+                    read_kernel_events(h);
+                }
+            }
+        }
+        if (hipEventRecord(h->ev1, s) != hipSuccess) return PMF_EDEVICE;
+        h->stats.supersteps += steps;
+        h->epoch_steps += steps;
+    }
+    if (hipMemcpyAsync(h->pinned, P.ring_count, 4, hipMemcpyDeviceToHost, s) != hipSuccess) return PMF_EDEVICE;
+    if (hipStreamSynchronize(s) != hipSuccess) return PMF_EDEVICE;
+    h->stats.host_syncs += 1;
+    if (P.ntiles > 0) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, h->ev0, h->ev1) == hipSuccess) h->stats.device_ns += (int64_t)(ms * 1e6);
+        if (timing) read_kernel_events(h);
+    }
+    const int32_t count = *(volatile int32_t *)h->pinned;
+    if (count <= h->ring_seen) return PMF_OK;
+    // the new ring entries, then the final states of those instances
+    const int cap = h->max_slots;
+    for (int32_t c = h->ring_seen; c < count; ++c) {
+        const int at = c % cap;
+        if (hipMemcpyAsync(h->pinned_ring + at, P.ring + at, 4, hipMemcpyDeviceToHost, s) != hipSuccess)
+            return PMF_EDEVICE;
+    }
+    if (hipStreamSynchronize(s) != hipSuccess) return PMF_EDEVICE;
+    std::vector<int> got;
+    for (int32_t c = h->ring_seen; c < count; ++c) {
+        const int id = h->pinned_ring[c % cap];
+        if (id < 0 || id >= cap) return PMF_EDEVICE;
+        got.push_back(id);
+        if (hipMemcpyAsync(h->pinned_state + id, P.st + id, sizeof(InstState), hipMemcpyDeviceToHost, s) !=
+            hipSuccess)
+            return PMF_EDEVICE;
+    }
+    if (hipStreamSynchronize(s) != hipSuccess) return PMF_EDEVICE;
+    h->ring_seen = count;
+    for (int id : got) {
+        Slot &sl = h->slots[id];
+        const InstState &x = h->pinned_state[id];
+        sl.finished = true;
+        sl.done_k = x.k;
+        h->stats.px_init += x.px_init;
+        h->stats.px_sweep += x.px_sweep;
+        h->stats.px_relabel += x.px_relabel;
+        h->stats.px_cut += x.px_cut;
+        h->stats.sweep_visits += x.sweeps;
+        h->stats.global_relabels += x.relabels;
+        h->stats.bfs_passes += x.passes;
+        if (finished) finished->push_back(id);
+    }
+    // finished instances leave the work list at the next step
+    h->wl_dirty = true;
+    return PMF_OK;
 }
 
 }  // namespace
@@ -169,10 +523,10 @@ extern "C" {
 void pmf_default_options(pmf_options *o) {
     if (!o) return;
     std::memset(o, 0, sizeof(*o));
-    o->tile_w = 64;
-    o->tile_h = 16;
+    o->tile_w = 32;
+    o->tile_h = 32;
     o->inner_iters = 16;
-    o->sweeps_per_relabel = 4;
+    o->sweeps_per_relabel = 8;
     o->local_bfs_iters = 64;
     o->steps_per_sync = 32;
     o->max_supersteps = 2000000;
@@ -192,7 +546,7 @@ const char *pmf_strerror(int code) {
         case PMF_ETIMEOUT: return "superstep budget exhausted";
         case PMF_ENOTSOLVED: return "no completed solve for this instance and lambda";
         case PMF_ERANGE: return "instance or lambda index out of range";
-        case PMF_EBUSY: return "no free slot";
+        case PMF_EBUSY: return "no free slot or pool memory";
         default: return "unknown status";
     }
 }
@@ -205,14 +559,18 @@ int pmf_create(const pmf_options *opt, void *stream, void *workspace, size_t ws_
         o = *opt;
     else
         pmf_default_options(&o);
-    if (o.tile_w == 0) o.tile_w = 64;
+    if (o.tile_w == 0) o.tile_w = 32;
+    if (o.tile_h == 0) o.tile_h = 1024 / o.tile_w;
+    if (o.max_slots == 0) o.max_slots = 4096;
     if (!valid_options(o)) return PMF_EINVAL;
     if (workspace && ws_bytes == 0) return PMF_EINVAL;
     pmf_handle *h = new (std::nothrow) pmf_handle();
     if (!h) return PMF_ENOMEM;
     h->opt = o;
+    tile_dims(o, &h->tw, &h->th);
     h->stream = (hipStream_t)stream;
     std::memset(&h->stats, 0, sizeof(h->stats));
+    std::memset(&h->P, 0, sizeof(h->P));
     if (hipGetDevice(&h->device) != hipSuccess) {
         delete h;
         return PMF_EDEVICE;
@@ -222,30 +580,16 @@ int pmf_create(const pmf_options *opt, void *stream, void *workspace, size_t ws_
         h->arena_bytes = ws_bytes;
         h->own_arena = false;
     }
-    if (hipHostMalloc((void **)&h->pinned, 64, hipHostMallocDefault) != hipSuccess) {
+    if (hipHostMalloc((void **)&h->pinned, 64, hipHostMallocDefault) != hipSuccess ||
+        hipStreamCreateWithFlags(&h->capture, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreate(&h->ev0) != hipSuccess || hipEventCreate(&h->ev1) != hipSuccess ||
+        hipEventCreate(&h->kev[0]) != hipSuccess || hipEventCreate(&h->kev[1]) != hipSuccess ||
+        hipEventCreate(&h->kev[2]) != hipSuccess || hipEventCreate(&h->kev[3]) != hipSuccess) {
         (void)hipGetLastError();
-        delete h;
-        return PMF_EDEVICE;
-    }
-    if (hipStreamCreateWithFlags(&h->capture, hipStreamNonBlocking) != hipSuccess) {
-        (void)hipHostFree(h->pinned);
-        delete h;
+        pmf_destroy(h);
         return PMF_EDEVICE;
     }
     *out = h;
-    return PMF_OK;
-}
-
-int pmf_query_bytes(const pmf_instance *inst, int32_t n, const pmf_options *opt, size_t *bytes) {
-    if (!bytes || n < 0 || (n > 0 && !inst)) return PMF_EINVAL;
-    pmf_options o;
-    if (opt)
-        o = *opt;
-    else
-        pmf_default_options(&o);
-    for (int i = 0; i < n; ++i)
-        if (check_instance(inst[i]) != PMF_OK) return PMF_EINVAL;
-    *bytes = plan(inst, n, o).total;
     return PMF_OK;
 }
 
@@ -261,159 +605,151 @@ int pmf_check_instances(const pmf_instance *inst, int32_t n_inst, int32_t *first
     return PMF_OK;
 }
 
+int pmf_query_bytes(const pmf_instance *inst, int32_t n, const pmf_options *opt, size_t *bytes) {
+    if (!bytes || n < 0 || (n > 0 && !inst)) return PMF_EINVAL;
+    pmf_options o;
+    if (opt)
+        o = *opt;
+    else
+        pmf_default_options(&o);
+    int tw, th;
+    tile_dims(o, &tw, &th);
+    size_t pool = 0;
+    for (int i = 0; i < n; ++i) {
+        if (check_instance(inst[i]) != PMF_OK) return PMF_EINVAL;
+        pool += block_layout(inst[i], tw, th).total;
+    }
+    *bytes = pool;
+    return PMF_OK;
+}
+
 int pmf_solve_batch(pmf_handle *h, const pmf_instance *inst, int32_t n_inst, int64_t *flows_out,
                     int32_t *status_out) {
     if (!h || n_inst < 0 || (n_inst > 0 && (!inst || !flows_out))) return PMF_EINVAL;
-    for (int i = 0; i < n_inst; ++i) {
-        const int rc = check_instance(inst[i]);
-        if (rc != PMF_OK) return rc;
-    }
-    h->solved = false;
-    h->n_inst = 0;
-    if (n_inst == 0) return PMF_OK;
-    drop_graph(h);
-    const Layout Lo = plan(inst, n_inst, h->opt);
-    int rc = ensure_arena(h, Lo.total);
+    int rc = pmf_check_instances(inst, n_inst, nullptr);
     if (rc != PMF_OK) return rc;
-    char *A = h->arena;
-    int tw, th;
-    tile_dims(h->opt, &tw, &th);
-
-    std::vector<InstDesc> desc(n_inst);
-    std::vector<InstState> st(n_inst);
-    std::vector<int32_t> tslot(Lo.ntiles), tlocal(Lo.ntiles);
-    int64_t lam_base = 0;
-    h->W.assign(n_inst, 0);
-    h->H.assign(n_inst, 0);
-    h->L.assign(n_inst, 0);
-    h->masks_off.assign(n_inst, 0);
-    for (int i = 0; i < n_inst; ++i) {
-        const pmf_instance &I = inst[i];
-        InstDesc &D = desc[i];
-        std::memset(&D, 0, sizeof(D));
-        D.W = I.W;
-        D.H = I.H;
-        D.K = I.K;
-        D.n = I.W * I.H;
-        D.tiles_x = Lo.tiles_x[i];
-        D.tiles_y = Lo.tiles_y[i];
-        D.ntiles = D.tiles_x * D.tiles_y;
-        D.tile0 = Lo.tile0[i];
-        D.L = I.L;
-        D.slot_id = i;
-        D.lambdas = I.lambdas;
-        D.nlink = I.nlink;
-        D.cap_src = I.cap_src;
-        D.cap_snk0 = I.cap_snk0;
-        D.slope = I.snk_slope;
-        D.seed = I.seed;
-        D.r = (int32_t *)(A + Lo.r[i]);
-        D.e = (int32_t *)(A + Lo.e[i]);
-        D.rt = (int32_t *)(A + Lo.rt[i]);
-        D.h = (int32_t *)(A + Lo.h[i]);
-        D.inbox = (int32_t *)(A + Lo.inbox[i]);
-        D.rmask = (uint16_t *)(A + Lo.rmask[i]);
-        D.masks = (uint8_t *)(A + Lo.masks[i]);
-        D.flows = flows_out + lam_base;
-        D.status = status_out ? status_out + i : nullptr;
-        lam_base += I.L;
-        std::memset(&st[i], 0, sizeof(InstState));
-        st[i].phase = kInit;
-        for (int t = 0; t < D.ntiles; ++t) {
-            tslot[D.tile0 + t] = i;
-            tlocal[D.tile0 + t] = t;
-        }
-        h->W[i] = I.W;
-        h->H[i] = I.H;
-        h->L[i] = I.L;
-        h->masks_off[i] = Lo.masks[i];
-    }
-    hipStream_t s = h->stream;
-    bool ok = true;
-    ok &= hipMemcpyAsync(A + Lo.desc, desc.data(), sizeof(InstDesc) * n_inst, hipMemcpyHostToDevice, s) == hipSuccess;
-    ok &= hipMemcpyAsync(A + Lo.st, st.data(), sizeof(InstState) * n_inst, hipMemcpyHostToDevice, s) == hipSuccess;
-    ok &= hipMemcpyAsync(A + Lo.tile_slot, tslot.data(), 4 * (size_t)Lo.ntiles, hipMemcpyHostToDevice, s) == hipSuccess;
-    ok &= hipMemcpyAsync(A + Lo.tile_local, tlocal.data(), 4 * (size_t)Lo.ntiles, hipMemcpyHostToDevice, s) == hipSuccess;
-    ok &= hipMemsetAsync(A + Lo.ctl, 0, 64, s) == hipSuccess;
-    if (!ok) return PMF_EDEVICE;
-
-    StepParams P;
-    std::memset(&P, 0, sizeof(P));
-    P.desc = (InstDesc *)(A + Lo.desc);
-    P.st = (InstState *)(A + Lo.st);
-    P.tile_slot = (const int32_t *)(A + Lo.tile_slot);
-    P.tile_local = (const int32_t *)(A + Lo.tile_local);
-    P.tile_act = (uint32_t *)(A + Lo.tile_act);
-    P.tile_chg = (uint8_t *)(A + Lo.tile_chg);
-    P.tile_cnt = (int32_t *)(A + Lo.tile_cnt);
-    P.arrive = (uint32_t *)(A + Lo.ctl);
-    P.ndone = (int32_t *)(A + Lo.ctl + 4);
-    P.counters = nullptr;
-    P.ntiles = Lo.ntiles;
-    P.per_xcd = (Lo.ntiles + 7) / 8;
-    P.nslots = n_inst;
-    P.inner_iters = h->opt.inner_iters;
-    P.sweeps_per_relabel = h->opt.sweeps_per_relabel;
-    P.local_bfs_iters = h->opt.local_bfs_iters;
-    P.max_steps = h->opt.max_supersteps;
-
-    const int S = h->opt.steps_per_sync;
-    if (h->opt.use_graph) {
-        hipGraph_t g = nullptr;
-        ok = hipStreamBeginCapture(h->capture, hipStreamCaptureModeThreadLocal) == hipSuccess;
-        for (int i = 0; ok && i < S; ++i) ok = launch_superstep(P, tw, h->capture) == 0;
-        const bool ended = hipStreamEndCapture(h->capture, &g) == hipSuccess;
-        ok = ok && ended && hipGraphInstantiate(&h->graph, g, nullptr, nullptr, 0) == hipSuccess;
-        if (g) (void)hipGraphDestroy(g);
-        if (!ok) {
-            (void)hipGetLastError();
-            drop_graph(h);
-            return PMF_EDEVICE;
-        }
-    }
-    std::memset(&h->stats, 0, sizeof(h->stats));
-    h->stats.device_bytes = (int64_t)h->arena_bytes;
-    // Every instance ends within max_supersteps supersteps (device watchdog),
-    // so this loop is bounded; the extra margin covers the final transitions.
+    size_t pool = 0;
+    for (int i = 0; i < n_inst; ++i) pool += block_layout(inst[i], h->tw, h->th).total;
+    rc = open_session(h, std::max(n_inst, 1), pool);
+    if (rc != PMF_OK) return rc;
+    if (n_inst == 0) return PMF_OK;
+    rc = submit(h, inst, n_inst, flows_out, status_out, nullptr);
+    if (rc != PMF_OK) return rc == PMF_EBUSY ? PMF_ENOMEM : rc;
+    // The work list keeps finished instances (their tiles exit at once), so
+    // one captured superstep graph serves the whole solve.
+    const int S = h->opt.timing ? 1 : h->opt.steps_per_sync;
     const int64_t max_rounds = h->opt.max_supersteps / S + 4;
-    int64_t rounds = 0;
-    for (;;) {
-        if (h->graph) {
-            if (hipGraphLaunch(h->graph, s) != hipSuccess) return PMF_EDEVICE;
-        } else {
-            for (int i = 0; i < S; ++i)
-                if (launch_superstep(P, tw, s) != 0) return PMF_EDEVICE;
-        }
-        h->stats.supersteps += S;
-        if (hipMemcpyAsync(h->pinned, P.ndone, 4, hipMemcpyDeviceToHost, s) != hipSuccess) return PMF_EDEVICE;
-        if (hipStreamSynchronize(s) != hipSuccess) return PMF_EDEVICE;
-        h->stats.host_syncs += 1;
-        if (*(volatile int32_t *)h->pinned >= n_inst) break;
-        if (++rounds > max_rounds) return PMF_ETIMEOUT;
+    int done = 0;
+    std::vector<int> fin;
+    for (int64_t round = 0; done < n_inst; ++round) {
+        if (round > max_rounds) return PMF_ETIMEOUT;
+        fin.clear();
+        rc = run_steps(h, S, &fin);
+        if (rc != PMF_OK) return rc;
+        done += (int)fin.size();
+        h->wl_dirty = false;
     }
-    h->final_state.resize(n_inst);
-    if (hipMemcpyAsync(h->final_state.data(), P.st, sizeof(InstState) * n_inst, hipMemcpyDeviceToHost, s) != hipSuccess)
-        return PMF_EDEVICE;
-    if (hipStreamSynchronize(s) != hipSuccess) return PMF_EDEVICE;
-    for (const InstState &x : h->final_state) {
-        h->stats.sweep_visits += x.sweeps;
-        h->stats.global_relabels += x.relabels;
-        h->stats.bfs_passes += x.passes;
-    }
-    h->n_inst = n_inst;
-    h->solved = true;
     return PMF_OK;
 }
 
 int pmf_extract_cut(pmf_handle *h, int32_t inst, int32_t lambda_idx, uint8_t *mask_out) {
     if (!h || !mask_out) return PMF_EINVAL;
-    if (!h->solved) return PMF_ENOTSOLVED;
-    if (inst < 0 || inst >= h->n_inst) return PMF_ERANGE;
-    if (lambda_idx < 0 || lambda_idx >= h->L[inst]) return PMF_ERANGE;
-    if (h->final_state[inst].k <= lambda_idx) return PMF_ENOTSOLVED;
-    const size_t px = (size_t)h->W[inst] * h->H[inst];
-    const char *src = h->arena + h->masks_off[inst] + (size_t)lambda_idx * px;
+    if (!h->open) return PMF_ENOTSOLVED;
+    if (inst < 0 || inst >= h->max_slots || !h->slots[inst].live) return PMF_ERANGE;
+    const Slot &s = h->slots[inst];
+    if (lambda_idx < 0 || lambda_idx >= s.L) return PMF_ERANGE;
+    if (!s.finished || s.done_k <= lambda_idx) return PMF_ENOTSOLVED;
+    const size_t px = (size_t)s.W * s.H;
+    const char *src = h->arena + s.masks + (size_t)lambda_idx * px;
     if (hipMemcpyAsync(mask_out, src, px, hipMemcpyDeviceToDevice, h->stream) != hipSuccess) return PMF_EDEVICE;
+    return PMF_OK;
+}
+
+int pmf_extract_levels(pmf_handle *h, int32_t inst, uint8_t *levels_out) {
+    if (!h || !levels_out) return PMF_EINVAL;
+    if (!h->open) return PMF_ENOTSOLVED;
+    if (inst < 0 || inst >= h->max_slots || !h->slots[inst].live) return PMF_ERANGE;
+    const Slot &s = h->slots[inst];
+    if (s.L > 255) return PMF_ERANGE;
+    if (!s.finished || s.done_k < s.L) return PMF_ENOTSOLVED;
+    const uint8_t *masks = (const uint8_t *)(h->arena + s.masks);
+    return launch_levels(masks, s.L, s.W * s.H, levels_out, h->stream) == 0 ? PMF_OK : PMF_EDEVICE;
+}
+
+int pmf_session_open(pmf_handle *h, int32_t max_slots, size_t pool_bytes) {
+    if (!h || max_slots < 1) return PMF_EINVAL;
+    if (pool_bytes == 0) {
+        size_t avail = 0;
+        if (!h->own_arena) {
+            avail = h->arena_bytes;
+        } else if (h->opt.mem_budget > 0) {
+            avail = (size_t)h->opt.mem_budget;
+        } else {
+            size_t fr = 0, tot = 0;
+            if (hipMemGetInfo(&fr, &tot) != hipSuccess) return PMF_EDEVICE;
+            avail = fr / 2 + h->arena_bytes;
+        }
+        // the control area grows with the pool (work list); leave room for it
+        const size_t ctl0 = control_bytes(max_slots, (size_t)max_slots);
+        if (avail <= ctl0 + (1 << 20)) return PMF_ENOMEM;
+        pool_bytes = (avail - ctl0) / 129 * 128;
+        while (pool_bytes > 0 && control_bytes(max_slots, worklist_cap(max_slots, pool_bytes)) + pool_bytes > avail)
+            pool_bytes -= std::min(pool_bytes, (size_t)1 << 20);
+    }
+    return open_session(h, max_slots, pool_bytes);
+}
+
+int pmf_session_submit(pmf_handle *h, const pmf_instance *inst, int32_t n_inst, int64_t *flows_out,
+                       int32_t *status_out, int32_t *ids_out) {
+    if (!h) return PMF_EINVAL;
+    return submit(h, inst, n_inst, flows_out, status_out, ids_out);
+}
+
+int pmf_session_step(pmf_handle *h, int32_t supersteps, int32_t *done_ids, int32_t max_ids, int32_t *n_done) {
+    if (!h || supersteps < 1 || supersteps > (1 << 16) || max_ids < 0 || (max_ids > 0 && !done_ids))
+        return PMF_EINVAL;
+    if (n_done) *n_done = 0;
+    if (!h->open) return PMF_EINVAL;
+    std::vector<int> fin;
+    const int rc = run_steps(h, supersteps, &fin);
+    if (rc != PMF_OK) return rc;
+    const int n = std::min((int)fin.size(), (int)max_ids);
+    for (int i = 0; i < n; ++i) done_ids[i] = fin[i];
+    if (n_done) *n_done = (int32_t)fin.size();
+    return PMF_OK;
+}
+
+int pmf_session_release(pmf_handle *h, int32_t id) {
+    if (!h || !h->open) return PMF_EINVAL;
+    if (id < 0 || id >= h->max_slots || !h->slots[id].live) return PMF_ERANGE;
+    Slot &s = h->slots[id];
+    if (!s.finished) {
+        // cancel: the slot goes idle before its memory can be reused
+        InstState idle;
+        std::memset(&idle, 0, sizeof(idle));
+        if (hipMemcpyAsync(h->P.st + id, &idle, sizeof(idle), hipMemcpyHostToDevice, h->stream) != hipSuccess ||
+            hipStreamSynchronize(h->stream) != hipSuccess)
+            return PMF_EDEVICE;
+        h->wl_dirty = true;
+    }
+    h->pool.release(s.off, s.bytes);
+    s = Slot();
+    h->free_slots.push_back(id);
+    std::sort(h->free_slots.begin(), h->free_slots.end(), std::greater<int>());
+    return PMF_OK;
+}
+
+int pmf_session_query(pmf_handle *h, pmf_session_info *out) {
+    if (!h || !out) return PMF_EINVAL;
+    std::memset(out, 0, sizeof(*out));
+    if (!h->open) return PMF_OK;
+    out->free_bytes = (int64_t)h->pool.free_bytes();
+    out->largest_free = (int64_t)h->pool.largest();
+    out->free_slots = (int32_t)h->free_slots.size();
+    for (const Slot &s : h->slots) {
+        out->admitted += s.live;
+        out->running += s.live && !s.finished;
+    }
     return PMF_OK;
 }
 
@@ -429,7 +765,13 @@ int pmf_destroy(pmf_handle *h) {
     drop_graph(h);
     if (h->own_arena && h->arena) (void)hipFree(h->arena);
     if (h->pinned) (void)hipHostFree(h->pinned);
+    if (h->pinned_ring) (void)hipHostFree(h->pinned_ring);
+    if (h->pinned_state) (void)hipHostFree(h->pinned_state);
     if (h->capture) (void)hipStreamDestroy(h->capture);
+    if (h->ev0) (void)hipEventDestroy(h->ev0);
+    if (h->ev1) (void)hipEventDestroy(h->ev1);
+    for (hipEvent_t e : h->kev)
+        if (e) (void)hipEventDestroy(e);
     delete h;
     return PMF_OK;
 }

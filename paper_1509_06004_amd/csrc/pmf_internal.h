@@ -51,6 +51,9 @@ struct alignas(16) InstDesc {
     uint8_t *masks;
     int64_t *flows;   // L entries (caller memory)
     int32_t *status;  // 1 entry (caller memory), may be null
+    uint32_t *tile_act;  // [ntiles] bit 0: active pixels, bit 1: inbox pending
+    uint8_t *tile_chg;   // [2][ntiles] a label changed in the pass of that parity
+    int32_t *tile_cnt;   // [ntiles] active pixels under the current labels
 };
 
 struct alignas(16) InstState {
@@ -66,21 +69,20 @@ struct alignas(16) InstState {
     int64_t sum_e;    // total excess at the end of a lambda
     int64_t steps;    // supersteps spent (budget)
     int64_t passes;   // relaxation passes (statistics)
+    int64_t px_init, px_sweep, px_relabel, px_cut;  // pixel visits per phase
 };
 
 struct StepParams {
-    InstDesc *desc;
-    InstState *st;
-    const int32_t *tile_slot;   // [ntiles] instance slot of each tile
-    const int32_t *tile_local;  // [ntiles] tile index inside its instance
-    uint32_t *tile_act;         // [ntiles] bit 0 active pixels, bit 1 inbox pending
-    uint8_t *tile_chg;          // [2][ntiles] label changed in pass (parity)
-    int32_t *tile_cnt;          // [ntiles] active pixels under current labels
-    uint32_t *arrive;           // arrival counter of the last-workgroup pattern
-    int32_t *ndone;             // instances finished (read by the host)
-    int64_t *counters;          // [4] sweep visits, bfs tile passes, relabels, steps
+    InstDesc *desc;             // [nslots]
+    InstState *st;              // [nslots]
+    const int32_t *tile_slot;   // work list: instance slot of each tile
+    const int32_t *tile_local;  // work list: tile index inside its instance
+    int32_t *ring;              // completion ring: slots in order of completion
+    int32_t *ring_count;        // completions so far (ring index = count % ring_cap)
+    int32_t ring_cap;
     int32_t ntiles;
-    int32_t per_xcd;            // ceil(ntiles / 8)
+    int32_t t4_begin, t4_count; // tiles of 4-connected instances (contiguous)
+    int32_t t8_begin, t8_count; // tiles of 8-connected instances (contiguous)
     int32_t nslots;
     int32_t inner_iters;
     int32_t sweeps_per_relabel;
@@ -88,8 +90,14 @@ struct StepParams {
     int64_t max_steps;
 };
 
-// Launch one superstep over every tile (defined in pmf_kernels.hip).
-int launch_superstep(const StepParams &p, int tile_w, void *stream);
-int max_lds_bytes(int tile_w);
+// Enqueue one superstep (sweep, relabel/cut and control kernels) over every
+// tile (defined in pmf_kernels.hip).  With `events` (4 hipEvent_t), events
+// 0..3 are recorded before the sweeps, after them, after the relabel/cut
+// kernels and after the control kernel.  Returns the number of sweep kernels
+// launched, or -1 on a launch error.
+int launch_superstep(const StepParams &p, int tile_w, void *stream, void *const *events = nullptr);
+
+// out[p] = number of the L masks that hold pixel p (n pixels).
+int launch_levels(const uint8_t *masks, int L, int n, uint8_t *out, void *stream);
 
 }  // namespace pmf

@@ -79,6 +79,18 @@ struct Geo {
     }
 };
 
+// Pixels of tile (tx, ty) that lie inside the W x H image.
+template <int TW, int TH>
+__device__ __forceinline__ long long tile_pixels(int W, int H, int x0, int y0) {
+    const int w = W - x0 < TW ? W - x0 : TW;
+    const int h = H - y0 < TH ? H - y0 : TH;
+    return (long long)w * h;
+}
+
+__device__ __forceinline__ void count_px(int64_t *ctr, long long v) {
+    atomicAdd((unsigned long long *)ctr, (unsigned long long)v);
+}
+
 // Shared by all phases: block-wide integer sum (returned to every thread).
 __device__ __forceinline__ int block_sum_int(int v, int *s_red) {
     __syncthreads();
@@ -175,10 +187,11 @@ __device__ void init_tile(const StepParams &P, const InstDesc &D, InstState *S, 
     const long long tot = block_sum_i64(scs, s_sum);
     if (tid == 0) {
         if (tot) atomicAdd((unsigned long long *)&S->sum_cs, (unsigned long long)tot);
-        P.tile_act[tg] = 0;
-        P.tile_cnt[tg] = 0;
-        P.tile_chg[tg] = 1;
-        P.tile_chg[P.ntiles + tg] = 1;
+        count_px(&S->px_init, tile_pixels<TW, TH>(W, H, x0, y0));
+        D.tile_act[tl] = 0;
+        D.tile_cnt[tl] = 0;
+        D.tile_chg[tl] = 1;
+        D.tile_chg[D.ntiles + tl] = 1;
     }
     if (err) atomicOr(&S->err, err);
     (void)s_red;
@@ -194,7 +207,7 @@ __device__ void sweep_tile(const StepParams &P, const InstDesc &D, InstState *S,
     constexpr int PPT = G::PPT, RPI = G::RPI, HW = G::HW;
     const int tid = threadIdx.x, lx = tid % TW, ly0 = tid / TW;
     // neighbours may set the pending bit concurrently: one read, broadcast
-    if (tid == 0) s_red[1] = (int)(ld_agent(&P.tile_act[tg]) & 3u);
+    if (tid == 0) s_red[1] = (int)(ld_agent(&D.tile_act[tl]) & 3u);
     __syncthreads();
     if (s_red[1] == 0) return;  // nothing to push here, nothing arrived
     const int tx = tl % D.tiles_x, ty = tl / D.tiles_x;
@@ -206,18 +219,22 @@ __device__ void sweep_tile(const StepParams &P, const InstDesc &D, InstState *S,
     __shared__ int s_nb[9];
 
     if (tid < 9) s_nb[tid] = 0;
-    if (tid == 0) atomicAnd(&P.tile_act[tg], ~2u);  // about to drain the inbox
+    if (tid == 0) atomicAnd(&D.tile_act[tl], ~2u);  // about to drain the inbox
     __syncthreads();
 
-    int r[PPT][K], e[PPT], rt[PPT], h[PPT], hacc[PPT][K];
+    int r[PPT][K], e[PPT], rt[PPT], h[PPT];
     bool valid[PPT];
 #pragma unroll
     for (int j = 0; j < PPT; ++j) {
         const int ly = ly0 + j * RPI;
         const int gx = x0 + lx, gy = y0 + ly;
         valid[j] = gx < W && gy < H;
+        // entries of sh_out towards other tiles accumulate over the whole visit
 #pragma unroll
-        for (int k = 0; k < K; ++k) hacc[j][k] = 0;
+        for (int k = 0; k < K; ++k) {
+            const int nx = lx + DXk(k), ny = ly + DYk(k);
+            if (!(nx >= 0 && nx < TW && ny >= 0 && ny < TH)) sh_out[k * (TW * TH) + ly * TW + lx] = 0;
+        }
         if (valid[j]) {
             const int p = gy * W + gx;
 #pragma unroll
@@ -265,7 +282,8 @@ __device__ void sweep_tile(const StepParams &P, const InstDesc &D, InstState *S,
             int o[K];
 #pragma unroll
             for (int k = 0; k < K; ++k) o[k] = 0;
-            if (e[j] > 0 && h[j] < kHInf) {
+            const bool act = e[j] > 0 && h[j] < kHInf;
+            if (act) {
                 if (rt[j] > 0) {
                     const int d = e[j] < rt[j] ? e[j] : rt[j];
                     e[j] -= d;
@@ -279,17 +297,20 @@ __device__ void sweep_tile(const StepParams &P, const InstDesc &D, InstState *S,
                             const int d = e[j] < r[j][k] ? e[j] : r[j][k];
                             e[j] -= d;
                             r[j][k] -= d;
-                            const int nx = lx + DXk(k), ny = ly + DYk(k);
-                            if (nx >= 0 && nx < TW && ny >= 0 && ny < TH)
-                                o[k] = d;
-                            else
-                                hacc[j][k] += d;
+                            o[k] = d;
                         }
                     }
                 }
             }
 #pragma unroll
-            for (int k = 0; k < K; ++k) sh_out[k * (TW * TH) + ly * TW + lx] = o[k];
+            for (int k = 0; k < K; ++k) {
+                const int nx = lx + DXk(k), ny = ly + DYk(k);
+                int32_t *slot = &sh_out[k * (TW * TH) + ly * TW + lx];
+                if (nx >= 0 && nx < TW && ny >= 0 && ny < TH)
+                    *slot = o[k];  // consumed by the neighbour's gather below
+                else if (o[k])
+                    *slot += o[k];  // handed to the neighbour tile after the visit
+            }
         }
         __syncthreads();
         // gather pushes from in-tile neighbours, then relabel stuck pixels
@@ -340,10 +361,12 @@ __device__ void sweep_tile(const StepParams &P, const InstDesc &D, InstState *S,
         for (int k = 0; k < K; ++k) {
             D.r[(size_t)k * n + p] = r[j][k];
             if (r[j][k] > 0) rm |= 1 << k;
-            if (hacc[j][k] > 0) {
+            const int nx = lx + DXk(k), ny = ly + DYk(k);
+            if (nx >= 0 && nx < TW && ny >= 0 && ny < TH) continue;
+            const int v = sh_out[k * (TW * TH) + ly * TW + lx];
+            if (v > 0) {
                 const int q = (gy + DYk(k)) * W + gx + DXk(k);
-                atomicAdd(&D.inbox[(size_t)(k ^ 1) * n + q], hacc[j][k]);
-                const int nx = lx + DXk(k), ny = ly + DYk(k);
+                atomicAdd(&D.inbox[(size_t)(k ^ 1) * n + q], v);
                 const int dtx = nx < 0 ? 0 : (nx >= TW ? 2 : 1);
                 const int dty = ny < 0 ? 0 : (ny >= TH ? 2 : 1);
                 s_nb[dty * 3 + dtx] = 1;
@@ -359,21 +382,20 @@ __device__ void sweep_tile(const StepParams &P, const InstDesc &D, InstState *S,
     if (tid < 9 && tid != 4 && s_nb[tid]) {
         const int ntx = tx + (tid % 3) - 1, nty = ty + (tid / 3) - 1;
         if (ntx >= 0 && ntx < D.tiles_x && nty >= 0 && nty < D.tiles_y)
-            atomicOr(&P.tile_act[D.tile0 + nty * D.tiles_x + ntx], 2u);
+            atomicOr(&D.tile_act[nty * D.tiles_x + ntx], 2u);
     }
     if (tid == 0) {
         if (tile_active)
-            atomicOr(&P.tile_act[tg], 1u);
+            atomicOr(&D.tile_act[tl], 1u);
         else
-            atomicAnd(&P.tile_act[tg], ~1u);
+            atomicAnd(&D.tile_act[tl], ~1u);
+        count_px(&S->px_sweep, tile_pixels<TW, TH>(W, H, x0, y0));
     }
-    (void)S;
 }
 
 // Whether this tile or one of its neighbours changed a label in the previous pass.
-__device__ __forceinline__ bool frontier_needs(const StepParams &P, const InstDesc &D, int tx, int ty,
-                                               int prev) {
-    const uint8_t *chg = P.tile_chg + (size_t)prev * P.ntiles;
+__device__ __forceinline__ bool frontier_needs(const InstDesc &D, int tx, int ty, int prev) {
+    const uint8_t *chg = D.tile_chg + (size_t)prev * D.ntiles;
     bool need = false;
 #pragma unroll
     for (int dy = -1; dy <= 1; ++dy)
@@ -381,7 +403,7 @@ __device__ __forceinline__ bool frontier_needs(const StepParams &P, const InstDe
         for (int dx = -1; dx <= 1; ++dx) {
             const int ntx = tx + dx, nty = ty + dy;
             if (ntx >= 0 && ntx < D.tiles_x && nty >= 0 && nty < D.tiles_y)
-                need |= chg[D.tile0 + nty * D.tiles_x + ntx] != 0;
+                need |= chg[nty * D.tiles_x + ntx] != 0;
         }
     return need;
 }
@@ -400,8 +422,8 @@ __device__ void relabel_tile(const StepParams &P, const InstDesc &D, InstState *
     const int W = D.W, H = D.H, n = D.n;
     const bool first = sub == 0;
     const int cur = sub & 1, prev = cur ^ 1;
-    if (!first && !frontier_needs(P, D, tx, ty, prev)) {
-        if (tid == 0) P.tile_chg[(size_t)cur * P.ntiles + tg] = 0;
+    if (!first && !frontier_needs(D, tx, ty, prev)) {
+        if (tid == 0) D.tile_chg[(size_t)cur * D.ntiles + tl] = 0;
         return;
     }
     int32_t *sh_d = lds;
@@ -496,12 +518,13 @@ __device__ void relabel_tile(const StepParams &P, const InstDesc &D, InstState *
     const int tchg = __syncthreads_or(changed);
     const int tcnt = block_sum_int(cnt, s_red);
     if (tid == 0) {
-        P.tile_chg[(size_t)cur * P.ntiles + tg] = (uint8_t)(tchg ? 1 : 0);
-        const int delta = first ? tcnt : tcnt - P.tile_cnt[tg];
-        P.tile_cnt[tg] = tcnt;
+        D.tile_chg[(size_t)cur * D.ntiles + tl] = (uint8_t)(tchg ? 1 : 0);
+        const int delta = first ? tcnt : tcnt - D.tile_cnt[tl];
+        D.tile_cnt[tl] = tcnt;
         if (delta) atomicAdd(&S->active, delta);
         if (tchg) atomicOr(&S->changed, 1);
-        P.tile_act[tg] = tcnt > 0 ? 1u : 0u;
+        D.tile_act[tl] = tcnt > 0 ? 1u : 0u;
+        count_px(&S->px_relabel, tile_pixels<TW, TH>(W, H, x0, y0));
     }
 }
 
@@ -521,8 +544,8 @@ __device__ void cut_tile(const StepParams &P, const InstDesc &D, InstState *S, i
     const int W = D.W, H = D.H, n = D.n;
     const bool first = sub == 0;
     const int cur = sub & 1, prev = cur ^ 1;
-    if (!first && !frontier_needs(P, D, tx, ty, prev)) {
-        if (tid == 0) P.tile_chg[(size_t)cur * P.ntiles + tg] = 0;
+    if (!first && !frontier_needs(D, tx, ty, prev)) {
+        if (tid == 0) D.tile_chg[(size_t)cur * D.ntiles + tl] = 0;
         return;
     }
     uint8_t *mask = D.masks + (size_t)kk * n;
@@ -613,9 +636,10 @@ __device__ void cut_tile(const StepParams &P, const InstDesc &D, InstState *S, i
     long long tse = 0;
     if (first) tse = block_sum_i64(se, s_sum);
     if (tid == 0) {
-        P.tile_chg[(size_t)cur * P.ntiles + tg] = (uint8_t)(tchg ? 1 : 0);
+        D.tile_chg[(size_t)cur * D.ntiles + tl] = (uint8_t)(tchg ? 1 : 0);
         if (tchg) atomicOr(&S->changed, 1);
         if (tse) atomicAdd((unsigned long long *)&S->sum_e, (unsigned long long)tse);
+        count_px(&S->px_cut, tile_pixels<TW, TH>(W, H, x0, y0));
     }
     (void)s_red;
 }
@@ -695,79 +719,105 @@ __device__ void control(const StepParams &P) {
             }
             if (D->status) *D->status = status;
             ph = kDone;
-            atomicAdd(P.ndone, 1);
+            const int at = atomicAdd(P.ring_count, 1);
+            P.ring[at % P.ring_cap] = i;
         }
         S->phase = ph;
     }
 }
 
-template <int TW, int TH>
-__global__ __launch_bounds__(kThreads) void k_superstep(StepParams P) {
-    __shared__ int32_t lds[((TW + 2) * (TH + 2) + 3) / 4 * 4 + 8 * TW * TH];
-    __shared__ int s_red[4];
-    __shared__ unsigned long long s_sum;
-    __shared__ int s_last;
-    // XCD-aware mapping: consecutive tiles (neighbours in one image) land on
-    // the same XCD, whose L2 then holds their shared halos.
-    const int b = blockIdx.x;
-    const int t = (b & 7) * P.per_xcd + (b >> 3);
-    if (t < P.ntiles) {
-        const int slot = P.tile_slot[t];
-        const int tl = P.tile_local[t];
-        InstState *S = &P.st[slot];
-        const int phase = S->phase;
-        if (phase != kIdle && phase != kDone) {
-            const InstDesc D = P.desc[slot];
-            if (tl < D.ntiles) {
-                const int sub = S->sub, kk = S->k;
-                if (D.K == 4) {
-                    switch (phase) {
-                        case kInit: init_tile<4, TW, TH>(P, D, S, t, tl, s_red, &s_sum); break;
-                        case kRelabel: relabel_tile<4, TW, TH>(P, D, S, t, tl, sub, lds, s_red); break;
-                        case kSweep: sweep_tile<4, TW, TH>(P, D, S, t, tl, lds, s_red); break;
-                        case kCut: cut_tile<4, TW, TH>(P, D, S, t, tl, sub, kk, lds, s_red, &s_sum); break;
-                    }
-                } else {
-                    switch (phase) {
-                        case kInit: init_tile<8, TW, TH>(P, D, S, t, tl, s_red, &s_sum); break;
-                        case kRelabel: relabel_tile<8, TW, TH>(P, D, S, t, tl, sub, lds, s_red); break;
-                        case kSweep: sweep_tile<8, TW, TH>(P, D, S, t, tl, lds, s_red); break;
-                        case kCut: cut_tile<8, TW, TH>(P, D, S, t, tl, sub, kk, lds, s_red, &s_sum); break;
-                    }
-                }
-            }
-        }
-    }
-    // last-workgroup pattern: the final arrival runs the phase machine
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        __threadfence();
-        const unsigned prev = atomicAdd(P.arrive, 1u);
-        s_last = prev == gridDim.x - 1;
-    }
-    __syncthreads();
-    if (s_last) {
-        __threadfence();
-        control(P);
-        __threadfence();
-        __syncthreads();
-        if (threadIdx.x == 0) atomicExch(P.arrive, 0u);
-    }
+// Tile index of workgroup b inside a launch covering tiles [tbeg, tbeg + tcount):
+// consecutive tiles (neighbours in one image) land on the same XCD, whose L2
+// then holds the halos they share.  Returns -1 for padding workgroups.
+__device__ __forceinline__ int xcd_tile(int b, int tbeg, int tcount, int per_xcd) {
+    const int t = (b & 7) * per_xcd + (b >> 3);
+    return t < tcount ? tbeg + t : -1;
 }
 
-int launch_superstep(const StepParams &p, int tile_w, void *stream) {
-    const dim3 grid(8 * p.per_xcd), block(kThreads);
-    hipStream_t s = (hipStream_t)stream;
-    if (tile_w == 64)
-        hipLaunchKernelGGL((k_superstep<64, 16>), grid, block, 0, s, p);
+template <int K, int TW, int TH>
+__global__ __launch_bounds__(kThreads) void k_sweep(StepParams P, int tbeg, int tcount, int per_xcd) {
+    __shared__ int32_t lds[((TW + 2) * (TH + 2) + 3) / 4 * 4 + K * TW * TH];
+    __shared__ int s_red[4];
+    const int t = xcd_tile(blockIdx.x, tbeg, tcount, per_xcd);
+    if (t < 0) return;
+    const int slot = P.tile_slot[t];
+    InstState *S = &P.st[slot];
+    if (S->phase != kSweep) return;
+    const InstDesc D = P.desc[slot];
+    const int tl = P.tile_local[t];
+    if (tl >= D.ntiles) return;
+    sweep_tile<K, TW, TH>(P, D, S, t, tl, lds, s_red);
+}
+
+template <int K, int TW, int TH>
+__global__ __launch_bounds__(kThreads) void k_bfs(StepParams P, int tbeg, int tcount, int per_xcd) {
+    __shared__ int32_t lds[2 * (TW + 2) * (TH + 2)];
+    __shared__ int s_red[4];
+    __shared__ unsigned long long s_sum;
+    const int t = xcd_tile(blockIdx.x, tbeg, tcount, per_xcd);
+    if (t < 0) return;
+    const int slot = P.tile_slot[t];
+    InstState *S = &P.st[slot];
+    const int phase = S->phase;
+    if (phase != kInit && phase != kRelabel && phase != kCut) return;
+    const InstDesc D = P.desc[slot];
+    const int tl = P.tile_local[t];
+    if (tl >= D.ntiles) return;
+    const int sub = S->sub, kk = S->k;
+    if (phase == kInit)
+        init_tile<K, TW, TH>(P, D, S, t, tl, s_red, &s_sum);
+    else if (phase == kRelabel)
+        relabel_tile<K, TW, TH>(P, D, S, t, tl, sub, lds, s_red);
     else
-        hipLaunchKernelGGL((k_superstep<32, 32>), grid, block, 0, s, p);
+        cut_tile<K, TW, TH>(P, D, S, t, tl, sub, kk, lds, s_red, &s_sum);
+}
+
+__global__ __launch_bounds__(kThreads) void k_control(StepParams P) { control(P); }
+
+// Nested masks to one byte per pixel: the number of lambdas whose minimal
+// source side holds the pixel (the sets shrink as lambda grows, so mask k is
+// level > k).
+__global__ __launch_bounds__(kThreads) void k_levels(const uint8_t *masks, int L, int n, uint8_t *out) {
+    const int p = blockIdx.x * kThreads + threadIdx.x;
+    if (p >= n) return;
+    int c = 0;
+    for (int k = 0; k < L; ++k) c += masks[(size_t)k * n + p];
+    out[p] = (uint8_t)c;
+}
+
+int launch_levels(const uint8_t *masks, int L, int n, uint8_t *out, void *stream) {
+    hipLaunchKernelGGL(k_levels, dim3((n + kThreads - 1) / kThreads), dim3(kThreads), 0, (hipStream_t)stream,
+                       masks, L, n, out);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
-int max_lds_bytes(int tile_w) {
-    (void)tile_w;
-    return (int)sizeof(int32_t) * ((66 * 18 + 3) / 4 * 4 + 8 * 1024);
+template <int TW, int TH>
+static int launch_tw(const StepParams &p, hipStream_t s, void *const *ev) {
+    const dim3 block(kThreads);
+    const int pc4 = (p.t4_count + 7) / 8, pc8 = (p.t8_count + 7) / 8;
+    int sweeps = 0;
+    if (ev) (void)hipEventRecord((hipEvent_t)ev[0], s);
+    if (p.t4_count) {
+        hipLaunchKernelGGL((k_sweep<4, TW, TH>), dim3(8 * pc4), block, 0, s, p, p.t4_begin, p.t4_count, pc4);
+        ++sweeps;
+    }
+    if (p.t8_count) {
+        hipLaunchKernelGGL((k_sweep<8, TW, TH>), dim3(8 * pc8), block, 0, s, p, p.t8_begin, p.t8_count, pc8);
+        ++sweeps;
+    }
+    if (ev) (void)hipEventRecord((hipEvent_t)ev[1], s);
+    if (p.t4_count) hipLaunchKernelGGL((k_bfs<4, TW, TH>), dim3(8 * pc4), block, 0, s, p, p.t4_begin, p.t4_count, pc4);
+    if (p.t8_count) hipLaunchKernelGGL((k_bfs<8, TW, TH>), dim3(8 * pc8), block, 0, s, p, p.t8_begin, p.t8_count, pc8);
+    if (ev) (void)hipEventRecord((hipEvent_t)ev[2], s);
+    hipLaunchKernelGGL(k_control, dim3(1), block, 0, s, p);
+    if (ev) (void)hipEventRecord((hipEvent_t)ev[3], s);
+    return sweeps;
+}
+
+int launch_superstep(const StepParams &p, int tile_w, void *stream, void *const *events) {
+    hipStream_t s = (hipStream_t)stream;
+    const int n = tile_w == 64 ? launch_tw<64, 16>(p, s, events) : launch_tw<32, 32>(p, s, events);
+    return hipGetLastError() == hipSuccess ? n : -1;
 }
 
 }  // namespace pmf

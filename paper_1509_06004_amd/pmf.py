@@ -45,7 +45,8 @@ class Options(ctypes.Structure):
         ("order", ctypes.c_int32),
         ("mem_budget", ctypes.c_int64),
         ("max_slots", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 7),
+        ("timing", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 6),
     ]
 
 
@@ -64,6 +65,17 @@ class InstanceC(ctypes.Structure):
     ]
 
 
+class SessionInfo(ctypes.Structure):
+    _fields_ = [
+        ("free_bytes", ctypes.c_int64),
+        ("largest_free", ctypes.c_int64),
+        ("free_slots", ctypes.c_int32),
+        ("admitted", ctypes.c_int32),
+        ("running", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+    ]
+
+
 class Stats(ctypes.Structure):
     _fields_ = [
         ("supersteps", ctypes.c_int64),
@@ -72,6 +84,15 @@ class Stats(ctypes.Structure):
         ("bfs_passes", ctypes.c_int64),
         ("host_syncs", ctypes.c_int64),
         ("device_bytes", ctypes.c_int64),
+        ("device_ns", ctypes.c_int64),
+        ("px_init", ctypes.c_int64),
+        ("px_sweep", ctypes.c_int64),
+        ("px_relabel", ctypes.c_int64),
+        ("px_cut", ctypes.c_int64),
+        ("sweep_ns", ctypes.c_int64),
+        ("bfs_ns", ctypes.c_int64),
+        ("control_ns", ctypes.c_int64),
+        ("sweep_launches", ctypes.c_int64),
     ]
 
 
@@ -100,6 +121,14 @@ def load_library() -> ctypes.CDLL:
         "pmf_check_instances": (ctypes.c_int, [ctypes.POINTER(InstanceC), ctypes.c_int32,
                                                ctypes.POINTER(ctypes.c_int32)]),
         "pmf_get_stats": (ctypes.c_int, [P, ctypes.POINTER(Stats)]),
+        "pmf_extract_levels": (ctypes.c_int, [P, ctypes.c_int32, P]),
+        "pmf_session_open": (ctypes.c_int, [P, ctypes.c_int32, ctypes.c_size_t]),
+        "pmf_session_submit": (ctypes.c_int, [P, ctypes.POINTER(InstanceC), ctypes.c_int32, P, P,
+                                              ctypes.POINTER(ctypes.c_int32)]),
+        "pmf_session_step": (ctypes.c_int, [P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
+                                            ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]),
+        "pmf_session_release": (ctypes.c_int, [P, ctypes.c_int32]),
+        "pmf_session_query": (ctypes.c_int, [P, ctypes.POINTER(SessionInfo)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -144,6 +173,10 @@ def pmf_extract_cut(handle, inst: int, lambda_idx: int, mask_ptr: int) -> int:
     return load_library().pmf_extract_cut(handle, int(inst), int(lambda_idx), ctypes.c_void_p(mask_ptr))
 
 
+def pmf_extract_levels(handle, inst: int, levels_ptr: int) -> int:
+    return load_library().pmf_extract_levels(handle, int(inst), ctypes.c_void_p(levels_ptr))
+
+
 def pmf_destroy(handle) -> int:
     return load_library().pmf_destroy(handle)
 
@@ -174,6 +207,39 @@ def pmf_get_stats(handle) -> Dict[str, int]:
     return {f: int(getattr(s, f)) for f, _ in Stats._fields_}
 
 
+def pmf_session_open(handle, max_slots: int, pool_bytes: int = 0) -> int:
+    return load_library().pmf_session_open(handle, int(max_slots), ctypes.c_size_t(pool_bytes))
+
+
+def pmf_session_submit(handle, instances: Sequence[InstanceC], flows_ptr: int, status_ptr: int):
+    """Returns (code, ids)."""
+    arr = (InstanceC * len(instances))(*instances)
+    ids = (ctypes.c_int32 * max(len(instances), 1))()
+    rc = load_library().pmf_session_submit(handle, arr, len(instances), ctypes.c_void_p(flows_ptr),
+                                           ctypes.c_void_p(status_ptr), ids)
+    return rc, [int(ids[i]) for i in range(len(instances))] if rc == PMF_OK else []
+
+
+def pmf_session_step(handle, supersteps: int, max_ids: int = 4096):
+    """Returns (code, finished ids)."""
+    buf = (ctypes.c_int32 * max_ids)()
+    n = ctypes.c_int32(0)
+    rc = load_library().pmf_session_step(handle, int(supersteps), buf, max_ids, ctypes.byref(n))
+    return rc, [int(buf[i]) for i in range(min(n.value, max_ids))]
+
+
+def pmf_session_release(handle, ident: int) -> int:
+    return load_library().pmf_session_release(handle, int(ident))
+
+
+def pmf_session_query(handle) -> Dict[str, int]:
+    info = SessionInfo()
+    rc = load_library().pmf_session_query(handle, ctypes.byref(info))
+    if rc != PMF_OK:
+        raise PmfError(rc, "pmf_session_query")
+    return {f: int(getattr(info, f)) for f, _ in SessionInfo._fields_ if f != "reserved"}
+
+
 # ---------------------------------------------------------------------------
 # Device-resident instances (torch tensors) and a convenience solver.
 # ---------------------------------------------------------------------------
@@ -194,19 +260,30 @@ class DeviceInstance:
                          ptr(self.cap_snk0), ptr(self.snk_slope), ptr(self.seed), ptr(self.lambdas))
 
 
-def to_device(insts, device="cuda", share: Optional[Dict[int, torch.Tensor]] = None) -> List[DeviceInstance]:
+def to_device(insts, device="cuda", share: Optional[Dict[int, torch.Tensor]] = None,
+              non_blocking: bool = False) -> List[DeviceInstance]:
     """Upload host instances (objects with the fields of ``workload.Instance``).
-    Instances whose ``nlink`` is the same numpy array share one device copy."""
+    Arrays that are the same numpy object (n-links of one image, shared
+    constant planes) get one device copy."""
     share = {} if share is None else share
+    keep = []  # the numpy objects behind the keys must outlive this call
+
+    def up(a, dt):
+        key = id(a)
+        if key not in share:
+            c = np.ascontiguousarray(a, dtype=dt)
+            h = torch.from_numpy(c if c.flags.writeable else c.copy())
+            if non_blocking:
+                h = h.pin_memory()
+            share[key] = h.to(device, non_blocking=non_blocking)
+            keep.append(a)
+        return share[key]
+
     out = []
     for inst in insts:
-        key = id(inst.nlink)
-        if key not in share:
-            share[key] = torch.from_numpy(np.ascontiguousarray(inst.nlink, dtype=np.int32)).to(device)
-        t = lambda a, dt: torch.from_numpy(np.ascontiguousarray(a, dtype=dt)).to(device)
-        out.append(DeviceInstance(inst.W, inst.H, inst.K, share[key], t(inst.cap_src, np.int32),
-                                  t(inst.cap_snk0, np.int32), t(inst.snk_slope, np.int32),
-                                  t(inst.seed, np.uint8), t(inst.lambdas, np.int32)))
+        out.append(DeviceInstance(inst.W, inst.H, inst.K, up(inst.nlink, np.int32), up(inst.cap_src, np.int32),
+                                  up(inst.cap_snk0, np.int32), up(inst.snk_slope, np.int32),
+                                  up(inst.seed, np.uint8), up(inst.lambdas, np.int32)))
     return out
 
 

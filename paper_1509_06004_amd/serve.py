@@ -1,0 +1,311 @@
+"""Continuous-batching serving loop over one resident libpmf session.
+
+Requests (one image with several seeds, each with its own lambda schedule)
+arrive at scheduled times.  The server keeps a FIFO of arrived requests and
+admits them, whole, while the backend has free instance slots and pool memory
+(admission by free memory) and the work in flight stays under a bound.
+Admitted requests join the running launches at the next superstep, so work of
+different requests overlaps on the device; a request completes when all its
+instances have finished, and its results (flow values and one nested-level
+byte per pixel per seed) are then copied to the host.  Latency is measured from
+the scheduled arrival to the results being on the host.
+
+The scheduling mirrors the paper's dynamic scheduler (Sec. 3.3.1): work goes to
+free capacity in FIFO order as soon as capacity frees up, instead of a fixed
+static assignment; here the capacity is device slots and memory of one GPU.
+
+Backends share one interface, so the server logic is tested on the CPU with a
+fake backend and run on the GPU with :class:`PmfBackend`.
+"""
+
+from __future__ import annotations
+
+import dataclasses
+import time
+from collections import deque
+from typing import Dict, List, Optional, Sequence
+
+import numpy as np
+
+
+@dataclasses.dataclass
+class Result:
+    flows: np.ndarray   # int64 [L] per instance
+    levels: np.ndarray  # uint8 [H, W]: mask of lambda k is levels > k
+    status: int
+
+
+@dataclasses.dataclass
+class RequestRecord:
+    index: int
+    arrival: float
+    n_inst: int
+    solves: int
+    admitted: float = float("nan")
+    finished: float = float("nan")
+    failed: Optional[str] = None
+    results: Optional[List[Result]] = None
+
+    @property
+    def latency(self) -> float:
+        return self.finished - self.arrival
+
+
+class Backend:
+    """Interface of a solver backend (all times host wall-clock)."""
+
+    def bytes_needed(self, insts) -> int:
+        raise NotImplementedError
+
+    def free_bytes(self) -> int:
+        raise NotImplementedError
+
+    def capacity(self) -> int:
+        """Bytes of the whole pool: a request needing more can never run."""
+        raise NotImplementedError
+
+    def submit(self, insts) -> Optional[List[int]]:
+        """Admit all instances (ids) or none (None)."""
+        raise NotImplementedError
+
+    def step(self) -> List[int]:
+        """Advance the device; ids of instances that finished."""
+        raise NotImplementedError
+
+    def fetch(self, ids: Sequence[int]) -> List[Result]:
+        raise NotImplementedError
+
+    def release(self, ids: Sequence[int]) -> None:
+        raise NotImplementedError
+
+
+class PmfBackend(Backend):
+    """libpmf session on one GPU (inputs uploaded per request)."""
+
+    def __init__(self, max_slots: int = 4096, pool_bytes: int = 0, supersteps: int = 16, **options):
+        import torch
+        from . import pmf
+        self.torch, self.pmf = torch, pmf
+        opts = pmf.pmf_default_options()
+        for k, v in options.items():
+            setattr(opts, k, v)
+        self.stream = torch.cuda.current_stream()
+        self.handle = pmf.pmf_create(opts, int(self.stream.cuda_stream))
+        rc = pmf.pmf_session_open(self.handle, max_slots, pool_bytes)
+        if rc != pmf.PMF_OK:
+            raise pmf.PmfError(rc, "pmf_session_open")
+        self.options = opts
+        self.supersteps = supersteps
+        self.pool_bytes = pmf.pmf_session_query(self.handle)["free_bytes"]
+        self.live: Dict[int, tuple] = {}  # id -> (device inputs, flows view, status view, L, H, W)
+
+    def bytes_needed(self, insts) -> int:
+        return self.pmf.pmf_query_bytes([self._fake(i) for i in insts], self.options)
+
+    def _fake(self, i):
+        return self.pmf.InstanceC(i.W, i.H, i.K, i.L, 1, 1, 1, 0, 0, 1)
+
+    def free_bytes(self) -> int:
+        return self.pmf.pmf_session_query(self.handle)["largest_free"]
+
+    def capacity(self) -> int:
+        return self.pool_bytes
+
+    def submit(self, insts) -> Optional[List[int]]:
+        torch, pmf = self.torch, self.pmf
+        dev = pmf.to_device(insts)
+        total = sum(d.L for d in dev)
+        flows = torch.empty(total, dtype=torch.int64, device="cuda")
+        status = torch.empty(len(dev), dtype=torch.int32, device="cuda")
+        rc, ids = pmf.pmf_session_submit(self.handle, [d.c_struct() for d in dev], int(flows.data_ptr()),
+                                         int(status.data_ptr()))
+        if rc == pmf.PMF_EBUSY:
+            return None
+        if rc != pmf.PMF_OK:
+            raise pmf.PmfError(rc, "pmf_session_submit")
+        off = 0
+        for j, (d, i) in enumerate(zip(dev, ids)):
+            self.live[i] = (d, flows[off:off + d.L], status[j:j + 1], d.L, d.H, d.W, (flows, status))
+            off += d.L
+        return ids
+
+    def step(self) -> List[int]:
+        rc, done = self.pmf.pmf_session_step(self.handle, self.supersteps)
+        if rc != self.pmf.PMF_OK:
+            raise self.pmf.PmfError(rc, "pmf_session_step")
+        return done
+
+    def fetch(self, ids: Sequence[int]) -> List[Result]:
+        torch, pmf = self.torch, self.pmf
+        lv, fl, stv = [], [], []
+        for i in ids:
+            d, flows, status, L, H, W, _ = self.live[i]
+            out = torch.empty((H, W), dtype=torch.uint8, device="cuda")
+            rc = pmf.pmf_extract_levels(self.handle, i, int(out.data_ptr()))
+            if rc != pmf.PMF_OK:
+                raise pmf.PmfError(rc, "pmf_extract_levels")
+            lv.append(out)
+            fl.append(flows)
+            stv.append(status)
+        flows_h = [f.to("cpu", non_blocking=True) for f in fl]
+        levels_h = [x.to("cpu", non_blocking=True) for x in lv]
+        status_h = [s.to("cpu", non_blocking=True) for s in stv]
+        torch.cuda.current_stream().synchronize()
+        return [Result(f.numpy(), l.numpy(), int(s.item())) for f, l, s in zip(flows_h, levels_h, status_h)]
+
+    def release(self, ids: Sequence[int]) -> None:
+        for i in ids:
+            rc = self.pmf.pmf_session_release(self.handle, i)
+            if rc != self.pmf.PMF_OK:
+                raise self.pmf.PmfError(rc, "pmf_session_release")
+            self.live.pop(i, None)
+
+    def stats(self) -> Dict[str, int]:
+        return self.pmf.pmf_get_stats(self.handle)
+
+    def close(self):
+        if self.handle is not None:
+            self.pmf.pmf_destroy(self.handle)
+            self.handle = None
+
+
+@dataclasses.dataclass
+class ServeReport:
+    qps: float
+    offered: int
+    completed: int
+    failed: int
+    duration_s: float
+    solves: int
+    solves_per_s: float
+    p50_ms: float
+    p99_ms: float
+    censored: int
+    max_queue: int
+    records: List[RequestRecord]
+
+    def summary(self) -> dict:
+        return {"qps": self.qps, "offered_requests": self.offered, "completed_requests": self.completed,
+                "failed_requests": self.failed, "duration_s": round(self.duration_s, 3),
+                "solves": self.solves, "solves_per_s": round(self.solves_per_s, 2),
+                "latency_ms": {"p50": round(self.p50_ms, 2), "p99": round(self.p99_ms, 2)},
+                "unfinished_at_end": self.censored, "max_queue": self.max_queue}
+
+
+class Server:
+    """FIFO admission by free memory, continuous batching, latency accounting."""
+
+    def __init__(self, backend: Backend, max_inflight_instances: int = 1 << 30, keep_results: bool = False,
+                 clock=time.perf_counter, sleep=time.sleep):
+        self.backend = backend
+        self.max_inflight = max_inflight_instances
+        self.keep_results = keep_results
+        self.clock = clock
+        self.sleep = sleep
+
+    def run(self, arrivals: Sequence[float], make_request, duration_s: float, warmup_s: float = 0.0,
+            qps: float = 0.0, drain: bool = False) -> ServeReport:
+        """Serve requests arriving at `arrivals` (seconds from the start);
+        `make_request(i)` returns the host instances of request i.  Requests
+        arriving in [warmup_s, warmup_s + duration_s) are measured; the run
+        stops at warmup_s + duration_s (or when everything is done, with
+        `drain`)."""
+        be = self.backend
+        t0 = self.clock()
+        end = warmup_s + duration_s
+        pending: deque = deque()
+        inflight: Dict[int, RequestRecord] = {}  # instance id -> record
+        left: Dict[int, int] = {}                # record index -> unfinished instances
+        ids_of: Dict[int, List[int]] = {}
+        records: List[RequestRecord] = []
+        nxt = 0
+        n_inflight = 0
+        max_queue = 0
+        while True:
+            now = self.clock() - t0
+            while nxt < len(arrivals) and arrivals[nxt] <= now and arrivals[nxt] < end:
+                insts = make_request(nxt)
+                rec = RequestRecord(index=nxt, arrival=arrivals[nxt], n_inst=len(insts),
+                                    solves=sum(i.L for i in insts))
+                records.append(rec)
+                pending.append((rec, insts))
+                nxt += 1
+            max_queue = max(max_queue, len(pending))
+            # admission: whole requests, FIFO, while memory, slots and the bound allow
+            while pending and (n_inflight == 0 or n_inflight + pending[0][0].n_inst <= self.max_inflight):
+                rec, insts = pending[0]
+                if be.bytes_needed(insts) > be.capacity():
+                    pending.popleft()
+                    rec.failed = "request larger than the whole pool"
+                    rec.finished = self.clock() - t0
+                    continue
+                try:
+                    ids = be.submit(insts)
+                except Exception as exc:  # a failed request must not stop the others
+                    pending.popleft()
+                    rec.failed = repr(exc)
+                    rec.finished = self.clock() - t0
+                    continue
+                if ids is None:
+                    break
+                pending.popleft()
+                rec.admitted = self.clock() - t0
+                ids_of[rec.index] = ids
+                left[rec.index] = len(ids)
+                for i in ids:
+                    inflight[i] = rec
+                n_inflight += len(ids)
+            now = self.clock() - t0
+            if now >= end and not drain:
+                break
+            if not inflight:
+                if nxt >= len(arrivals) and not pending:
+                    break
+                if not pending and nxt < len(arrivals):
+                    self.sleep(max(0.0, min(arrivals[nxt] - now, 0.002)))
+                continue
+            try:
+                done = be.step()
+            except Exception as exc:
+                # the device step failed: fail every request in flight
+                for i, rec in list(inflight.items()):
+                    rec.failed = repr(exc)
+                    rec.finished = self.clock() - t0
+                inflight.clear()
+                left.clear()
+                n_inflight = 0
+                continue
+            finished_recs = []
+            for i in done:
+                rec = inflight.pop(i, None)
+                if rec is None:
+                    continue
+                left[rec.index] -= 1
+                if left[rec.index] == 0:
+                    finished_recs.append(rec)
+            for rec in finished_recs:
+                ids = ids_of.pop(rec.index)
+                res = be.fetch(ids)
+                rec.finished = self.clock() - t0
+                if self.keep_results:
+                    rec.results = res
+                be.release(ids)
+                n_inflight -= len(ids)
+                del left[rec.index]
+        dur = self.clock() - t0
+        window = [r for r in records if warmup_s <= r.arrival < end]
+        ok = [r for r in window if r.failed is None and np.isfinite(r.finished)]
+        # requests still unfinished at the end count with (end of run - arrival),
+        # a lower bound of their latency, so that overload shows in p50/p99
+        open_ = [r for r in window if r.failed is None and not np.isfinite(r.finished)]
+        lat_list = [r.latency for r in ok] + [dur - r.arrival for r in open_]
+        lat = np.array(lat_list) * 1e3 if lat_list else np.array([float("nan")])
+        # throughput counts the solves of every instance that finished in the
+        # measured window (finished requests only)
+        measured_solves = sum(r.solves for r in ok)
+        span = max(min(dur, end) - warmup_s, 1e-9) if not drain else max(dur - warmup_s, 1e-9)
+        return ServeReport(qps=qps, offered=len(window), completed=len(ok),
+                           failed=sum(r.failed is not None for r in window), duration_s=dur,
+                           solves=measured_solves, solves_per_s=measured_solves / span,
+                           p50_ms=float(np.percentile(lat, 50)), p99_ms=float(np.percentile(lat, 99)),
+                           censored=len(open_), max_queue=max_queue, records=records)

@@ -120,6 +120,19 @@ def border_mask(W: int, H: int) -> np.ndarray:
     return m
 
 
+_CONST = {}
+
+
+def const_plane(H: int, W: int, value: int) -> np.ndarray:
+    """Read-only int32 plane shared by every instance of that shape."""
+    key = (H, W, value)
+    if key not in _CONST:
+        a = np.full((H, W), value, dtype=np.int32)
+        a.flags.writeable = False
+        _CONST[key] = a
+    return _CONST[key]
+
+
 def seed_instance(img: np.ndarray, nl: np.ndarray, K: int, cx: int, cy: int, side: int,
                   lambdas: Sequence[int], image: int = 0, src_scale: float = 200.0) -> Instance:
     """Foreground seed = side x side square centred at (cx, cy); background seed
@@ -137,10 +150,10 @@ def seed_instance(img: np.ndarray, nl: np.ndarray, K: int, cx: int, cy: int, sid
     cap_src = np.rint(src_scale * (1.0 - np.abs(img - iseed))).astype(np.int32)
     free = seed == 0
     cap_src = np.where(free, cap_src, 0).astype(np.int32)
-    cap_snk0 = np.zeros((H, W), dtype=np.int32)
-    slope = free.astype(np.int32)
-    return Instance(W=W, H=H, K=K, nlink=nl, cap_src=cap_src, cap_snk0=cap_snk0,
-                    snk_slope=slope, seed=seed,
+    # sink capacity lambda for free pixels; seeds ignore these two planes, so
+    # every instance of the image shares them
+    return Instance(W=W, H=H, K=K, nlink=nl, cap_src=cap_src, cap_snk0=const_plane(H, W, 0),
+                    snk_slope=const_plane(H, W, 1), seed=seed,
                     lambdas=np.ascontiguousarray(lambdas, dtype=np.int32), image=image)
 
 
@@ -231,31 +244,25 @@ def config3(images: int = 256, wmax: int = 640, hmax: int = 480) -> List[Instanc
     return out
 
 
-@dataclasses.dataclass
-class Request:
-    arrival_s: float
-    instances: List[Instance]
+def config4_stream(qps: float, seconds: float, warmup_s: float = 0.0, templates: int = 24):
+    """Serving workload: Poisson arrivals at `qps` over warmup_s + seconds; each
+    request is one image (W in 128..640, H in 96..480, K by coin flip, 8..48
+    regions) with 1..32 seeds, each with its own 10..30-point schedule in
+    [1, 5000].  Requests are drawn from a pool of `templates` generated images
+    (drawing a fresh 640x480 image per request would take longer than serving
+    it); arrival times and template choice are seeded by the QPS.
 
-
-def config4_requests(qps: float, seconds: float, warmup_s: float = 0.0,
-                     max_requests: Optional[int] = None) -> List[Request]:
-    """Poisson stream at ``qps``: each request is one image (128x96 .. 640x480)
-    with 1..32 seeds and a 10..30-point lambda schedule."""
-    rng = np.random.default_rng([MASTER_SEED, 4, int(qps)])
-    t = 0.0
-    out: List[Request] = []
-    i = 0
+    Returns (arrival times [n], template index [n], template list)."""
+    rng = np.random.default_rng([MASTER_SEED, 4, int(round(qps))])
+    t, arr = 0.0, []
     while True:
         t += float(rng.exponential(1.0 / qps))
-        if t > warmup_s + seconds:
+        if t >= warmup_s + seconds:
             break
-        img_rng = np.random.default_rng([MASTER_SEED, 4, int(qps), i])
-        out.append(Request(arrival_s=t, instances=random_image_instances(
-            img_rng, i, 128, 640, 96, 480, 32)))
-        i += 1
-        if max_requests is not None and i >= max_requests:
-            break
-    return out
+        arr.append(t)
+    pick = rng.integers(0, templates, size=len(arr))
+    pool = [random_image_instances(rng_for(4, 1000 + i), i, 128, 640, 96, 480, 32) for i in range(templates)]
+    return np.array(arr, dtype=np.float64), pick, pool
 
 
 def tiny_random(rng: np.random.Generator, W: int, H: int, K: int, cmax: int = 20,
