@@ -96,6 +96,25 @@ def cpu_baseline(insts, n_sample: int, threads: int):
     return pairs, res, wall
 
 
+def run_serving(qps: float, seconds: float, warmup: float, templates: int, inflight: int, log) -> dict:
+    """The serving workload: Poisson requests (one image, 1..32 seeds, 10..30
+    lambdas each) served by the continuous-batching loop on one session."""
+    from paper_1509_06004_amd import workload
+    from paper_1509_06004_amd.serve import PmfBackend, Server
+    arrivals, pick, pool = workload.config4_stream(qps, seconds, warmup, templates=templates)
+    be = PmfBackend(max_slots=4096, supersteps=16)
+    srv = Server(be, max_inflight_instances=inflight)
+    rep = srv.run(arrivals, lambda i: pool[pick[i]], duration_s=seconds, warmup_s=warmup, qps=qps)
+    be.close()
+    out = rep.summary()
+    out["workload"] = ("Poisson arrivals; request = one synthetic image 128x96..640x480 (K 4 or 8) with "
+                       "1..32 seeds x 10..30 lambdas in [1, 5000], drawn from %d generated images" % templates)
+    out["max_inflight_instances"] = inflight
+    out["warmup_s"] = warmup
+    log("serving qps %g: %s" % (qps, json.dumps({k: v for k, v in out.items() if k != "workload"})))
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -112,6 +131,16 @@ def main():
     ap.add_argument("--no-8conn", action="store_true")
     ap.add_argument("--no-verify", action="store_true")
     ap.add_argument("--no-roofline", action="store_true")
+    ap.add_argument("--serve-qps", type=float, default=50.0)
+    ap.add_argument("--serve-seconds", type=float, default=8.0)
+    ap.add_argument("--serve-warmup", type=float, default=2.0)
+    ap.add_argument("--serve-templates", type=int, default=12)
+    ap.add_argument("--serve-inflight", type=int, default=96)
+    ap.add_argument("--serve-full", action="store_true",
+                    help="serving sweep at 50, 200 and 800 requests/s, 60 s each after 5 s warm-up")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="finish with one 1 GiB device-to-device copy (counter calibration)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -179,8 +208,17 @@ def main():
     achieved = per_launch_bytes / avg_launch_s / 1e9
     bfs_bytes = ts["px_relabel"] * bpx["relabel"] + ts["px_cut"] * bpx["cut"] + ts["px_init"] * bpx["init"]
     tw = solver.options.tile_w
+    # HBM bytes per launch from the committed counter summary, while it still
+    # describes the current kernel source
+    from paper_1509_06004_amd import rocprof_summary
+    prof = rocprof_summary.read_summary(os.path.join(ROOT, "profiles", "k_sweep_500x375_4conn_traffic.txt"))
+    traffic = None
+    if (prof.get("kernel_source_sha256") == rocprof_summary.source_hash()
+            and "traffic_bytes_per_launch" in prof and "k_sweep<4,%d,%d>" % (solver.options.tile_w, 1024 // solver.options.tile_w)
+            in prof.get("traffic_kernel", "").replace(" ", "")):
+        traffic = float(prof["traffic_bytes_per_launch"])
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
             "kernel": "k_sweep<4, %d, %d>" % (tw, 1024 // tw), "avg_launch_us": round(avg_launch_s * 1e6, 2),
             "alg_bytes_per_launch": int(per_launch_bytes), "launches": int(n_sweep),
             "bytes_per_px": bpx,
@@ -243,6 +281,18 @@ def main():
         del dev8
         log("8-conn %.1f solves/s" % (n_solves / t8))
 
+    if not args.no_serve:
+        if args.serve_full:
+            out["serving"] = [run_serving(q, 60.0, 5.0, 24, args.serve_inflight, log) for q in (50.0, 200.0, 800.0)]
+        else:
+            out["serving"] = run_serving(args.serve_qps, args.serve_seconds, args.serve_warmup,
+                                         args.serve_templates, args.serve_inflight, log)
+        sv = out["serving"] if isinstance(out["serving"], dict) else out["serving"][0]
+        out["latency_ms"] = dict(sv["latency_ms"], what="serving: scheduled arrival to results on host, "
+                                                         "%g requests/s" % sv["qps"])
+        out["latency_ms_batched_step"] = {"p50": round(float(np.percentile(times, 50)) * 1e3, 2),
+                                          "p99": round(float(np.percentile(times, 99)) * 1e3, 2)}
+
     if not args.no_cpu:
         threads = min(os.cpu_count() or 1, 16)
         pairs, res, wall = cpu_baseline(insts, args.cpu_sample, threads)
@@ -259,6 +309,11 @@ def main():
             if bad or cert:
                 print(json.dumps(out))
                 raise SystemExit("verification failed")
+    if args.calib_copy:
+        src = torch.empty(1 << 28, dtype=torch.int32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
     print(json.dumps(out), flush=True)
 
 

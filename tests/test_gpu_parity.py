@@ -38,9 +38,13 @@ def solve(pmf, insts, **opts):
     flows, status = s.solve(dev)
     torch.cuda.synchronize()
     masks = []
+    st = status.cpu().numpy()
     for i, inst in enumerate(insts):
+        if st[i] != 0:  # no masks for an instance that failed validation
+            masks.append(None)
+            continue
         masks.append(np.stack([s.extract_cut(i, k).cpu().numpy().astype(bool) for k in range(inst.L)]))
-    out = (flows.cpu().numpy(), status.cpu().numpy(), masks, s.stats())
+    out = (flows.cpu().numpy(), st, masks, s.stats())
     s.close()
     return out
 
@@ -119,3 +123,103 @@ def test_config1_warm_chain(pmf):
     flows, status, masks, st = solve(pmf, insts)
     say("stats", st)
     check_against_oracle(insts, flows, status, masks)
+
+
+def test_options_do_not_change_results(pmf):
+    """Tile shape, inner iterations, relabel period, packing order, graph replay:
+    speed knobs only; results are identical."""
+    rng = np.random.default_rng(29)
+    insts = [W.tiny_random(rng, 90, 70, 4, cmax=300, L=4, p_seed=0.02, lam_max=100),
+             W.tiny_random(rng, 61, 83, 8, cmax=300, L=3, p_seed=0.02, lam_max=100)]
+    ref = None
+    for opts in [dict(), dict(tile_w=64, tile_h=16), dict(inner_iters=1, sweeps_per_relabel=1),
+                 dict(inner_iters=64, sweeps_per_relabel=32, local_bfs_iters=4), dict(order=0),
+                 dict(use_graph=0, steps_per_sync=3), dict(timing=1)]:
+        say("options", opts)
+        flows, status, masks, _ = solve(pmf, insts, **opts)
+        assert (status == 0).all()
+        got = (flows, [m.copy() for m in masks])
+        if ref is None:
+            ref = got
+            check_against_oracle(insts, flows, status, masks)
+        else:
+            assert (got[0] == ref[0]).all()
+            assert all((a == b).all() for a, b in zip(got[1], ref[1]))
+
+
+def test_config2_full_size_sampled(pmf):
+    """The benchmark workload at full size (500x375, 4- and 8-connected, 25 seeds
+    x 20 lambdas, one batched call): oracle-exact on a sample of solves, and
+    every solve checked by the flow = cut-cost certificate and by nesting."""
+    for K in (4, 8):
+        insts = W.config2(K=K)
+        say("config2 full size K=%d" % K)
+        flows, status, masks, st = solve(pmf, insts)
+        say("stats", st)
+        fl = split(flows, insts)
+        assert (status == 0).all()
+        for i, inst in enumerate(insts):
+            for k in range(inst.L):
+                assert O.cut_cost_c(inst, int(inst.lambdas[k]), masks[i][k]) == fl[i][k]
+                if k:
+                    assert not (masks[i][k] & ~masks[i][k - 1]).any()
+        picks = [(0, 0), (7, 3), (12, 9), (18, 14), (24, 19)] if K == 4 else [(3, 1), (21, 8)]
+        for i, k in picks:
+            f, m = O.fifo_pr(insts[i], int(insts[i].lambdas[k]))
+            assert fl[i][k] == f and (masks[i][k] == m).all(), (K, i, k)
+
+
+def test_config3_uneven_subset(pmf):
+    """Uneven sizes and mixed connectivity in one call (images of the uneven
+    workload, shrunk so the oracle check stays short), bit-exact."""
+    insts = []
+    for img in range(6):
+        rng = W.rng_for(3, img)
+        insts.extend(W.random_image_instances(rng, img, 64, 200, 64, 160, 3))
+    say("config3-like subset", len(insts), sorted({(i.W, i.H, i.K) for i in insts}))
+    flows, status, masks, _ = solve(pmf, insts)
+    check_against_oracle(insts, flows, status, masks,
+                         lam_idx=lambda i, inst: sorted({0, inst.L // 2, inst.L - 1}))
+
+
+def test_invalid_capacities_report_status(pmf):
+    """Bad values are found on the device: that instance gets EINVAL/EOVERFLOW
+    and flows -1; the other instances of the batch are unaffected."""
+    rng = np.random.default_rng(31)
+    good = W.tiny_random(rng, 20, 15, 4, cmax=20, L=2)
+    neg = W.tiny_random(rng, 20, 15, 4, cmax=20, L=2)
+    neg.cap_src[3, 4] = -1
+    offgrid = W.tiny_random(rng, 20, 15, 4, cmax=20, L=2)
+    offgrid.nlink[0, 2, 19] = 5  # arc towards x = 20, off the grid
+    over = W.tiny_random(rng, 20, 15, 8, cmax=20, L=2)
+    over.nlink[1, 5, 5] = (1 << 30)  # beyond the int32 headroom for K = 8
+    sink = W.tiny_random(rng, 20, 15, 4, cmax=20, L=2)
+    sink.snk_slope[:] = 1
+    sink.lambdas[:] = [5, 1 << 30]  # cap_snk0 + slope * lambda > INF
+    badlam = W.tiny_random(rng, 20, 15, 4, cmax=20, L=2)
+    badlam.lambdas[:] = [9, 3]  # decreasing schedule
+    insts = [good, neg, offgrid, over, sink, badlam]
+    flows, status, masks, _ = solve(pmf, insts)
+    fl = split(flows, insts)
+    assert list(status) == [0, pmf.PMF_EINVAL, pmf.PMF_EINVAL, pmf.PMF_EOVERFLOW, pmf.PMF_EOVERFLOW,
+                            pmf.PMF_EINVAL]
+    for i in range(1, len(insts)):
+        assert (fl[i] == -1).all()
+    check_against_oracle([good], fl[0], status[:1], masks[:1])
+
+
+def test_superstep_budget_times_out(pmf):
+    """A budget too small to finish (forced from the host): status ETIMEOUT,
+    flows of unfinished lambdas -1, and every kernel still exits normally."""
+    import torch
+    insts = W.config1()
+    s = pmf.Solver(max_supersteps=40)
+    flows, status = s.solve(pmf.to_device(insts))
+    torch.cuda.synchronize()
+    assert int(status.cpu()[0]) == pmf.PMF_ETIMEOUT
+    f = flows.cpu().numpy()
+    assert f[-1] == -1
+    done = int((f >= 0).sum())
+    for k in range(done):
+        assert f[k] == O.fifo_pr(insts[0], int(insts[0].lambdas[k]))[0]
+    s.close()
