@@ -67,7 +67,11 @@ typedef struct pmf_options {
     int64_t mem_budget;         /* bytes the library may allocate (0 = no limit)     */
     int32_t max_slots;          /* instance slots of a serving session (0 = 4096)    */
     int32_t timing;             /* 1: no graph; time every kernel with HIP events    */
-    int32_t reserved[6];
+    int32_t lambda_chunk;       /* pmf_solve_batch: lambdas per device instance.     */
+                                /*   1 = every lambda solved from scratch, all in   */
+                                /*   parallel; >= L = one warm-started chain; 0 =   */
+                                /*   the smallest chunk whose state fits in memory  */
+    int32_t reserved[5];
 } pmf_options;
 
 /* One (image, seed) problem and its lambda schedule.  All pointers are device

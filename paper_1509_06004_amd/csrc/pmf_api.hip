@@ -181,6 +181,11 @@ struct pmf_handle {
     pmf_stats stats;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;  // bracket every launch group (device time)
     hipEvent_t kev[4] = {nullptr, nullptr, nullptr, nullptr};  // per-kernel timing mode
+    // pmf_solve_batch: caller instance i = slots [user_first[i], user_first[i+1]),
+    // lambda k of it in slot user_first[i] + k / chunk at index k % chunk
+    bool batch = false;
+    int32_t chunk = 1;
+    std::vector<int32_t> user_first, user_L;
 };
 
 namespace {
@@ -323,7 +328,7 @@ int rebuild_worklist(pmf_handle *h) {
 }
 
 int submit(pmf_handle *h, const pmf_instance *inst, int n, int64_t *flows_out, int32_t *status_out,
-           int32_t *ids_out) {
+           int32_t *ids_out, const uint8_t *check_prev = nullptr) {
     if (!h->open) return PMF_EINVAL;
     if (n < 0 || (n > 0 && (!inst || !flows_out))) return PMF_EINVAL;
     for (int i = 0; i < n; ++i) {
@@ -366,6 +371,7 @@ int submit(pmf_handle *h, const pmf_instance *inst, int n, int64_t *flows_out, i
         D.tile0 = 0;
         D.L = I.L;
         D.slot_id = id;
+        D.check_prev = check_prev ? check_prev[i] : 0;
         D.lambdas = I.lambdas;
         D.nlink = I.nlink;
         D.cap_src = I.cap_src;
@@ -478,22 +484,36 @@ int run_steps(pmf_handle *h, int steps, std::vector<int> *finished) {
     }
     const int32_t count = *(volatile int32_t *)h->pinned;
     if (count <= h->ring_seen) return PMF_OK;
-    // the new ring entries, then the final states of those instances
+    // the new ring entries (at most two contiguous ranges), then the final
+    // states of those instances (one bulk copy when many finished)
     const int cap = h->max_slots;
-    for (int32_t c = h->ring_seen; c < count; ++c) {
-        const int at = c % cap;
-        if (hipMemcpyAsync(h->pinned_ring + at, P.ring + at, 4, hipMemcpyDeviceToHost, s) != hipSuccess)
-            return PMF_EDEVICE;
-    }
+    const int32_t fresh = count - h->ring_seen;
+    if (fresh > cap) return PMF_EDEVICE;  // a slot can finish only once per admission
+    const int a0 = h->ring_seen % cap;
+    const int first_len = std::min(fresh, cap - a0);
+    if (hipMemcpyAsync(h->pinned_ring + a0, P.ring + a0, 4 * (size_t)first_len, hipMemcpyDeviceToHost, s) !=
+        hipSuccess)
+        return PMF_EDEVICE;
+    if (fresh > first_len &&
+        hipMemcpyAsync(h->pinned_ring, P.ring, 4 * (size_t)(fresh - first_len), hipMemcpyDeviceToHost, s) !=
+            hipSuccess)
+        return PMF_EDEVICE;
     if (hipStreamSynchronize(s) != hipSuccess) return PMF_EDEVICE;
     std::vector<int> got;
     for (int32_t c = h->ring_seen; c < count; ++c) {
         const int id = h->pinned_ring[c % cap];
         if (id < 0 || id >= cap) return PMF_EDEVICE;
         got.push_back(id);
-        if (hipMemcpyAsync(h->pinned_state + id, P.st + id, sizeof(InstState), hipMemcpyDeviceToHost, s) !=
+    }
+    if (got.size() > 64) {
+        if (hipMemcpyAsync(h->pinned_state, P.st, sizeof(InstState) * (size_t)cap, hipMemcpyDeviceToHost, s) !=
             hipSuccess)
             return PMF_EDEVICE;
+    } else {
+        for (int id : got)
+            if (hipMemcpyAsync(h->pinned_state + id, P.st + id, sizeof(InstState), hipMemcpyDeviceToHost, s) !=
+                hipSuccess)
+                return PMF_EDEVICE;
     }
     if (hipStreamSynchronize(s) != hipSuccess) return PMF_EDEVICE;
     h->ring_seen = count;
@@ -623,44 +643,155 @@ int pmf_query_bytes(const pmf_instance *inst, int32_t n, const pmf_options *opt,
     return PMF_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+// Bytes of the pool for a batch whose schedules are cut into chunks of C lambdas.
+size_t batch_pool_bytes(const pmf_instance *inst, int n, int C, int tw, int th, int64_t *n_sub) {
+    size_t pool = 0;
+    int64_t subs = 0;
+    for (int i = 0; i < n; ++i) {
+        pmf_instance I = inst[i];
+        const int full = I.L / C, rest = I.L % C;
+        if (full) {
+            I.L = C;
+            pool += (size_t)full * block_layout(I, tw, th).total;
+        }
+        if (rest) {
+            I.L = rest;
+            pool += block_layout(I, tw, th).total;
+        }
+        subs += full + (rest ? 1 : 0);
+    }
+    pool += align_up(8 * (3 * (size_t)n + 1)) + align_up(4 * (size_t)subs);  // finalize metadata
+    *n_sub = subs;
+    return pool;
+}
+
+// The lambda chunk: the caller's choice, else the smallest chunk (the most
+// parallel work: chunks run concurrently, each lambda after the first of a
+// chunk is warm-started from the one before) whose state fits the memory
+// available to the handle.
+int choose_chunk(pmf_handle *h, const pmf_instance *inst, int n) {
+    int maxL = 1;
+    for (int i = 0; i < n; ++i) maxL = std::max(maxL, (int)inst[i].L);
+    if (h->opt.lambda_chunk > 0) return std::min((int)h->opt.lambda_chunk, maxL);
+    size_t budget;
+    if (!h->own_arena) {
+        budget = h->arena_bytes;
+    } else if (h->opt.mem_budget > 0) {
+        budget = (size_t)h->opt.mem_budget;
+    } else {
+        size_t fr = 0, tot = 0;
+        if (hipMemGetInfo(&fr, &tot) != hipSuccess) return maxL;
+        budget = (size_t)((double)(fr + h->arena_bytes) * 0.7);
+    }
+    for (int C = 1;; C = C < 4 ? C + 1 : C * 2) {
+        if (C >= maxL) return maxL;
+        int64_t subs = 0;
+        const size_t pool = batch_pool_bytes(inst, n, C, h->tw, h->th, &subs);
+        if (subs <= (1 << 20) && pool + control_bytes((int)subs, worklist_cap((int)subs, pool)) <= budget) return C;
+    }
+}
+
+// Slot and lambda index inside it of (caller instance, lambda).
+int locate(pmf_handle *h, int32_t inst, int32_t lambda_idx, int *slot, int *k) {
+    if (h->batch) {
+        if (inst < 0 || inst >= (int)h->user_L.size()) return PMF_ERANGE;
+        if (lambda_idx < 0 || lambda_idx >= h->user_L[inst]) return PMF_ERANGE;
+        *slot = h->user_first[inst] + lambda_idx / h->chunk;
+        *k = lambda_idx % h->chunk;
+        return PMF_OK;
+    }
+    if (inst < 0 || inst >= h->max_slots || !h->slots[inst].live) return PMF_ERANGE;
+    if (lambda_idx < 0 || lambda_idx >= h->slots[inst].L) return PMF_ERANGE;
+    *slot = inst;
+    *k = lambda_idx;
+    return PMF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
 int pmf_solve_batch(pmf_handle *h, const pmf_instance *inst, int32_t n_inst, int64_t *flows_out,
                     int32_t *status_out) {
     if (!h || n_inst < 0 || (n_inst > 0 && (!inst || !flows_out))) return PMF_EINVAL;
     int rc = pmf_check_instances(inst, n_inst, nullptr);
     if (rc != PMF_OK) return rc;
-    size_t pool = 0;
-    for (int i = 0; i < n_inst; ++i) pool += block_layout(inst[i], h->tw, h->th).total;
-    rc = open_session(h, std::max(n_inst, 1), pool);
+    const int C = n_inst ? choose_chunk(h, inst, n_inst) : 1;
+    int64_t n_sub = 0;
+    const size_t pool = batch_pool_bytes(inst, n_inst, C, h->tw, h->th, &n_sub);
+    rc = open_session(h, (int)std::max<int64_t>(n_sub, 1), pool);
     if (rc != PMF_OK) return rc;
+    h->batch = true;
+    h->chunk = C;
+    h->user_first.assign(n_inst + 1, 0);
+    h->user_L.assign(n_inst, 0);
     if (n_inst == 0) return PMF_OK;
-    rc = submit(h, inst, n_inst, flows_out, status_out, nullptr);
+    // chunks in caller order, so that their flows are contiguous in flows_out
+    std::vector<pmf_instance> subs;
+    std::vector<uint8_t> prev;
+    std::vector<int64_t> meta(3 * (size_t)n_inst + 1);
+    int64_t foff = 0;
+    for (int i = 0; i < n_inst; ++i) {
+        h->user_first[i] = (int32_t)subs.size();
+        h->user_L[i] = inst[i].L;
+        meta[i] = (int64_t)subs.size();
+        meta[n_inst + 1 + i] = foff;
+        meta[2 * n_inst + 1 + i] = inst[i].L;
+        foff += inst[i].L;
+        for (int a = 0; a < inst[i].L; a += C) {
+            pmf_instance I = inst[i];
+            I.lambdas = inst[i].lambdas + a;
+            I.L = std::min(C, inst[i].L - a);
+            subs.push_back(I);
+            prev.push_back(a > 0 ? 1 : 0);
+        }
+    }
+    meta[n_inst] = (int64_t)subs.size();
+    h->user_first[n_inst] = (int32_t)subs.size();
+    // the finalize metadata takes the first pool block
+    size_t moff = 0;
+    const size_t mbytes = align_up(8 * meta.size()) + align_up(4 * subs.size());
+    if (!h->pool.alloc(mbytes, &moff)) return PMF_ENOMEM;
+    char *mbase = h->arena + h->pool_base + moff;
+    int64_t *d_meta = (int64_t *)mbase;
+    int32_t *d_sub_status = (int32_t *)(mbase + align_up(8 * meta.size()));
+    if (hipMemcpyAsync(d_meta, meta.data(), 8 * meta.size(), hipMemcpyHostToDevice, h->stream) != hipSuccess)
+        return PMF_EDEVICE;
+    rc = submit(h, subs.data(), (int)subs.size(), flows_out, d_sub_status, nullptr, prev.data());
     if (rc != PMF_OK) return rc == PMF_EBUSY ? PMF_ENOMEM : rc;
     // The work list keeps finished instances (their tiles exit at once), so
     // one captured superstep graph serves the whole solve.
     const int S = h->opt.timing ? 1 : h->opt.steps_per_sync;
     const int64_t max_rounds = h->opt.max_supersteps / S + 4;
-    int done = 0;
+    int64_t done = 0;
     std::vector<int> fin;
-    for (int64_t round = 0; done < n_inst; ++round) {
+    for (int64_t round = 0; done < (int64_t)subs.size(); ++round) {
         if (round > max_rounds) return PMF_ETIMEOUT;
         fin.clear();
         rc = run_steps(h, S, &fin);
         if (rc != PMF_OK) return rc;
-        done += (int)fin.size();
+        done += (int64_t)fin.size();
         h->wl_dirty = false;
     }
+    if (launch_finalize(d_sub_status, d_meta, n_inst, flows_out, status_out, h->stream) != 0) return PMF_EDEVICE;
+    if (hipStreamSynchronize(h->stream) != hipSuccess) return PMF_EDEVICE;
     return PMF_OK;
 }
 
 int pmf_extract_cut(pmf_handle *h, int32_t inst, int32_t lambda_idx, uint8_t *mask_out) {
     if (!h || !mask_out) return PMF_EINVAL;
     if (!h->open) return PMF_ENOTSOLVED;
-    if (inst < 0 || inst >= h->max_slots || !h->slots[inst].live) return PMF_ERANGE;
-    const Slot &s = h->slots[inst];
-    if (lambda_idx < 0 || lambda_idx >= s.L) return PMF_ERANGE;
-    if (!s.finished || s.done_k <= lambda_idx) return PMF_ENOTSOLVED;
+    int slot, k;
+    const int rc = locate(h, inst, lambda_idx, &slot, &k);
+    if (rc != PMF_OK) return rc;
+    const Slot &s = h->slots[slot];
+    if (!s.live || !s.finished || s.done_k <= k) return PMF_ENOTSOLVED;
     const size_t px = (size_t)s.W * s.H;
-    const char *src = h->arena + s.masks + (size_t)lambda_idx * px;
+    const char *src = h->arena + s.masks + (size_t)k * px;
     if (hipMemcpyAsync(mask_out, src, px, hipMemcpyDeviceToDevice, h->stream) != hipSuccess) return PMF_EDEVICE;
     return PMF_OK;
 }
@@ -668,16 +799,34 @@ int pmf_extract_cut(pmf_handle *h, int32_t inst, int32_t lambda_idx, uint8_t *ma
 int pmf_extract_levels(pmf_handle *h, int32_t inst, uint8_t *levels_out) {
     if (!h || !levels_out) return PMF_EINVAL;
     if (!h->open) return PMF_ENOTSOLVED;
-    if (inst < 0 || inst >= h->max_slots || !h->slots[inst].live) return PMF_ERANGE;
-    const Slot &s = h->slots[inst];
-    if (s.L > 255) return PMF_ERANGE;
-    if (!s.finished || s.done_k < s.L) return PMF_ENOTSOLVED;
-    const uint8_t *masks = (const uint8_t *)(h->arena + s.masks);
-    return launch_levels(masks, s.L, s.W * s.H, levels_out, h->stream) == 0 ? PMF_OK : PMF_EDEVICE;
+    int first, last;
+    if (h->batch) {
+        if (inst < 0 || inst >= (int)h->user_L.size()) return PMF_ERANGE;
+        if (h->user_L[inst] > 255) return PMF_ERANGE;
+        first = h->user_first[inst];
+        last = h->user_first[inst + 1];
+    } else {
+        if (inst < 0 || inst >= h->max_slots || !h->slots[inst].live) return PMF_ERANGE;
+        if (h->slots[inst].L > 255) return PMF_ERANGE;
+        first = inst;
+        last = inst + 1;
+    }
+    for (int sl = first; sl < last; ++sl) {
+        const Slot &s = h->slots[sl];
+        if (!s.live || !s.finished || s.done_k < s.L) return PMF_ENOTSOLVED;
+    }
+    // every chunk adds the lambdas it holds (the sets are nested across chunks too)
+    for (int sl = first; sl < last; ++sl) {
+        const Slot &s = h->slots[sl];
+        const uint8_t *masks = (const uint8_t *)(h->arena + s.masks);
+        if (launch_levels(masks, s.L, s.W * s.H, levels_out, sl > first, h->stream) != 0) return PMF_EDEVICE;
+    }
+    return PMF_OK;
 }
 
 int pmf_session_open(pmf_handle *h, int32_t max_slots, size_t pool_bytes) {
     if (!h || max_slots < 1) return PMF_EINVAL;
+    h->batch = false;
     if (pool_bytes == 0) {
         size_t avail = 0;
         if (!h->own_arena) {

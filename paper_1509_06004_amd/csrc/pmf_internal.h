@@ -35,7 +35,8 @@ struct alignas(16) InstDesc {
     int32_t W, H, K, n;
     int32_t tiles_x, tiles_y, ntiles, tile0;
     int32_t L, slot_id;
-    int32_t pad0, pad1;
+    int32_t check_prev;  // lambdas[-1] belongs to the same schedule: check it too
+    int32_t pad1;
     const int32_t *lambdas;
     const int32_t *nlink;
     const int32_t *cap_src;
@@ -97,7 +98,14 @@ struct StepParams {
 // launched, or -1 on a launch error.
 int launch_superstep(const StepParams &p, int tile_w, void *stream, void *const *events = nullptr);
 
-// out[p] = number of the L masks that hold pixel p (n pixels).
-int launch_levels(const uint8_t *masks, int L, int n, uint8_t *out, void *stream);
+// out[p] (+)= number of the L masks that hold pixel p (n pixels).
+int launch_levels(const uint8_t *masks, int L, int n, uint8_t *out, bool accumulate, void *stream);
+
+// Merge the statuses of the lambda chunks of each caller instance:
+// user i owns chunks [first[i], first[i+1]) and flows [flow_off[i], +L[i]).
+// The merged status is EINVAL, else EOVERFLOW, else ETIMEOUT, else OK; an
+// invalid instance gets flows -1 throughout.
+int launch_finalize(const int32_t *sub_status, const int64_t *meta, int n_user, int64_t *flows,
+                    int32_t *status_out, void *stream);
 
 }  // namespace pmf

@@ -178,11 +178,13 @@ __device__ void init_tile(const StepParams &P, const InstDesc &D, InstState *S, 
         D.rmask[p] = (uint16_t)rm;
     }
     if (tl == 0 && tid < 64) {
-        // the schedule: lambda_0 >= 0, non-decreasing
+        // the schedule: lambda_0 >= 0, non-decreasing (also across the start
+        // of a chunk of a longer schedule)
         for (int i = tid; i < D.L; i += 64) {
             const int li = D.lambdas[i];
             if (li < 0 || (i > 0 && li < D.lambdas[i - 1])) err |= 1;
         }
+        if (tid == 0 && D.check_prev && D.lambdas[-1] > D.lambdas[0]) err |= 1;
     }
     const long long tot = block_sum_i64(scs, s_sum);
     if (tid == 0) {
@@ -777,17 +779,44 @@ __global__ __launch_bounds__(kThreads) void k_control(StepParams P) { control(P)
 // Nested masks to one byte per pixel: the number of lambdas whose minimal
 // source side holds the pixel (the sets shrink as lambda grows, so mask k is
 // level > k).
-__global__ __launch_bounds__(kThreads) void k_levels(const uint8_t *masks, int L, int n, uint8_t *out) {
+__global__ __launch_bounds__(kThreads) void k_levels(const uint8_t *masks, int L, int n, uint8_t *out,
+                                                     int accumulate) {
     const int p = blockIdx.x * kThreads + threadIdx.x;
     if (p >= n) return;
-    int c = 0;
+    int c = accumulate ? out[p] : 0;
     for (int k = 0; k < L; ++k) c += masks[(size_t)k * n + p];
     out[p] = (uint8_t)c;
 }
 
-int launch_levels(const uint8_t *masks, int L, int n, uint8_t *out, void *stream) {
+int launch_levels(const uint8_t *masks, int L, int n, uint8_t *out, bool accumulate, void *stream) {
     hipLaunchKernelGGL(k_levels, dim3((n + kThreads - 1) / kThreads), dim3(kThreads), 0, (hipStream_t)stream,
-                       masks, L, n, out);
+                       masks, L, n, out, accumulate ? 1 : 0);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+// meta layout: first[n_user + 1], flow_off[n_user], L[n_user] (int64)
+__global__ __launch_bounds__(kThreads) void k_finalize(const int32_t *sub_status, const int64_t *meta,
+                                                       int n_user, int64_t *flows, int32_t *status_out) {
+    const int i = blockIdx.x * kThreads + threadIdx.x;
+    if (i >= n_user) return;
+    const int64_t *first = meta, *off = meta + n_user + 1, *len = meta + 2 * n_user + 1;
+    bool inval = false, over = false, tout = false;
+    for (int64_t c = first[i]; c < first[i + 1]; ++c) {
+        const int st = sub_status[c];
+        inval |= st == PMF_EINVAL;
+        over |= st == PMF_EOVERFLOW;
+        tout |= st == PMF_ETIMEOUT;
+    }
+    const int st = inval ? PMF_EINVAL : over ? PMF_EOVERFLOW : tout ? PMF_ETIMEOUT : PMF_OK;
+    if (inval || over)
+        for (int64_t k = 0; k < len[i]; ++k) flows[off[i] + k] = -1;
+    if (status_out) status_out[i] = st;
+}
+
+int launch_finalize(const int32_t *sub_status, const int64_t *meta, int n_user, int64_t *flows,
+                    int32_t *status_out, void *stream) {
+    hipLaunchKernelGGL(k_finalize, dim3((n_user + kThreads - 1) / kThreads), dim3(kThreads), 0,
+                       (hipStream_t)stream, sub_status, meta, n_user, flows, status_out);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

@@ -46,7 +46,8 @@ class Options(ctypes.Structure):
         ("mem_budget", ctypes.c_int64),
         ("max_slots", ctypes.c_int32),
         ("timing", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 6),
+        ("lambda_chunk", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 5),
     ]
 
 

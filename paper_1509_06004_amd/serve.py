@@ -82,7 +82,8 @@ class Backend:
 class PmfBackend(Backend):
     """libpmf session on one GPU (inputs uploaded per request)."""
 
-    def __init__(self, max_slots: int = 4096, pool_bytes: int = 0, supersteps: int = 16, **options):
+    def __init__(self, max_slots: int = 4096, pool_bytes: int = 0, supersteps: int = 16, lambda_chunk: int = 1,
+                 **options):
         import torch
         from . import pmf
         self.torch, self.pmf = torch, pmf
@@ -96,14 +97,23 @@ class PmfBackend(Backend):
             raise pmf.PmfError(rc, "pmf_session_open")
         self.options = opts
         self.supersteps = supersteps
+        # every request instance is split into chunks of lambda_chunk lambdas,
+        # each a device instance of its own: more parallel work per request
+        self.chunk = max(1, int(lambda_chunk))
+        self.groups: Dict[int, List[int]] = {}  # first device id -> device ids of one instance
         self.pool_bytes = pmf.pmf_session_query(self.handle)["free_bytes"]
         self.live: Dict[int, tuple] = {}  # id -> (device inputs, flows view, status view, L, H, W)
 
-    def bytes_needed(self, insts) -> int:
-        return self.pmf.pmf_query_bytes([self._fake(i) for i in insts], self.options)
+    def _chunks(self, inst):
+        L = int(inst.lambdas.shape[0])
+        return [(a, min(L, a + self.chunk)) for a in range(0, L, self.chunk)]
 
-    def _fake(self, i):
-        return self.pmf.InstanceC(i.W, i.H, i.K, i.L, 1, 1, 1, 0, 0, 1)
+    def bytes_needed(self, insts) -> int:
+        fake = []
+        for i in insts:
+            for a, b in self._chunks(i):
+                fake.append(self.pmf.InstanceC(i.W, i.H, i.K, b - a, 1, 1, 1, 0, 0, 1))
+        return self.pmf.pmf_query_bytes(fake, self.options)
 
     def free_bytes(self) -> int:
         return self.pmf.pmf_session_query(self.handle)["largest_free"]
@@ -112,38 +122,69 @@ class PmfBackend(Backend):
         return self.pool_bytes
 
     def submit(self, insts) -> Optional[List[int]]:
+        """One id per request instance (the id of its first chunk)."""
         torch, pmf = self.torch, self.pmf
         dev = pmf.to_device(insts)
-        total = sum(d.L for d in dev)
+        subs, owner = [], []
+        for j, d in enumerate(dev):
+            for a, b in self._chunks(insts[j]):
+                subs.append(pmf.DeviceInstance(d.W, d.H, d.K, d.nlink, d.cap_src, d.cap_snk0, d.snk_slope,
+                                               d.seed, d.lambdas[a:b]))
+                owner.append(j)
+        total = sum(d.L for d in subs)
         flows = torch.empty(total, dtype=torch.int64, device="cuda")
-        status = torch.empty(len(dev), dtype=torch.int32, device="cuda")
-        rc, ids = pmf.pmf_session_submit(self.handle, [d.c_struct() for d in dev], int(flows.data_ptr()),
+        status = torch.empty(len(subs), dtype=torch.int32, device="cuda")
+        rc, ids = pmf.pmf_session_submit(self.handle, [d.c_struct() for d in subs], int(flows.data_ptr()),
                                          int(status.data_ptr()))
         if rc == pmf.PMF_EBUSY:
             return None
         if rc != pmf.PMF_OK:
             raise pmf.PmfError(rc, "pmf_session_submit")
-        off = 0
-        for j, (d, i) in enumerate(zip(dev, ids)):
-            self.live[i] = (d, flows[off:off + d.L], status[j:j + 1], d.L, d.H, d.W, (flows, status))
+        firsts, off, pos = [], 0, 0
+        for j, d in enumerate(dev):
+            n_ch = len(self._chunks(insts[j]))
+            grp = ids[pos:pos + n_ch]
+            self.groups[grp[0]] = grp
+            self.live[grp[0]] = (d, flows[off:off + d.L], status[pos:pos + n_ch], d.L, d.H, d.W,
+                                 (flows, status, subs))
+            firsts.append(grp[0])
             off += d.L
-        return ids
+            pos += n_ch
+        self.owner_of = getattr(self, "owner_of", {})
+        for f in firsts:
+            for i in self.groups[f]:
+                self.owner_of[i] = f
+        self.pending = getattr(self, "pending", {})
+        for f in firsts:
+            self.pending[f] = len(self.groups[f])
+        return firsts
 
     def step(self) -> List[int]:
         rc, done = self.pmf.pmf_session_step(self.handle, self.supersteps)
         if rc != self.pmf.PMF_OK:
             raise self.pmf.PmfError(rc, "pmf_session_step")
-        return done
+        out = []
+        for i in done:
+            f = self.owner_of.get(i)
+            if f is None:
+                continue
+            self.pending[f] -= 1
+            if self.pending[f] == 0:
+                out.append(f)
+        return out
 
     def fetch(self, ids: Sequence[int]) -> List[Result]:
         torch, pmf = self.torch, self.pmf
         lv, fl, stv = [], [], []
-        for i in ids:
-            d, flows, status, L, H, W, _ = self.live[i]
-            out = torch.empty((H, W), dtype=torch.uint8, device="cuda")
-            rc = pmf.pmf_extract_levels(self.handle, i, int(out.data_ptr()))
-            if rc != pmf.PMF_OK:
-                raise pmf.PmfError(rc, "pmf_extract_levels")
+        for f in ids:
+            d, flows, status, L, H, W, _ = self.live[f]
+            out = torch.zeros((H, W), dtype=torch.uint8, device="cuda")
+            tmp = torch.empty((H, W), dtype=torch.uint8, device="cuda")
+            for i in self.groups[f]:
+                rc = pmf.pmf_extract_levels(self.handle, i, int(tmp.data_ptr()))
+                if rc != pmf.PMF_OK:
+                    raise pmf.PmfError(rc, "pmf_extract_levels")
+                out += tmp  # chunks partition the schedule; the sets are nested
             lv.append(out)
             fl.append(flows)
             stv.append(status)
@@ -151,14 +192,22 @@ class PmfBackend(Backend):
         levels_h = [x.to("cpu", non_blocking=True) for x in lv]
         status_h = [s.to("cpu", non_blocking=True) for s in stv]
         torch.cuda.current_stream().synchronize()
-        return [Result(f.numpy(), l.numpy(), int(s.item())) for f, l, s in zip(flows_h, levels_h, status_h)]
+        res = []
+        for f, l, s in zip(flows_h, levels_h, status_h):
+            st = s.numpy()
+            code = int(st[st != 0][0]) if (st != 0).any() else 0
+            res.append(Result(f.numpy(), l.numpy(), code))
+        return res
 
     def release(self, ids: Sequence[int]) -> None:
-        for i in ids:
-            rc = self.pmf.pmf_session_release(self.handle, i)
-            if rc != self.pmf.PMF_OK:
-                raise self.pmf.PmfError(rc, "pmf_session_release")
-            self.live.pop(i, None)
+        for f in ids:
+            for i in self.groups.pop(f):
+                rc = self.pmf.pmf_session_release(self.handle, i)
+                if rc != self.pmf.PMF_OK:
+                    raise self.pmf.PmfError(rc, "pmf_session_release")
+                self.owner_of.pop(i, None)
+            self.pending.pop(f, None)
+            self.live.pop(f, None)
 
     def stats(self) -> Dict[str, int]:
         return self.pmf.pmf_get_stats(self.handle)

@@ -134,7 +134,8 @@ def test_options_do_not_change_results(pmf):
     ref = None
     for opts in [dict(), dict(tile_w=64, tile_h=16), dict(inner_iters=1, sweeps_per_relabel=1),
                  dict(inner_iters=64, sweeps_per_relabel=32, local_bfs_iters=4), dict(order=0),
-                 dict(use_graph=0, steps_per_sync=3), dict(timing=1)]:
+                 dict(use_graph=0, steps_per_sync=3), dict(timing=1), dict(lambda_chunk=1),
+                 dict(lambda_chunk=3), dict(lambda_chunk=100)]:
         say("options", opts)
         flows, status, masks, _ = solve(pmf, insts, **opts)
         assert (status == 0).all()
@@ -199,13 +200,14 @@ def test_invalid_capacities_report_status(pmf):
     badlam = W.tiny_random(rng, 20, 15, 4, cmax=20, L=2)
     badlam.lambdas[:] = [9, 3]  # decreasing schedule
     insts = [good, neg, offgrid, over, sink, badlam]
-    flows, status, masks, _ = solve(pmf, insts)
-    fl = split(flows, insts)
-    assert list(status) == [0, pmf.PMF_EINVAL, pmf.PMF_EINVAL, pmf.PMF_EOVERFLOW, pmf.PMF_EOVERFLOW,
-                            pmf.PMF_EINVAL]
-    for i in range(1, len(insts)):
-        assert (fl[i] == -1).all()
-    check_against_oracle([good], fl[0], status[:1], masks[:1])
+    for chunk in (1, 2):  # the decreasing pair of badlam straddles two chunks when chunk = 1
+        flows, status, masks, _ = solve(pmf, insts, lambda_chunk=chunk)
+        fl = split(flows, insts)
+        assert list(status) == [0, pmf.PMF_EINVAL, pmf.PMF_EINVAL, pmf.PMF_EOVERFLOW, pmf.PMF_EOVERFLOW,
+                                pmf.PMF_EINVAL], chunk
+        for i in range(1, len(insts)):
+            assert (fl[i] == -1).all()
+        check_against_oracle([good], fl[0], status[:1], masks[:1])
 
 
 def test_superstep_budget_times_out(pmf):
@@ -213,7 +215,7 @@ def test_superstep_budget_times_out(pmf):
     flows of unfinished lambdas -1, and every kernel still exits normally."""
     import torch
     insts = W.config1()
-    s = pmf.Solver(max_supersteps=40)
+    s = pmf.Solver(max_supersteps=40, lambda_chunk=20)  # one warm chain: finished lambdas form a prefix
     flows, status = s.solve(pmf.to_device(insts))
     torch.cuda.synchronize()
     assert int(status.cpu()[0]) == pmf.PMF_ETIMEOUT
@@ -222,4 +224,13 @@ def test_superstep_budget_times_out(pmf):
     done = int((f >= 0).sum())
     for k in range(done):
         assert f[k] == O.fifo_pr(insts[0], int(insts[0].lambdas[k]))[0]
+    assert (f[done:] == -1).all()
+    s.close()
+    s = pmf.Solver(max_supersteps=12, lambda_chunk=1)  # every lambda on its own budget
+    flows, status = s.solve(pmf.to_device(insts))
+    torch.cuda.synchronize()
+    f = flows.cpu().numpy()
+    assert int(status.cpu()[0]) == pmf.PMF_ETIMEOUT and (f == -1).any()
+    for k in range(len(f)):
+        assert f[k] == -1 or f[k] == O.fifo_pr(insts[0], int(insts[0].lambdas[k]))[0]
     s.close()
