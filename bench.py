@@ -126,6 +126,8 @@ def main():
     ap.add_argument("--local-bfs-iters", type=int, default=0)
     ap.add_argument("--steps-per-sync", type=int, default=0)
     ap.add_argument("--lambda-chunk", type=int, default=0)
+    ap.add_argument("--tune", action="store_true",
+                    help="autotune the speed knobs on this workload before timing (results must not change)")
     ap.add_argument("--cpu-sample", type=int, default=48)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
@@ -169,6 +171,17 @@ def main():
     insts = workload.config2(K=4)
     n_solves = sum(i.L for i in insts)
     dev = pmf.to_device(insts)
+    tuned = None
+    if args.tune:
+        from paper_1509_06004_amd import tune as T
+        t0 = time.perf_counter()
+        res = T.tune(dev, start=overrides or None, log=log)
+        tuned = {"options": res["options"], "tune_seconds": round(time.perf_counter() - t0, 1),
+                 "trials": len(res["trials"]), "rejected": len(res["rejected"])}
+        if res["rejected"]:
+            raise SystemExit("autotuner found configurations with different results: %s" % res["rejected"])
+        overrides = dict(res["options"])
+        overrides["tile_h"] = 1024 // overrides["tile_w"]
     solver = pmf.Solver(**overrides)
     torch.cuda.synchronize()
     log("workload: %d instances, %d solves; warmup %d" % (len(insts), n_solves, args.warmup))
@@ -243,6 +256,7 @@ def main():
                           "p99": round(float(np.percentile(times, 99)) * 1e3, 2),
                           "what": "per batched step of 500 solves"},
            "device_time_frac": round(acc["device_ns"] * 1e-9 / sum(times), 3),
+           "autotuned": tuned,
            "roofline": roof}
 
     # plain: one instance (one seed's 20-lambda chain, warm-started, not split)
