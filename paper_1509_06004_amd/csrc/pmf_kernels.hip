@@ -34,6 +34,8 @@
 // an exact relabel on a quiescent state.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "pmf.h"
 #include "pmf_internal.h"
 
@@ -91,12 +93,17 @@ __device__ __forceinline__ void count_px(int64_t *ctr, long long v) {
     atomicAdd((unsigned long long *)ctr, (unsigned long long)v);
 }
 
-// Shared by all phases: block-wide integer sum (returned to every thread).
-__device__ __forceinline__ int block_sum_int(int v, int *s_red) {
+// Block-wide count of set flags by wave ballots: each wave adds the popcount
+// of its ballots once (returned to every thread).
+template <int N>
+__device__ __forceinline__ int block_count_ballot(const bool (&flag)[N], int *s_red) {
+    int c = 0;
+#pragma unroll
+    for (int j = 0; j < N; ++j) c += __popcll(__ballot(flag[j]));
     __syncthreads();
     if (threadIdx.x == 0) s_red[0] = 0;
     __syncthreads();
-    if (v) atomicAdd(&s_red[0], v);
+    if ((threadIdx.x & 63) == 0 && c) atomicAdd(&s_red[0], c);
     __syncthreads();
     return s_red[0];
 }
@@ -200,13 +207,33 @@ __device__ void init_tile(const StepParams &P, const InstDesc &D, InstState *S, 
 }
 
 // ---------------------------------------------------------------------------
-// kSweep: tile-local push/relabel iterations in registers + LDS.
+// kSweep: tile-local push/relabel iterations in LDS.
+//
+// Residuals r_k and excess e of the tile live in LDS planes indexed like the
+// height plane, with a one-pixel halo.  Each inner iteration has two phases
+// separated by a barrier:
+//   push:    every active pixel p pushes d = min(e, r) along admissible arcs
+//            (h(p) = h(q) + 1; to the sink whenever rt > 0).  It writes both
+//            residuals of the arc pair, r(p->q) -= d and r(q->p) += d, without
+//            atomics: heights do not change during this phase, so two
+//            neighbours never both see the other as admissible, and every
+//            residual word has at most one writer.  Excess moves with LDS
+//            atomics (several neighbours may push into one pixel).  A push to
+//            a halo pixel (another tile) accumulates in the halo cell's
+//            residual word of the reverse arc, which is exactly the amount
+//            handed over.
+//   relabel: an active pixel with no admissible arc takes height
+//            1 + min h(q) over its residual arcs (H_INF when none is below the
+//            height cap).
+// An inactive pixel costs two LDS reads per iteration.  At the end the tile
+// is written back and the halo accumulators go to the neighbours' inboxes
+// with one atomicAdd per nonzero word.
 // ---------------------------------------------------------------------------
 template <int K, int TW, int TH>
 __device__ void sweep_tile(const StepParams &P, const InstDesc &D, InstState *S, int tg, int tl,
                            int32_t *lds, int *s_red) {
     using G = Geo<TW, TH>;
-    constexpr int PPT = G::PPT, RPI = G::RPI, HW = G::HW;
+    constexpr int PPT = G::PPT, RPI = G::RPI, HW = G::HW, HH = G::HH, HALO = G::HALO;
     const int tid = threadIdx.x, lx = tid % TW, ly0 = tid / TW;
     // neighbours may set the pending bit concurrently: one read, broadcast
     if (tid == 0) s_red[1] = (int)(ld_agent(&D.tile_act[tl]) & 3u);
@@ -216,32 +243,37 @@ __device__ void sweep_tile(const StepParams &P, const InstDesc &D, InstState *S,
     const int x0 = tx * TW, y0 = ty * TH;
     const int W = D.W, H = D.H, n = D.n;
     const int hcap = n + 1;  // no exact distance to t exceeds n
-    int32_t *sh_h = lds;
-    int32_t *sh_out = lds + ((G::HALO + 3) & ~3);
+    int32_t *sh_h = lds;             // [HALO] heights
+    int32_t *sh_e = lds + HALO;      // [HALO] excess (tile cells only)
+    int32_t *sh_r = lds + 2 * HALO;  // [K][HALO] residuals; halo cells: pushes handed over
     __shared__ int s_nb[9];
 
     if (tid < 9) s_nb[tid] = 0;
     if (tid == 0) atomicAnd(&D.tile_act[tl], ~2u);  // about to drain the inbox
-    __syncthreads();
-
-    int r[PPT][K], e[PPT], rt[PPT], h[PPT];
+    // halo cells: heights of the neighbour tiles, zeroed hand-over words
+    for (int i = tid; i < G::RING; i += kThreads) {
+        int hx, hy;
+        G::ring(i, hx, hy);
+        const int gx = x0 + hx - 1, gy = y0 + hy - 1;
+        const int c = hy * HW + hx;
+        sh_h[c] = (gx >= 0 && gx < W && gy >= 0 && gy < H) ? D.h[gy * W + gx] : kHInf;
+#pragma unroll
+        for (int k = 0; k < K; ++k) sh_r[k * HALO + c] = 0;
+    }
+    int rt[PPT], h[PPT];
     bool valid[PPT];
 #pragma unroll
     for (int j = 0; j < PPT; ++j) {
         const int ly = ly0 + j * RPI;
         const int gx = x0 + lx, gy = y0 + ly;
+        const int c = (ly + 1) * HW + lx + 1;
         valid[j] = gx < W && gy < H;
-        // entries of sh_out towards other tiles accumulate over the whole visit
-#pragma unroll
-        for (int k = 0; k < K; ++k) {
-            const int nx = lx + DXk(k), ny = ly + DYk(k);
-            if (!(nx >= 0 && nx < TW && ny >= 0 && ny < TH)) sh_out[k * (TW * TH) + ly * TW + lx] = 0;
-        }
         if (valid[j]) {
             const int p = gy * W + gx;
+            int e = D.e[p];
+            int r[K];
 #pragma unroll
-            for (int k = 0; k < K; ++k) r[j][k] = D.r[(size_t)k * n + p];
-            e[j] = D.e[p];
+            for (int k = 0; k < K; ++k) r[k] = D.r[(size_t)k * n + p];
             rt[j] = D.rt[p];
             h[j] = D.h[p];
             // drain flow pushed in by neighbour tiles
@@ -255,130 +287,125 @@ __device__ void sweep_tile(const StepParams &P, const InstDesc &D, InstState *S,
                 int v = ld_agent(slot);
                 if (v) {
                     v = atomicExch(slot, 0);
-                    e[j] += v;
-                    r[j][k] += v;
+                    e += v;
+                    r[k] += v;
                 }
             }
-        } else {
+            sh_e[c] = e;
 #pragma unroll
-            for (int k = 0; k < K; ++k) r[j][k] = 0;
-            e[j] = 0;
+            for (int k = 0; k < K; ++k) sh_r[k * HALO + c] = r[k];
+        } else {
             rt[j] = 0;
             h[j] = kHInf;
+            sh_e[c] = 0;
+#pragma unroll
+            for (int k = 0; k < K; ++k) sh_r[k * HALO + c] = 0;
         }
-        sh_h[(ly + 1) * HW + lx + 1] = h[j];
-    }
-    for (int i = tid; i < G::RING; i += kThreads) {
-        int hx, hy;
-        G::ring(i, hx, hy);
-        const int gx = x0 + hx - 1, gy = y0 + hy - 1;
-        sh_h[hy * HW + hx] = (gx >= 0 && gx < W && gy >= 0 && gy < H) ? D.h[gy * W + gx] : kHInf;
+        sh_h[c] = h[j];
     }
     __syncthreads();
 
     for (int it = 0; it < P.inner_iters; ++it) {
-        // push: every active pixel sends as much as it can along admissible arcs
+        // push
 #pragma unroll
         for (int j = 0; j < PPT; ++j) {
+            if (h[j] >= kHInf) continue;
             const int ly = ly0 + j * RPI;
-            int o[K];
-#pragma unroll
-            for (int k = 0; k < K; ++k) o[k] = 0;
-            const bool act = e[j] > 0 && h[j] < kHInf;
-            if (act) {
-                if (rt[j] > 0) {
-                    const int d = e[j] < rt[j] ? e[j] : rt[j];
-                    e[j] -= d;
-                    rt[j] -= d;
-                }
-#pragma unroll
-                for (int k = 0; k < K; ++k) {
-                    if (e[j] > 0 && r[j][k] > 0) {
-                        const int hq = sh_h[(ly + 1 + DYk(k)) * HW + lx + 1 + DXk(k)];
-                        if (hq == h[j] - 1) {
-                            const int d = e[j] < r[j][k] ? e[j] : r[j][k];
-                            e[j] -= d;
-                            r[j][k] -= d;
-                            o[k] = d;
-                        }
-                    }
-                }
+            const int c = (ly + 1) * HW + lx + 1;
+            int e = sh_e[c];
+            if (e <= 0) continue;
+            int pushed = 0;
+            if (rt[j] > 0) {
+                const int d = e < rt[j] ? e : rt[j];
+                e -= d;
+                rt[j] -= d;
+                pushed += d;
             }
 #pragma unroll
             for (int k = 0; k < K; ++k) {
+                if (e <= 0) break;
+                const int r = sh_r[k * HALO + c];
+                if (r <= 0) continue;
+                const int q = c + DYk(k) * HW + DXk(k);
+                if (sh_h[q] != h[j] - 1) continue;
+                const int d = e < r ? e : r;
+                e -= d;
+                pushed += d;
+                sh_r[k * HALO + c] = r - d;
+                sh_r[(k ^ 1) * HALO + q] += d;
                 const int nx = lx + DXk(k), ny = ly + DYk(k);
-                int32_t *slot = &sh_out[k * (TW * TH) + ly * TW + lx];
-                if (nx >= 0 && nx < TW && ny >= 0 && ny < TH)
-                    *slot = o[k];  // consumed by the neighbour's gather below
-                else if (o[k])
-                    *slot += o[k];  // handed to the neighbour tile after the visit
+                if (nx >= 0 && nx < TW && ny >= 0 && ny < TH) atomicAdd(&sh_e[q], d);
             }
+            if (pushed) atomicSub(&sh_e[c], pushed);
         }
         __syncthreads();
-        // gather pushes from in-tile neighbours, then relabel stuck pixels
+        // relabel stuck pixels
         int any = 0;
 #pragma unroll
         for (int j = 0; j < PPT; ++j) {
-            const int ly = ly0 + j * RPI;
+            if (h[j] >= kHInf) continue;
+            const int c = (ly0 + j * RPI + 1) * HW + lx + 1;
+            if (sh_e[c] <= 0) continue;
+            bool adm = rt[j] > 0;
+            int mn = kHInf;
 #pragma unroll
             for (int k = 0; k < K; ++k) {
-                const int nx = lx + DXk(k), ny = ly + DYk(k);
-                if (nx >= 0 && nx < TW && ny >= 0 && ny < TH) {
-                    const int inc = sh_out[(k ^ 1) * (TW * TH) + ny * TW + nx];
-                    e[j] += inc;
-                    r[j][k] += inc;
+                if (sh_r[k * HALO + c] > 0) {
+                    const int hq = sh_h[c + DYk(k) * HW + DXk(k)];
+                    if (hq == h[j] - 1) adm = true;
+                    if (hq < kHInf && hq + 1 < mn) mn = hq + 1;
                 }
             }
-            if (e[j] > 0 && h[j] < kHInf) {
-                bool adm = rt[j] > 0;
-                int mn = kHInf;
-#pragma unroll
-                for (int k = 0; k < K; ++k) {
-                    if (r[j][k] > 0) {
-                        const int hq = sh_h[(ly + 1 + DYk(k)) * HW + lx + 1 + DXk(k)];
-                        if (hq == h[j] - 1) adm = true;
-                        if (hq < kHInf && hq + 1 < mn) mn = hq + 1;
-                    }
-                }
-                if (!adm) {
-                    h[j] = mn >= hcap ? kHInf : mn;
-                    sh_h[(ly + 1) * HW + lx + 1] = h[j];
-                }
-                any |= h[j] < kHInf;
+            if (!adm) {
+                h[j] = mn >= hcap ? kHInf : mn;
+                sh_h[c] = h[j];
             }
+            any |= h[j] < kHInf;
         }
         if (!__syncthreads_or(any)) break;
     }
 
-    // write back and hand cross-tile pushes to the neighbours' inboxes
+    // write back
     int active = 0;
 #pragma unroll
     for (int j = 0; j < PPT; ++j) {
         if (!valid[j]) continue;
         const int ly = ly0 + j * RPI;
-        const int gx = x0 + lx, gy = y0 + ly;
-        const int p = gy * W + gx;
-        int rm = (rt[j] > 0 ? kRtBit : 0) | (e[j] > 0 ? kEBit : 0);
+        const int p = (y0 + ly) * W + x0 + lx;
+        const int c = (ly + 1) * HW + lx + 1;
+        const int e = sh_e[c];
+        int rm = (rt[j] > 0 ? kRtBit : 0) | (e > 0 ? kEBit : 0);
 #pragma unroll
         for (int k = 0; k < K; ++k) {
-            D.r[(size_t)k * n + p] = r[j][k];
-            if (r[j][k] > 0) rm |= 1 << k;
-            const int nx = lx + DXk(k), ny = ly + DYk(k);
-            if (nx >= 0 && nx < TW && ny >= 0 && ny < TH) continue;
-            const int v = sh_out[k * (TW * TH) + ly * TW + lx];
-            if (v > 0) {
-                const int q = (gy + DYk(k)) * W + gx + DXk(k);
-                atomicAdd(&D.inbox[(size_t)(k ^ 1) * n + q], v);
-                const int dtx = nx < 0 ? 0 : (nx >= TW ? 2 : 1);
-                const int dty = ny < 0 ? 0 : (ny >= TH ? 2 : 1);
-                s_nb[dty * 3 + dtx] = 1;
-            }
+            const int r = sh_r[k * HALO + c];
+            D.r[(size_t)k * n + p] = r;
+            if (r > 0) rm |= 1 << k;
         }
-        D.e[p] = e[j];
+        D.e[p] = e;
         D.rt[p] = rt[j];
         D.h[p] = h[j];
         D.rmask[p] = (uint16_t)rm;
-        active |= e[j] > 0 && h[j] < kHInf;
+        active |= e > 0 && h[j] < kHInf;
+    }
+    // hand pushes into halo cells to the neighbour tiles' inboxes: the word
+    // r_j of halo cell q with q + d_j inside the tile holds what q received
+    for (int i = tid; i < G::RING; i += kThreads) {
+        int hx, hy;
+        G::ring(i, hx, hy);
+        const int c = hy * HW + hx;
+        const int gx = x0 + hx - 1, gy = y0 + hy - 1;
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const int ix = hx + DXk(k), iy = hy + DYk(k);
+            if (ix < 1 || ix > TW || iy < 1 || iy > TH) continue;
+            const int v = sh_r[k * HALO + c];
+            if (v > 0 && gx >= 0 && gx < W && gy >= 0 && gy < H) {
+                atomicAdd(&D.inbox[(size_t)k * n + gy * W + gx], v);
+                const int dtx = hx == 0 ? 0 : (hx == HW - 1 ? 2 : 1);
+                const int dty = hy == 0 ? 0 : (hy == HH - 1 ? 2 : 1);
+                s_nb[dty * 3 + dtx] = 1;
+            }
+        }
     }
     const int tile_active = __syncthreads_or(active);
     if (tid < 9 && tid != 4 && s_nb[tid]) {
@@ -505,20 +532,21 @@ __device__ void relabel_tile(const StepParams &P, const InstDesc &D, InstState *
         }
         if (!__syncthreads_or(ch)) break;
     }
-    int changed = first ? 1 : 0, cnt = 0;
+    int changed = first ? 1 : 0;
+    bool act[PPT];
 #pragma unroll
     for (int j = 0; j < PPT; ++j) {
         const int ly = ly0 + j * RPI;
         const int gx = x0 + lx, gy = y0 + ly;
+        act[j] = (rm[j] & kEBit) && d[j] < kHInf;  // rm = 0 outside the image
         if (gx >= W || gy >= H) continue;
         if (first || d[j] != d0[j]) {
             D.h[gy * W + gx] = d[j];
             changed = 1;
         }
-        cnt += (rm[j] & kEBit) && d[j] < kHInf;
     }
     const int tchg = __syncthreads_or(changed);
-    const int tcnt = block_sum_int(cnt, s_red);
+    const int tcnt = block_count_ballot(act, s_red);
     if (tid == 0) {
         D.tile_chg[(size_t)cur * D.ntiles + tl] = (uint8_t)(tchg ? 1 : 0);
         const int delta = first ? tcnt : tcnt - D.tile_cnt[tl];
@@ -728,53 +756,122 @@ __device__ void control(const StepParams &P) {
     }
 }
 
-// Tile index of workgroup b inside a launch covering tiles [tbeg, tbeg + tcount):
-// consecutive tiles (neighbours in one image) land on the same XCD, whose L2
-// then holds the halos they share.  Returns -1 for padding workgroups.
-__device__ __forceinline__ int xcd_tile(int b, int tbeg, int tcount, int per_xcd) {
-    const int t = (b & 7) * per_xcd + (b >> 3);
-    return t < tcount ? tbeg + t : -1;
+// Append `value` to `list` for every lane whose `want` is set: one atomic per
+// wave on the list counter, lanes packed in lane order.
+__device__ __forceinline__ void wave_append(bool want, int32_t *list, int32_t *count, int value) {
+    const unsigned long long m = __ballot(want);
+    if (m == 0ull) return;
+    const int lane = threadIdx.x & 63;
+    const int leader = __ffsll((long long)m) - 1;
+    int base = 0;
+    if (lane == leader) base = atomicAdd(count, __popcll(m));
+    base = __shfl(base, leader);
+    if (want) list[base + __popcll(m & ((1ull << lane) - 1ull))] = value;
 }
 
+// Work compaction, one thread per tile of the work list: the tiles that need
+// a sweep (instance sweeping, pixels active or inflow pending) and the tiles
+// that need a relabel / cut / init pass (first pass of a phase, or a change in
+// the 3x3 tile neighbourhood during the previous pass) go to four lists
+// (sweep K=4, sweep K=8, pass K=4, pass K=8).  Skipped pass tiles record "no
+// change" for the current pass here, as a processed tile would.
+__global__ __launch_bounds__(kThreads) void k_compact(StepParams P) {
+    const int t = blockIdx.x * kThreads + threadIdx.x;
+    bool sw = false, bf = false, is8 = false;
+    if (t < P.ntiles) {
+        const int slot = P.tile_slot[t];
+        const int tl = P.tile_local[t];
+        const InstState *S = &P.st[slot];
+        const InstDesc *D = &P.desc[slot];
+        const int phase = S->phase;
+        is8 = t >= P.t8_begin;
+        if (tl < D->ntiles) {
+            if (phase == kSweep) {
+                sw = (D->tile_act[tl] & 3u) != 0u;
+            } else if (phase == kInit) {
+                bf = true;
+            } else if (phase == kRelabel || phase == kCut) {
+                const int sub = S->sub;
+                if (sub == 0) {
+                    bf = true;
+                } else {
+                    const int tx = tl % D->tiles_x, ty = tl / D->tiles_x;
+                    bf = frontier_needs(*D, tx, ty, (sub & 1) ^ 1);
+                    if (!bf) D->tile_chg[(size_t)(sub & 1) * D->ntiles + tl] = 0;
+                }
+            }
+        }
+    }
+    wave_append(sw && !is8, P.lists, P.list_count + 0, t);
+    wave_append(sw && is8, P.lists + (size_t)P.list_cap, P.list_count + 1, t);
+    wave_append(bf && !is8, P.lists + 2 * (size_t)P.list_cap, P.list_count + 2, t);
+    wave_append(bf && is8, P.lists + 3 * (size_t)P.list_cap, P.list_count + 3, t);
+}
+
+// Workgroup b of a list-driven launch takes items of its XCD's eighth of the
+// list (b & 7 picks the eighth, b >> 3 strides inside it), so that
+// consecutive items -- neighbouring tiles of one image -- share an L2.
+struct ListWalk {
+    const int32_t *list;
+    int cnt, eighth, stride, base, first;
+    __device__ ListWalk(const StepParams &P, int which) {
+        cnt = P.list_count[which];
+        list = P.lists + (size_t)which * P.list_cap;
+        eighth = (cnt + 7) >> 3;
+        stride = (int)(gridDim.x >> 3);
+        base = (int)(blockIdx.x & 7) * eighth;
+        first = (int)(blockIdx.x >> 3);
+    }
+};
+
 template <int K, int TW, int TH>
-__global__ __launch_bounds__(kThreads) void k_sweep(StepParams P, int tbeg, int tcount, int per_xcd) {
-    __shared__ int32_t lds[((TW + 2) * (TH + 2) + 3) / 4 * 4 + K * TW * TH];
+__global__ __launch_bounds__(kThreads) void k_sweep(StepParams P, int which) {
+    __shared__ int32_t lds[(2 + K) * (TW + 2) * (TH + 2)];
     __shared__ int s_red[4];
-    const int t = xcd_tile(blockIdx.x, tbeg, tcount, per_xcd);
-    if (t < 0) return;
-    const int slot = P.tile_slot[t];
-    InstState *S = &P.st[slot];
-    if (S->phase != kSweep) return;
-    const InstDesc D = P.desc[slot];
-    const int tl = P.tile_local[t];
-    if (tl >= D.ntiles) return;
-    sweep_tile<K, TW, TH>(P, D, S, t, tl, lds, s_red);
+    const ListWalk w(P, which);
+    for (int i = w.first; i < w.eighth && w.base + i < w.cnt; i += w.stride) {
+        const int t = w.list[w.base + i];
+        __syncthreads();  // the previous tile's LDS is no longer in use
+        const int slot = P.tile_slot[t];
+        InstState *S = &P.st[slot];
+        if (S->phase != kSweep) continue;
+        const InstDesc D = P.desc[slot];
+        const int tl = P.tile_local[t];
+        if (tl >= D.ntiles) continue;
+        sweep_tile<K, TW, TH>(P, D, S, t, tl, lds, s_red);
+    }
 }
 
 template <int K, int TW, int TH>
-__global__ __launch_bounds__(kThreads) void k_bfs(StepParams P, int tbeg, int tcount, int per_xcd) {
+__global__ __launch_bounds__(kThreads) void k_bfs(StepParams P, int which) {
     __shared__ int32_t lds[2 * (TW + 2) * (TH + 2)];
     __shared__ int s_red[4];
     __shared__ unsigned long long s_sum;
-    const int t = xcd_tile(blockIdx.x, tbeg, tcount, per_xcd);
-    if (t < 0) return;
-    const int slot = P.tile_slot[t];
-    InstState *S = &P.st[slot];
-    const int phase = S->phase;
-    if (phase != kInit && phase != kRelabel && phase != kCut) return;
-    const InstDesc D = P.desc[slot];
-    const int tl = P.tile_local[t];
-    if (tl >= D.ntiles) return;
-    const int sub = S->sub, kk = S->k;
-    if (phase == kInit)
-        init_tile<K, TW, TH>(P, D, S, t, tl, s_red, &s_sum);
-    else if (phase == kRelabel)
-        relabel_tile<K, TW, TH>(P, D, S, t, tl, sub, lds, s_red);
-    else
-        cut_tile<K, TW, TH>(P, D, S, t, tl, sub, kk, lds, s_red, &s_sum);
+    const ListWalk w(P, which);
+    for (int i = w.first; i < w.eighth && w.base + i < w.cnt; i += w.stride) {
+        const int t = w.list[w.base + i];
+        __syncthreads();
+        const int slot = P.tile_slot[t];
+        InstState *S = &P.st[slot];
+        const int phase = S->phase;
+        if (phase != kInit && phase != kRelabel && phase != kCut) continue;
+        const InstDesc D = P.desc[slot];
+        const int tl = P.tile_local[t];
+        if (tl >= D.ntiles) continue;
+        const int sub = S->sub, kk = S->k;
+        if (phase == kInit)
+            init_tile<K, TW, TH>(P, D, S, t, tl, s_red, &s_sum);
+        else if (phase == kRelabel)
+            relabel_tile<K, TW, TH>(P, D, S, t, tl, sub, lds, s_red);
+        else
+            cut_tile<K, TW, TH>(P, D, S, t, tl, sub, kk, lds, s_red, &s_sum);
+    }
 }
 
-__global__ __launch_bounds__(kThreads) void k_control(StepParams P) { control(P); }
+__global__ __launch_bounds__(kThreads) void k_control(StepParams P) {
+    control(P);
+    if (threadIdx.x < 4) P.list_count[threadIdx.x] = 0;  // the next superstep compacts afresh
+}
 
 // Nested masks to one byte per pixel: the number of lambdas whose minimal
 // source side holds the pixel (the sets shrink as lambda grows, so mask k is
@@ -820,23 +917,27 @@ int launch_finalize(const int32_t *sub_status, const int64_t *meta, int n_user, 
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
+// Workgroups of a list-driven launch: enough to fill the device, a multiple of 8.
+static int list_grid(int tiles) { return 8 * ((std::min(tiles, 2048) + 7) / 8); }
+
 template <int TW, int TH>
 static int launch_tw(const StepParams &p, hipStream_t s, void *const *ev) {
     const dim3 block(kThreads);
-    const int pc4 = (p.t4_count + 7) / 8, pc8 = (p.t8_count + 7) / 8;
     int sweeps = 0;
+    if (p.ntiles == 0) return 0;
+    hipLaunchKernelGGL(k_compact, dim3((p.ntiles + kThreads - 1) / kThreads), block, 0, s, p);
     if (ev) (void)hipEventRecord((hipEvent_t)ev[0], s);
     if (p.t4_count) {
-        hipLaunchKernelGGL((k_sweep<4, TW, TH>), dim3(8 * pc4), block, 0, s, p, p.t4_begin, p.t4_count, pc4);
+        hipLaunchKernelGGL((k_sweep<4, TW, TH>), dim3(list_grid(p.t4_count)), block, 0, s, p, 0);
         ++sweeps;
     }
     if (p.t8_count) {
-        hipLaunchKernelGGL((k_sweep<8, TW, TH>), dim3(8 * pc8), block, 0, s, p, p.t8_begin, p.t8_count, pc8);
+        hipLaunchKernelGGL((k_sweep<8, TW, TH>), dim3(list_grid(p.t8_count)), block, 0, s, p, 1);
         ++sweeps;
     }
     if (ev) (void)hipEventRecord((hipEvent_t)ev[1], s);
-    if (p.t4_count) hipLaunchKernelGGL((k_bfs<4, TW, TH>), dim3(8 * pc4), block, 0, s, p, p.t4_begin, p.t4_count, pc4);
-    if (p.t8_count) hipLaunchKernelGGL((k_bfs<8, TW, TH>), dim3(8 * pc8), block, 0, s, p, p.t8_begin, p.t8_count, pc8);
+    if (p.t4_count) hipLaunchKernelGGL((k_bfs<4, TW, TH>), dim3(list_grid(p.t4_count)), block, 0, s, p, 2);
+    if (p.t8_count) hipLaunchKernelGGL((k_bfs<8, TW, TH>), dim3(list_grid(p.t8_count)), block, 0, s, p, 3);
     if (ev) (void)hipEventRecord((hipEvent_t)ev[2], s);
     hipLaunchKernelGGL(k_control, dim3(1), block, 0, s, p);
     if (ev) (void)hipEventRecord((hipEvent_t)ev[3], s);
