@@ -71,7 +71,8 @@ typedef struct pmf_options {
                                 /*   1 = every lambda solved from scratch, all in   */
                                 /*   parallel; >= L = one warm-started chain; 0 =   */
                                 /*   the smallest chunk whose state fits in memory  */
-    int32_t reserved[5];
+    int32_t exchange_rounds;    /* relabel/cut passes: halo re-reads per tile visit  */
+    int32_t reserved[4];
 } pmf_options;
 
 /* One (image, seed) problem and its lambda schedule.  All pointers are device
@@ -231,6 +232,14 @@ int pmf_session_query(pmf_handle *h, pmf_session_info *out);
  * NULL) receives the index of the first offending instance.  Returns PMF_OK
  * or PMF_EINVAL. */
 int pmf_check_instances(const pmf_instance *inst, int32_t n_inst, int32_t *first_bad);
+
+/* Per device instance (slot) counters of the last solve or session, for
+ * tuning and diagnosis: out (host, int64 [max_slots][8]) receives, for every
+ * slot below max_slots, { finished (0/1), supersteps, sweep supersteps,
+ * completed global relabels, relaxation passes, lambdas done, pixels swept,
+ * pixels relaxed }.  In a pmf_solve_batch the chunks of caller instance i are
+ * consecutive slots in caller order.  *n_slots = slots in use. */
+int pmf_slot_stats(pmf_handle *h, int64_t *out, int32_t max_slots, int32_t *n_slots);
 
 /* Counters of the last solve. */
 int pmf_get_stats(pmf_handle *h, pmf_stats *out);

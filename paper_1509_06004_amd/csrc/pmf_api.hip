@@ -35,6 +35,7 @@ bool valid_options(const pmf_options &o) {
     if (o.inner_iters < 1 || o.inner_iters > 4096) return false;
     if (o.sweeps_per_relabel < 1 || o.sweeps_per_relabel > 1 << 20) return false;
     if (o.local_bfs_iters < 1 || o.local_bfs_iters > 1 << 20) return false;
+    if (o.exchange_rounds < 1 || o.exchange_rounds > 64) return false;
     if (o.steps_per_sync < 1 || o.steps_per_sync > 1 << 16) return false;
     if (o.max_supersteps < 1) return false;
     if (o.order != 0 && o.order != 1) return false;
@@ -263,6 +264,7 @@ int open_session(pmf_handle *h, int slots, size_t pool_bytes) {
     P.inner_iters = h->opt.inner_iters;
     P.sweeps_per_relabel = h->opt.sweeps_per_relabel;
     P.local_bfs_iters = h->opt.local_bfs_iters;
+    P.exchange_rounds = h->opt.exchange_rounds;
     P.max_steps = h->opt.max_supersteps;
     h->pool_base = off;
     // the work list is sized for pool_bytes, so the pool must not exceed it
@@ -551,6 +553,7 @@ void pmf_default_options(pmf_options *o) {
     o->inner_iters = 16;
     o->sweeps_per_relabel = 8;
     o->local_bfs_iters = 64;
+    o->exchange_rounds = 4;
     o->steps_per_sync = 32;
     o->max_supersteps = 2000000;
     o->use_graph = 1;
@@ -585,6 +588,7 @@ int pmf_create(const pmf_options *opt, void *stream, void *workspace, size_t ws_
     if (o.tile_w == 0) o.tile_w = 32;
     if (o.tile_h == 0) o.tile_h = 1024 / o.tile_w;
     if (o.max_slots == 0) o.max_slots = 4096;
+    if (o.exchange_rounds == 0) o.exchange_rounds = 1;
     if (!valid_options(o)) return PMF_EINVAL;
     if (workspace && ws_bytes == 0) return PMF_EINVAL;
     pmf_handle *h = new (std::nothrow) pmf_handle();
@@ -901,6 +905,28 @@ int pmf_session_query(pmf_handle *h, pmf_session_info *out) {
     for (const Slot &s : h->slots) {
         out->admitted += s.live;
         out->running += s.live && !s.finished;
+    }
+    return PMF_OK;
+}
+
+int pmf_slot_stats(pmf_handle *h, int64_t *out, int32_t max_slots, int32_t *n_slots) {
+    if (!h || max_slots < 0 || (max_slots > 0 && !out)) return PMF_EINVAL;
+    const int n = h->open ? h->max_slots : 0;
+    if (n_slots) *n_slots = n;
+    for (int i = 0; i < std::min(n, (int)max_slots); ++i) {
+        int64_t *o = out + 8 * (size_t)i;
+        const Slot &s = h->slots[i];
+        std::memset(o, 0, 8 * sizeof(int64_t));
+        if (!s.live || !s.finished) continue;
+        const InstState &x = h->pinned_state[i];
+        o[0] = 1;
+        o[1] = x.steps;
+        o[2] = x.sweeps;
+        o[3] = x.relabels;
+        o[4] = x.passes;
+        o[5] = x.k;
+        o[6] = x.px_sweep;
+        o[7] = x.px_relabel;
     }
     return PMF_OK;
 }

@@ -91,6 +91,7 @@ struct StepParams {
     int32_t inner_iters;
     int32_t sweeps_per_relabel;
     int32_t local_bfs_iters;
+    int32_t exchange_rounds;
     int64_t max_steps;
 };
 

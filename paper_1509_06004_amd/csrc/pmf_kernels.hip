@@ -209,25 +209,19 @@ __device__ void init_tile(const StepParams &P, const InstDesc &D, InstState *S, 
 // ---------------------------------------------------------------------------
 // kSweep: tile-local push/relabel iterations in LDS.
 //
-// Residuals r_k and excess e of the tile live in LDS planes indexed like the
-// height plane, with a one-pixel halo.  Each inner iteration has two phases
-// separated by a barrier:
-//   push:    every active pixel p pushes d = min(e, r) along admissible arcs
-//            (h(p) = h(q) + 1; to the sink whenever rt > 0).  It writes both
-//            residuals of the arc pair, r(p->q) -= d and r(q->p) += d, without
-//            atomics: heights do not change during this phase, so two
-//            neighbours never both see the other as admissible, and every
-//            residual word has at most one writer.  Excess moves with LDS
-//            atomics (several neighbours may push into one pixel).  A push to
-//            a halo pixel (another tile) accumulates in the halo cell's
-//            residual word of the reverse arc, which is exactly the amount
-//            handed over.
-//   relabel: an active pixel with no admissible arc takes height
-//            1 + min h(q) over its residual arcs (H_INF when none is below the
-//            height cap).
-// An inactive pixel costs two LDS reads per iteration.  At the end the tile
-// is written back and the halo accumulators go to the neighbours' inboxes
-// with one atomicAdd per nonzero word.
+// The tile's residuals (one record of K words per cell, so that a pixel reads
+// all of them at once), excess and heights live in LDS with a one-pixel halo.
+// Every inner iteration is one phase: each active pixel p (e > 0, h < H_INF)
+// pushes d = min(e, r) to the sink when rt > 0 and along admissible arcs
+// (h(p) = h(q) + 1), then, if excess is left and no admissible arc, relabels
+// to 1 + min h(q) over its residual arcs.  All residual and excess updates are
+// LDS atomics without return: whatever the interleaving of neighbours, every
+// update is applied exactly once, a pixel never sends more than the excess and
+// residual it read (other threads only add to those), so the bookkeeping stays
+// exact and non-negative.  Labels are only a guide here; maximality is
+// certified by the exact global relabel.  A push to a halo pixel (another
+// tile) lands in the halo cell's word of the reverse arc, i.e. exactly the
+// amount handed over; those words go to the neighbours' inboxes at the end.
 // ---------------------------------------------------------------------------
 template <int K, int TW, int TH>
 __device__ void sweep_tile(const StepParams &P, const InstDesc &D, InstState *S, int tg, int tl,
@@ -245,7 +239,7 @@ __device__ void sweep_tile(const StepParams &P, const InstDesc &D, InstState *S,
     const int hcap = n + 1;  // no exact distance to t exceeds n
     int32_t *sh_h = lds;             // [HALO] heights
     int32_t *sh_e = lds + HALO;      // [HALO] excess (tile cells only)
-    int32_t *sh_r = lds + 2 * HALO;  // [K][HALO] residuals; halo cells: pushes handed over
+    int32_t *sh_r = lds + 2 * HALO;  // [HALO][K] residuals; halo cells: pushes handed over
     __shared__ int s_nb[9];
 
     if (tid < 9) s_nb[tid] = 0;
@@ -258,7 +252,7 @@ __device__ void sweep_tile(const StepParams &P, const InstDesc &D, InstState *S,
         const int c = hy * HW + hx;
         sh_h[c] = (gx >= 0 && gx < W && gy >= 0 && gy < H) ? D.h[gy * W + gx] : kHInf;
 #pragma unroll
-        for (int k = 0; k < K; ++k) sh_r[k * HALO + c] = 0;
+        for (int k = 0; k < K; ++k) sh_r[c * K + k] = 0;
     }
     int rt[PPT], h[PPT];
     bool valid[PPT];
@@ -268,10 +262,14 @@ __device__ void sweep_tile(const StepParams &P, const InstDesc &D, InstState *S,
         const int gx = x0 + lx, gy = y0 + ly;
         const int c = (ly + 1) * HW + lx + 1;
         valid[j] = gx < W && gy < H;
+        int e = 0, r[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) r[k] = 0;
+        rt[j] = 0;
+        h[j] = kHInf;
         if (valid[j]) {
             const int p = gy * W + gx;
-            int e = D.e[p];
-            int r[K];
+            e = D.e[p];
 #pragma unroll
             for (int k = 0; k < K; ++k) r[k] = D.r[(size_t)k * n + p];
             rt[j] = D.rt[p];
@@ -291,79 +289,83 @@ __device__ void sweep_tile(const StepParams &P, const InstDesc &D, InstState *S,
                     r[k] += v;
                 }
             }
-            sh_e[c] = e;
-#pragma unroll
-            for (int k = 0; k < K; ++k) sh_r[k * HALO + c] = r[k];
-        } else {
-            rt[j] = 0;
-            h[j] = kHInf;
-            sh_e[c] = 0;
-#pragma unroll
-            for (int k = 0; k < K; ++k) sh_r[k * HALO + c] = 0;
         }
+        sh_e[c] = e;
+#pragma unroll
+        for (int k = 0; k < K; ++k) sh_r[c * K + k] = r[k];
         sh_h[c] = h[j];
     }
     __syncthreads();
 
+    // pixels are processed in groups of GB: every read of a group is issued
+    // before any is used (GB bounds the registers this takes)
+    constexpr int GB = K == 8 ? 2 : 4;
+    static_assert(PPT % GB == 0, "group size must divide the pixels per thread");
     for (int it = 0; it < P.inner_iters; ++it) {
-        // push
-#pragma unroll
-        for (int j = 0; j < PPT; ++j) {
-            if (h[j] >= kHInf) continue;
-            const int ly = ly0 + j * RPI;
-            const int c = (ly + 1) * HW + lx + 1;
-            int e = sh_e[c];
-            if (e <= 0) continue;
-            int pushed = 0;
-            if (rt[j] > 0) {
-                const int d = e < rt[j] ? e : rt[j];
-                e -= d;
-                rt[j] -= d;
-                pushed += d;
-            }
-#pragma unroll
-            for (int k = 0; k < K; ++k) {
-                if (e <= 0) break;
-                const int r = sh_r[k * HALO + c];
-                if (r <= 0) continue;
-                const int q = c + DYk(k) * HW + DXk(k);
-                if (sh_h[q] != h[j] - 1) continue;
-                const int d = e < r ? e : r;
-                e -= d;
-                pushed += d;
-                sh_r[k * HALO + c] = r - d;
-                sh_r[(k ^ 1) * HALO + q] += d;
-                const int nx = lx + DXk(k), ny = ly + DYk(k);
-                if (nx >= 0 && nx < TW && ny >= 0 && ny < TH) atomicAdd(&sh_e[q], d);
-            }
-            if (pushed) atomicSub(&sh_e[c], pushed);
-        }
-        __syncthreads();
-        // relabel stuck pixels
         int any = 0;
 #pragma unroll
-        for (int j = 0; j < PPT; ++j) {
-            if (h[j] >= kHInf) continue;
-            const int c = (ly0 + j * RPI + 1) * HW + lx + 1;
-            if (sh_e[c] <= 0) continue;
-            bool adm = rt[j] > 0;
-            int mn = kHInf;
+        for (int g = 0; g < PPT; g += GB) {
+            int e[GB], r[GB][K], hq[GB][K];
 #pragma unroll
-            for (int k = 0; k < K; ++k) {
-                if (sh_r[k * HALO + c] > 0) {
-                    const int hq = sh_h[c + DYk(k) * HW + DXk(k)];
-                    if (hq == h[j] - 1) adm = true;
-                    if (hq < kHInf && hq + 1 < mn) mn = hq + 1;
+            for (int b = 0; b < GB; ++b) {
+                const int c = (ly0 + (g + b) * RPI + 1) * HW + lx + 1;
+                e[b] = sh_e[c];
+#pragma unroll
+                for (int k = 0; k < K; ++k) {
+                    r[b][k] = sh_r[c * K + k];
+                    hq[b][k] = sh_h[c + DYk(k) * HW + DXk(k)];
                 }
             }
-            if (!adm) {
-                h[j] = mn >= hcap ? kHInf : mn;
-                sh_h[c] = h[j];
+#pragma unroll
+            for (int b = 0; b < GB; ++b) {
+                const int j = g + b;
+                if (e[b] <= 0 || h[j] >= kHInf) continue;
+                const int ly = ly0 + j * RPI;
+                const int c = (ly + 1) * HW + lx + 1;
+                int ex = e[b], pushed = 0;
+                if (rt[j] > 0) {
+                    const int d = ex < rt[j] ? ex : rt[j];
+                    ex -= d;
+                    rt[j] -= d;
+                    pushed += d;
+                }
+                int mn = kHInf;
+                bool adm = false;
+#pragma unroll
+                for (int k = 0; k < K; ++k) {
+                    if (r[b][k] <= 0) continue;
+                    if (hq[b][k] == h[j] - 1 && ex > 0) {
+                        const int d = ex < r[b][k] ? ex : r[b][k];
+                        ex -= d;
+                        pushed += d;
+                        r[b][k] -= d;
+                        const int q = c + DYk(k) * HW + DXk(k);
+                        atomicSub(&sh_r[c * K + k], d);
+                        atomicAdd(&sh_r[q * K + (k ^ 1)], d);
+                        const int nx = lx + DXk(k), ny = ly + DYk(k);
+                        if (nx >= 0 && nx < TW && ny >= 0 && ny < TH) atomicAdd(&sh_e[q], d);
+                    }
+                    if (r[b][k] > 0) {
+                        adm |= hq[b][k] == h[j] - 1;
+                        if (hq[b][k] < kHInf && hq[b][k] + 1 < mn) mn = hq[b][k] + 1;
+                    }
+                }
+                if (pushed) atomicSub(&sh_e[c], pushed);
+                if (ex > 0 && rt[j] == 0 && !adm) {
+                    // stuck: lift above the lowest residual neighbour
+                    h[j] = mn >= hcap ? kHInf : mn;
+                    sh_h[c] = h[j];
+                }
+                any |= h[j] < kHInf;
             }
-            any |= h[j] < kHInf;
         }
-        if (!__syncthreads_or(any)) break;
+        // progress check every 2 rounds (updates are atomic, so rounds need
+        // no barrier between them)
+        if ((it & 1) == 1 || it + 1 == P.inner_iters) {
+            if (!__syncthreads_or(any)) break;
+        }
     }
+    __syncthreads();
 
     // write back
     int active = 0;
@@ -377,7 +379,7 @@ __device__ void sweep_tile(const StepParams &P, const InstDesc &D, InstState *S,
         int rm = (rt[j] > 0 ? kRtBit : 0) | (e > 0 ? kEBit : 0);
 #pragma unroll
         for (int k = 0; k < K; ++k) {
-            const int r = sh_r[k * HALO + c];
+            const int r = sh_r[c * K + k];
             D.r[(size_t)k * n + p] = r;
             if (r > 0) rm |= 1 << k;
         }
@@ -388,7 +390,7 @@ __device__ void sweep_tile(const StepParams &P, const InstDesc &D, InstState *S,
         active |= e > 0 && h[j] < kHInf;
     }
     // hand pushes into halo cells to the neighbour tiles' inboxes: the word
-    // r_j of halo cell q with q + d_j inside the tile holds what q received
+    // k of halo cell q with q + d_k inside the tile holds what q received
     for (int i = tid; i < G::RING; i += kThreads) {
         int hx, hy;
         G::ring(i, hx, hy);
@@ -398,7 +400,7 @@ __device__ void sweep_tile(const StepParams &P, const InstDesc &D, InstState *S,
         for (int k = 0; k < K; ++k) {
             const int ix = hx + DXk(k), iy = hy + DYk(k);
             if (ix < 1 || ix > TW || iy < 1 || iy > TH) continue;
-            const int v = sh_r[k * HALO + c];
+            const int v = sh_r[c * K + k];
             if (v > 0 && gx >= 0 && gx < W && gy >= 0 && gy < H) {
                 atomicAdd(&D.inbox[(size_t)k * n + gy * W + gx], v);
                 const int dtx = hx == 0 ? 0 : (hx == HW - 1 ? 2 : 1);
@@ -510,27 +512,72 @@ __device__ void relabel_tile(const StepParams &P, const InstDesc &D, InstState *
         sh_d[hy * HW + hx] = v;
     }
     __syncthreads();
+    // After the first pass of a relabel every stored label is an upper bound
+    // of the true distance that only decreases, so the tile may publish its
+    // improved labels and take newer halo labels written by neighbour tiles
+    // during this same launch, several times per visit (exchange rounds).
+    // Stale reads only delay convergence.  The first pass keeps one round: its
+    // neighbours' stored labels are still those of the previous phase.
+    int dpub[PPT];
+#pragma unroll
+    for (int j = 0; j < PPT; ++j) dpub[j] = d0[j];
+    const int rounds = first ? 1 : P.exchange_rounds;
+    for (int round = 0; round < rounds; ++round) {
+    // Relaxation rounds; the convergence check (a barrier) runs every 4
+    // rounds.  Labels only decrease and every value read is an upper bound of
+    // the true distance, so rounds need no barrier between them; a window in
+    // which no thread changed a label proves the local fixed point.
+    int ch = 0;
     for (int it = 0; it < P.local_bfs_iters; ++it) {
-        int ch = 0;
+        int v[PPT][K];
+#pragma unroll
+        for (int j = 0; j < PPT; ++j) {
+            const int c = (ly0 + j * RPI + 1) * HW + lx + 1;
+#pragma unroll
+            for (int k = 0; k < K; ++k) v[j][k] = sh_d[c + DYk(k) * HW + DXk(k)];
+        }
 #pragma unroll
         for (int j = 0; j < PPT; ++j) {
             if (d[j] <= 1) continue;
-            const int ly = ly0 + j * RPI;
             int nd = d[j];
 #pragma unroll
-            for (int k = 0; k < K; ++k) {
-                if (rm[j] & (1u << k)) {
-                    const int v = sh_d[(ly + 1 + DYk(k)) * HW + lx + 1 + DXk(k)];
-                    if (v < kHInf && v + 1 < nd) nd = v + 1;
-                }
-            }
+            for (int k = 0; k < K; ++k)
+                if ((rm[j] & (1u << k)) && v[j][k] < kHInf && v[j][k] + 1 < nd) nd = v[j][k] + 1;
             if (nd < d[j]) {
                 d[j] = nd;
-                sh_d[(ly + 1) * HW + lx + 1] = nd;
+                sh_d[(ly0 + j * RPI + 1) * HW + lx + 1] = nd;
                 ch = 1;
             }
         }
-        if (!__syncthreads_or(ch)) break;
+        if ((it & 3) == 3 || it + 1 == P.local_bfs_iters) {
+            if (!__syncthreads_or(ch)) break;
+            ch = 0;
+        }
+    }
+    if (round + 1 == rounds) break;
+    // publish, then take the neighbours' newer labels
+#pragma unroll
+    for (int j = 0; j < PPT; ++j) {
+        const int ly = ly0 + j * RPI;
+        const int gx = x0 + lx, gy = y0 + ly;
+        if (gx < W && gy < H && d[j] < dpub[j]) {
+            __hip_atomic_store(&D.h[gy * W + gx], d[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            dpub[j] = d[j];
+        }
+    }
+    int got = 0;
+    for (int i = tid; i < G::RING; i += kThreads) {
+        int hx, hy;
+        G::ring(i, hx, hy);
+        const int gx = x0 + hx - 1, gy = y0 + hy - 1;
+        if (gx < 0 || gx >= W || gy < 0 || gy >= H) continue;
+        const int v = ld_agent(&D.h[gy * W + gx]);
+        if (v < sh_d[hy * HW + hx]) {
+            sh_d[hy * HW + hx] = v;
+            got = 1;
+        }
+    }
+    if (!__syncthreads_or(got)) break;
     }
     int changed = first ? 1 : 0;
     bool act[PPT];
@@ -540,10 +587,8 @@ __device__ void relabel_tile(const StepParams &P, const InstDesc &D, InstState *
         const int gx = x0 + lx, gy = y0 + ly;
         act[j] = (rm[j] & kEBit) && d[j] < kHInf;  // rm = 0 outside the image
         if (gx >= W || gy >= H) continue;
-        if (first || d[j] != d0[j]) {
-            D.h[gy * W + gx] = d[j];
-            changed = 1;
-        }
+        if (first || d[j] != d0[j]) changed = 1;
+        if (first || d[j] != dpub[j]) D.h[gy * W + gx] = d[j];
     }
     const int tchg = __syncthreads_or(changed);
     const int tcnt = block_count_ballot(act, s_red);
@@ -579,23 +624,24 @@ __device__ void cut_tile(const StepParams &P, const InstDesc &D, InstState *S, i
         return;
     }
     uint8_t *mask = D.masks + (size_t)kk * n;
-    int32_t *sh_m = lds;
-    int32_t *sh_rm = lds + G::HALO;
+    // one LDS word per cell: the residual bits, and bit 15 = reached
+    constexpr int kReached = 1 << 15;
+    int32_t *sh_w = lds;
     const bool raise = first && kk + 1 < D.L;
     const int dlam = raise ? D.lambdas[kk + 1] - D.lambdas[kk] : 0;
-    int m[PPT], m0[PPT];
+    int m[PPT], m0[PPT], rmv[PPT];
     long long se = 0;
 #pragma unroll
     for (int j = 0; j < PPT; ++j) {
         const int ly = ly0 + j * RPI;
         const int gx = x0 + lx, gy = y0 + ly;
-        int rmv = 0;
+        rmv[j] = 0;
         m[j] = 0;
         if (gx < W && gy < H) {
             const int p = gy * W + gx;
-            rmv = D.rmask[p];
+            rmv[j] = D.rmask[p];
             if (first) {
-                m[j] = (rmv & kEBit) ? 1 : 0;
+                m[j] = (rmv[j] & kEBit) ? 1 : 0;
                 if (m[j]) se += D.e[p];
                 if (dlam > 0) {
                     const int sd = D.seed ? (int)D.seed[p] : 0;
@@ -603,7 +649,7 @@ __device__ void cut_tile(const StepParams &P, const InstDesc &D, InstState *S, i
                     if (sl > 0) {
                         const int nrt = D.rt[p] + sl * dlam;
                         D.rt[p] = nrt;
-                        if (nrt > 0 && !(rmv & kRtBit)) D.rmask[p] = (uint16_t)(rmv | kRtBit);
+                        if (nrt > 0 && !(rmv[j] & kRtBit)) D.rmask[p] = (uint16_t)(rmv[j] | kRtBit);
                     }
                 }
             } else {
@@ -611,45 +657,85 @@ __device__ void cut_tile(const StepParams &P, const InstDesc &D, InstState *S, i
             }
         }
         m0[j] = m[j];
-        sh_m[(ly + 1) * HW + lx + 1] = m[j];
-        sh_rm[(ly + 1) * HW + lx + 1] = rmv;
+        sh_w[(ly + 1) * HW + lx + 1] = rmv[j] | (m[j] ? kReached : 0);
     }
     for (int i = tid; i < G::RING; i += kThreads) {
         int hx, hy;
         G::ring(i, hx, hy);
         const int gx = x0 + hx - 1, gy = y0 + hy - 1;
-        int mv = 0, rmv = 0;
+        int w = 0;
         if (gx >= 0 && gx < W && gy >= 0 && gy < H) {
             const int q = gy * W + gx;
-            rmv = D.rmask[q];
-            mv = first ? ((rmv & kEBit) ? 1 : 0) : mask[q];
+            const int rq = D.rmask[q];
+            const int mq = first ? ((rq & kEBit) ? 1 : 0) : mask[q];
+            w = rq | (mq ? kReached : 0);
         }
-        sh_m[hy * HW + hx] = mv;
-        sh_rm[hy * HW + hx] = rmv;
+        sh_w[hy * HW + hx] = w;
     }
     __syncthreads();
+    // Exchange rounds as in the relabel pass: after the first pass every stored
+    // reached bit is final once set, so newer bits of neighbour tiles written
+    // during this launch can be taken up within the visit.
+    int mpub[PPT];
+#pragma unroll
+    for (int j = 0; j < PPT; ++j) mpub[j] = m0[j];
+    const int rounds = first ? 1 : P.exchange_rounds;
+    for (int round = 0; round < rounds; ++round) {
+    // Reachability rounds, convergence checked every 4 rounds: reached bits
+    // only get set, so rounds need no barrier between them.
+    int ch = 0;
     for (int it = 0; it < P.local_bfs_iters; ++it) {
-        int ch = 0;
+        int v[PPT][K];
+#pragma unroll
+        for (int j = 0; j < PPT; ++j) {
+            const int c = (ly0 + j * RPI + 1) * HW + lx + 1;
+#pragma unroll
+            for (int k = 0; k < K; ++k) v[j][k] = sh_w[c + DYk(k) * HW + DXk(k)];
+        }
 #pragma unroll
         for (int j = 0; j < PPT; ++j) {
             if (m[j]) continue;
             const int ly = ly0 + j * RPI;
-            const int gx = x0 + lx, gy = y0 + ly;
-            if (gx >= W || gy >= H) continue;
+            if (x0 + lx >= W || y0 + ly >= H) continue;
             bool reach = false;
 #pragma unroll
-            for (int k = 0; k < K; ++k) {
-                const int a = (ly + 1 + DYk(k)) * HW + lx + 1 + DXk(k);
-                // q = p + d_k reaches p if q is reached and r(q -> p) > 0
-                reach |= sh_m[a] != 0 && ((sh_rm[a] >> (k ^ 1)) & 1);
-            }
+            for (int k = 0; k < K; ++k)  // q = p + d_k reaches p if q is reached and r(q -> p) > 0
+                reach |= (v[j][k] & kReached) && ((v[j][k] >> (k ^ 1)) & 1);
             if (reach) {
                 m[j] = 1;
-                sh_m[(ly + 1) * HW + lx + 1] = 1;
+                sh_w[(ly + 1) * HW + lx + 1] = rmv[j] | kReached;
                 ch = 1;
             }
         }
-        if (!__syncthreads_or(ch)) break;
+        if ((it & 3) == 3 || it + 1 == P.local_bfs_iters) {
+            if (!__syncthreads_or(ch)) break;
+            ch = 0;
+        }
+    }
+    if (round + 1 == rounds) break;
+    // publish, then take the neighbours' newer reached bits
+#pragma unroll
+    for (int j = 0; j < PPT; ++j) {
+        const int ly = ly0 + j * RPI;
+        const int gx = x0 + lx, gy = y0 + ly;
+        if (gx < W && gy < H && m[j] && !mpub[j]) {
+            __hip_atomic_store(&mask[gy * W + gx], (uint8_t)1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            mpub[j] = 1;
+        }
+    }
+    int got = 0;
+    for (int i = tid; i < G::RING; i += kThreads) {
+        int hx, hy;
+        G::ring(i, hx, hy);
+        const int gx = x0 + hx - 1, gy = y0 + hy - 1;
+        if (gx < 0 || gx >= W || gy < 0 || gy >= H) continue;
+        const int c = hy * HW + hx;
+        if (!(sh_w[c] & kReached) && ld_agent(&mask[gy * W + gx])) {
+            sh_w[c] |= kReached;
+            got = 1;
+        }
+    }
+    if (!__syncthreads_or(got)) break;
     }
     int changed = first ? 1 : 0;
 #pragma unroll
@@ -657,10 +743,8 @@ __device__ void cut_tile(const StepParams &P, const InstDesc &D, InstState *S, i
         const int ly = ly0 + j * RPI;
         const int gx = x0 + lx, gy = y0 + ly;
         if (gx >= W || gy >= H) continue;
-        if (first || m[j] != m0[j]) {
-            mask[gy * W + gx] = (uint8_t)m[j];
-            changed = 1;
-        }
+        if (first || m[j] != m0[j]) changed = 1;
+        if (first || m[j] != mpub[j]) mask[gy * W + gx] = (uint8_t)m[j];
     }
     const int tchg = __syncthreads_or(changed);
     long long tse = 0;

@@ -47,7 +47,8 @@ class Options(ctypes.Structure):
         ("max_slots", ctypes.c_int32),
         ("timing", ctypes.c_int32),
         ("lambda_chunk", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 5),
+        ("exchange_rounds", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 4),
     ]
 
 
@@ -122,6 +123,7 @@ def load_library() -> ctypes.CDLL:
         "pmf_check_instances": (ctypes.c_int, [ctypes.POINTER(InstanceC), ctypes.c_int32,
                                                ctypes.POINTER(ctypes.c_int32)]),
         "pmf_get_stats": (ctypes.c_int, [P, ctypes.POINTER(Stats)]),
+        "pmf_slot_stats": (ctypes.c_int, [P, P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]),
         "pmf_extract_levels": (ctypes.c_int, [P, ctypes.c_int32, P]),
         "pmf_session_open": (ctypes.c_int, [P, ctypes.c_int32, ctypes.c_size_t]),
         "pmf_session_submit": (ctypes.c_int, [P, ctypes.POINTER(InstanceC), ctypes.c_int32, P, P,
@@ -198,6 +200,17 @@ def pmf_check_instances(instances: Sequence[InstanceC]) -> Tuple[int, int]:
     bad = ctypes.c_int32(-1)
     rc = load_library().pmf_check_instances(arr, len(instances), ctypes.byref(bad))
     return rc, int(bad.value)
+
+
+def pmf_slot_stats(handle, max_slots: int = 1 << 16) -> np.ndarray:
+    """int64 [slots, 8]: finished, supersteps, sweeps, relabels, passes, lambdas
+    done, pixels swept, pixels relaxed."""
+    out = np.zeros((max_slots, 8), dtype=np.int64)
+    n = ctypes.c_int32(0)
+    rc = load_library().pmf_slot_stats(handle, out.ctypes.data, max_slots, ctypes.byref(n))
+    if rc != PMF_OK:
+        raise PmfError(rc, "pmf_slot_stats")
+    return out[:min(n.value, max_slots)]
 
 
 def pmf_get_stats(handle) -> Dict[str, int]:

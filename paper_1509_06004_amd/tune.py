@@ -23,12 +23,14 @@ from typing import Dict, List, Optional, Sequence
 
 from . import pmf
 
-KNOBS = ("tile_w", "inner_iters", "sweeps_per_relabel", "local_bfs_iters", "order", "lambda_chunk")
+KNOBS = ("tile_w", "inner_iters", "sweeps_per_relabel", "local_bfs_iters", "exchange_rounds", "order",
+         "lambda_chunk")
 SPACE = {
     "tile_w": [32, 64],
     "inner_iters": [4, 8, 16, 32],
     "sweeps_per_relabel": [2, 4, 8, 16],
     "local_bfs_iters": [16, 64, 256],
+    "exchange_rounds": [1, 2, 4, 8],
     "order": [0, 1],
     "lambda_chunk": [0, 1, 2, 4],
 }

@@ -135,7 +135,8 @@ def test_options_do_not_change_results(pmf):
     for opts in [dict(), dict(tile_w=64, tile_h=16), dict(inner_iters=1, sweeps_per_relabel=1),
                  dict(inner_iters=64, sweeps_per_relabel=32, local_bfs_iters=4), dict(order=0),
                  dict(use_graph=0, steps_per_sync=3), dict(timing=1), dict(lambda_chunk=1),
-                 dict(lambda_chunk=3), dict(lambda_chunk=100)]:
+                 dict(lambda_chunk=3), dict(lambda_chunk=100), dict(exchange_rounds=1),
+                 dict(exchange_rounds=16, local_bfs_iters=2)]:
         say("options", opts)
         flows, status, masks, _ = solve(pmf, insts, **opts)
         assert (status == 0).all()
@@ -233,4 +234,19 @@ def test_superstep_budget_times_out(pmf):
     assert int(status.cpu()[0]) == pmf.PMF_ETIMEOUT and (f == -1).any()
     for k in range(len(f)):
         assert f[k] == -1 or f[k] == O.fifo_pr(insts[0], int(insts[0].lambdas[k]))[0]
+    s.close()
+
+
+def test_slot_stats_describe_the_split(pmf):
+    """Per-slot counters: with every lambda in its own chunk, config 1 uses 20
+    slots, each finished with one lambda done and positive work counters."""
+    import torch
+    insts = W.config1()
+    s = pmf.Solver(lambda_chunk=1, max_supersteps=400000)
+    s.solve(pmf.to_device(insts))
+    torch.cuda.synchronize()
+    st = pmf.pmf_slot_stats(s.handle)
+    assert st.shape == (20, 8)
+    assert (st[:, 0] == 1).all() and (st[:, 5] == 1).all()
+    assert (st[:, 1] > 0).all() and (st[:, 4] >= 4).all()  # >= 2 relabel + 2 cut passes
     s.close()

@@ -30,7 +30,8 @@ def test_tuner_trials_agree(tmp_path):
              W.tiny_random(rng, 40, 90, 8, cmax=200, L=3, p_seed=0.03, lam_max=60)]
     dev = pmf.to_device(insts)
     space = {"tile_w": [32, 64], "inner_iters": [4, 16], "sweeps_per_relabel": [2, 8],
-             "local_bfs_iters": [16, 64], "order": [0, 1], "lambda_chunk": [1, 3]}
+             "local_bfs_iters": [16, 64], "exchange_rounds": [1, 3], "order": [0, 1],
+             "lambda_chunk": [1, 3]}
     out = T.tune(dev, repeats=1, space=space)
     assert out["rejected"] == []
     assert len(out["trials"]) >= 6
