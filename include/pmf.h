@@ -244,6 +244,17 @@ int pmf_slot_stats(pmf_handle *h, int64_t *out, int32_t max_slots, int32_t *n_sl
 /* Counters of the last solve. */
 int pmf_get_stats(pmf_handle *h, pmf_stats *out);
 
+/* Superstep trace of the last solve or session run with options.timing = 1
+ * (empty otherwise): one row of PMF_TRACE_COLS int64 per superstep, { tiles
+ * swept (4-connected instances), tiles swept (8-connected), tiles passed by
+ * the relabel / cut / init kernels (4-connected), the same (8-connected),
+ * sweep kernel ns, relabel / cut / init kernel ns, control kernel ns, 0 }.
+ * Copies min(rows, max_rows) rows to out (host) and returns the number of
+ * rows recorded, or -PMF_EINVAL for a null handle, negative max_rows, or a
+ * null out with max_rows > 0. */
+#define PMF_TRACE_COLS 8
+int64_t pmf_get_trace(pmf_handle *h, int64_t *out, int64_t max_rows);
+
 #ifdef __cplusplus
 }
 #endif

@@ -182,6 +182,7 @@ struct pmf_handle {
     pmf_stats stats;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;  // bracket every launch group (device time)
     hipEvent_t kev[4] = {nullptr, nullptr, nullptr, nullptr};  // per-kernel timing mode
+    std::vector<int64_t> trace;  // timing mode: PMF_TRACE_COLS values per superstep
     // pmf_solve_batch: caller instance i = slots [user_first[i], user_first[i+1]),
     // lambda k of it in slot user_first[i] + k / chunk at index k % chunk
     bool batch = false;
@@ -278,6 +279,7 @@ int open_session(pmf_handle *h, int slots, size_t pool_bytes) {
     h->wl_dirty = true;
     h->epoch_steps = 0;
     std::memset(&h->stats, 0, sizeof(h->stats));
+    h->trace.clear();
     h->stats.device_bytes = (int64_t)h->arena_bytes;
     // every slot starts idle; the completion counter at zero
     if (hipMemsetAsync(P.st, 0, sizeof(InstState) * (size_t)slots, h->stream) != hipSuccess ||
@@ -425,11 +427,18 @@ int submit(pmf_handle *h, const pmf_instance *inst, int n, int64_t *flows_out, i
     return PMF_OK;
 }
 
+// Timing mode, after a superstep has completed: kernel times from the events
+// and one trace row (list sizes of that superstep and the three times).
 void read_kernel_events(pmf_handle *h) {
     float a = 0.f, b = 0.f, c = 0.f;
     if (hipEventElapsedTime(&a, h->kev[0], h->kev[1]) == hipSuccess) h->stats.sweep_ns += (int64_t)(a * 1e6);
     if (hipEventElapsedTime(&b, h->kev[1], h->kev[2]) == hipSuccess) h->stats.bfs_ns += (int64_t)(b * 1e6);
     if (hipEventElapsedTime(&c, h->kev[2], h->kev[3]) == hipSuccess) h->stats.control_ns += (int64_t)(c * 1e6);
+    int32_t cnt[4] = {0, 0, 0, 0};
+    if (hipMemcpy(cnt, h->P.list_count + 4, sizeof(cnt), hipMemcpyDeviceToHost) != hipSuccess) return;
+    const int64_t row[PMF_TRACE_COLS] = {cnt[0], cnt[1], cnt[2], cnt[3], (int64_t)(a * 1e6), (int64_t)(b * 1e6),
+                                         (int64_t)(c * 1e6), 0};
+    h->trace.insert(h->trace.end(), row, row + PMF_TRACE_COLS);
 }
 
 // Launch `steps` supersteps, wait, and collect the slots that finished.
@@ -935,6 +944,14 @@ int pmf_get_stats(pmf_handle *h, pmf_stats *out) {
     if (!h || !out) return PMF_EINVAL;
     *out = h->stats;
     return PMF_OK;
+}
+
+int64_t pmf_get_trace(pmf_handle *h, int64_t *out, int64_t max_rows) {
+    if (!h || max_rows < 0 || (max_rows > 0 && !out)) return -(int64_t)PMF_EINVAL;
+    const int64_t rows = (int64_t)h->trace.size() / PMF_TRACE_COLS;
+    const int64_t n = std::min(rows, max_rows);
+    if (n > 0) std::copy(h->trace.begin(), h->trace.begin() + n * PMF_TRACE_COLS, out);
+    return rows;
 }
 
 int pmf_destroy(pmf_handle *h) {

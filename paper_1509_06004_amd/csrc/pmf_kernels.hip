@@ -39,6 +39,15 @@
 #include "pmf.h"
 #include "pmf_internal.h"
 
+// Pixels per read group of the sweep (4- and 8-connected): the registers a
+// group holds against the LDS reads in flight.
+#ifndef PMF_SWEEP_GROUP4
+#define PMF_SWEEP_GROUP4 4
+#endif
+#ifndef PMF_SWEEP_GROUP8
+#define PMF_SWEEP_GROUP8 2
+#endif
+
 namespace pmf {
 
 __device__ constexpr int DXk(int k) {
@@ -297,19 +306,30 @@ __device__ void sweep_tile(const StepParams &P, const InstDesc &D, InstState *S,
     }
     __syncthreads();
 
-    // pixels are processed in groups of GB: every read of a group is issued
-    // before any is used (GB bounds the registers this takes)
-    constexpr int GB = K == 8 ? 2 : 4;
+    // Pixels are processed in groups of GB.  A group whose pixels are all
+    // inactive in the whole wave is skipped after reading only its excess;
+    // otherwise every read of the group is issued before any is used, and the
+    // pushes and the lift are computed with selects (the only branches guard
+    // the LDS atomics of an arc, skipped when no lane pushes along it).
+    constexpr int GB = K == 8 ? PMF_SWEEP_GROUP8 : PMF_SWEEP_GROUP4;
     static_assert(PPT % GB == 0, "group size must divide the pixels per thread");
     for (int it = 0; it < P.inner_iters; ++it) {
         int any = 0;
 #pragma unroll
         for (int g = 0; g < PPT; g += GB) {
-            int e[GB], r[GB][K], hq[GB][K];
+            int e[GB];
+            bool act[GB], wact = false;
+#pragma unroll
+            for (int b = 0; b < GB; ++b) {
+                e[b] = sh_e[(ly0 + (g + b) * RPI + 1) * HW + lx + 1];
+                act[b] = e[b] > 0 && h[g + b] < kHInf;
+                wact |= act[b];
+            }
+            if (__ballot(wact) == 0ull) continue;
+            int r[GB][K], hq[GB][K];
 #pragma unroll
             for (int b = 0; b < GB; ++b) {
                 const int c = (ly0 + (g + b) * RPI + 1) * HW + lx + 1;
-                e[b] = sh_e[c];
 #pragma unroll
                 for (int k = 0; k < K; ++k) {
                     r[b][k] = sh_r[c * K + k];
@@ -319,44 +339,41 @@ __device__ void sweep_tile(const StepParams &P, const InstDesc &D, InstState *S,
 #pragma unroll
             for (int b = 0; b < GB; ++b) {
                 const int j = g + b;
-                if (e[b] <= 0 || h[j] >= kHInf) continue;
-                const int ly = ly0 + j * RPI;
-                const int c = (ly + 1) * HW + lx + 1;
-                int ex = e[b], pushed = 0;
-                if (rt[j] > 0) {
-                    const int d = ex < rt[j] ? ex : rt[j];
-                    ex -= d;
-                    rt[j] -= d;
-                    pushed += d;
-                }
+                const int c = (ly0 + j * RPI + 1) * HW + lx + 1;
+                // sink first, then the admissible arcs (h(q) = h(p) - 1) in
+                // arc order, each taking min(excess left, residual)
+                int ex = act[b] ? e[b] : 0;
+                const int dt = ex < rt[j] ? ex : rt[j];
+                ex -= dt;
+                rt[j] -= dt;
+                int pushed = dt;
+                const int hm1 = h[j] - 1;
                 int mn = kHInf;
-                bool adm = false;
 #pragma unroll
                 for (int k = 0; k < K; ++k) {
-                    if (r[b][k] <= 0) continue;
-                    if (hq[b][k] == h[j] - 1 && ex > 0) {
-                        const int d = ex < r[b][k] ? ex : r[b][k];
-                        ex -= d;
-                        pushed += d;
-                        r[b][k] -= d;
+                    const int rk = r[b][k];
+                    const bool down = hq[b][k] == hm1;
+                    const int d = down ? (rk < ex ? rk : ex) : 0;  // residuals are never negative
+                    ex -= d;
+                    pushed += d;
+                    const int cand = rk - d > 0 ? hq[b][k] + 1 : kHInf;
+                    mn = cand < mn ? cand : mn;
+                    if (d) {
                         const int q = c + DYk(k) * HW + DXk(k);
                         atomicSub(&sh_r[c * K + k], d);
                         atomicAdd(&sh_r[q * K + (k ^ 1)], d);
-                        const int nx = lx + DXk(k), ny = ly + DYk(k);
-                        if (nx >= 0 && nx < TW && ny >= 0 && ny < TH) atomicAdd(&sh_e[q], d);
-                    }
-                    if (r[b][k] > 0) {
-                        adm |= hq[b][k] == h[j] - 1;
-                        if (hq[b][k] < kHInf && hq[b][k] + 1 < mn) mn = hq[b][k] + 1;
+                        // halo cells' excess words are never read: no test needed
+                        atomicAdd(&sh_e[q], d);
                     }
                 }
                 if (pushed) atomicSub(&sh_e[c], pushed);
-                if (ex > 0 && rt[j] == 0 && !adm) {
-                    // stuck: lift above the lowest residual neighbour
-                    h[j] = mn >= hcap ? kHInf : mn;
-                    sh_h[c] = h[j];
-                }
-                any |= h[j] < kHInf;
+                // excess left means the sink arc and every admissible arc are
+                // saturated: lift above the lowest residual neighbour
+                const bool lift = ex > 0;
+                const int nh = mn >= hcap ? kHInf : mn;
+                if (lift) sh_h[c] = nh;
+                h[j] = lift ? nh : h[j];
+                any |= act[b] && h[j] < kHInf;
             }
         }
         // progress check every 2 rounds (updates are atomic, so rounds need
@@ -536,18 +553,19 @@ __device__ void relabel_tile(const StepParams &P, const InstDesc &D, InstState *
 #pragma unroll
             for (int k = 0; k < K; ++k) v[j][k] = sh_d[c + DYk(k) * HW + DXk(k)];
         }
+        // branch-free: every label is rewritten (only its owner writes it);
+        // a neighbour at H_INF gives H_INF + 1, never below the label
 #pragma unroll
         for (int j = 0; j < PPT; ++j) {
-            if (d[j] <= 1) continue;
             int nd = d[j];
 #pragma unroll
-            for (int k = 0; k < K; ++k)
-                if ((rm[j] & (1u << k)) && v[j][k] < kHInf && v[j][k] + 1 < nd) nd = v[j][k] + 1;
-            if (nd < d[j]) {
-                d[j] = nd;
-                sh_d[(ly0 + j * RPI + 1) * HW + lx + 1] = nd;
-                ch = 1;
+            for (int k = 0; k < K; ++k) {
+                const int cand = ((rm[j] >> k) & 1u) ? v[j][k] + 1 : kHInf;
+                nd = cand < nd ? cand : nd;
             }
+            ch |= nd < d[j];
+            d[j] = nd;
+            sh_d[(ly0 + j * RPI + 1) * HW + lx + 1] = nd;
         }
         if ((it & 3) == 3 || it + 1 == P.local_bfs_iters) {
             if (!__syncthreads_or(ch)) break;
@@ -692,20 +710,18 @@ __device__ void cut_tile(const StepParams &P, const InstDesc &D, InstState *S, i
 #pragma unroll
             for (int k = 0; k < K; ++k) v[j][k] = sh_w[c + DYk(k) * HW + DXk(k)];
         }
+        // branch-free; a pixel outside the image is never reached: its
+        // neighbours have no residual arc towards it
 #pragma unroll
         for (int j = 0; j < PPT; ++j) {
-            if (m[j]) continue;
-            const int ly = ly0 + j * RPI;
-            if (x0 + lx >= W || y0 + ly >= H) continue;
-            bool reach = false;
+            int reach = 0;
 #pragma unroll
             for (int k = 0; k < K; ++k)  // q = p + d_k reaches p if q is reached and r(q -> p) > 0
-                reach |= (v[j][k] & kReached) && ((v[j][k] >> (k ^ 1)) & 1);
-            if (reach) {
-                m[j] = 1;
-                sh_w[(ly + 1) * HW + lx + 1] = rmv[j] | kReached;
-                ch = 1;
-            }
+                reach |= (v[j][k] >> (k ^ 1)) & (v[j][k] >> 15);
+            const int nm = m[j] | (reach & 1);
+            ch |= nm ^ m[j];
+            m[j] = nm;
+            sh_w[(ly0 + j * RPI + 1) * HW + lx + 1] = rmv[j] | (nm << 15);
         }
         if ((it & 3) == 3 || it + 1 == P.local_bfs_iters) {
             if (!__syncthreads_or(ch)) break;
@@ -954,7 +970,12 @@ __global__ __launch_bounds__(kThreads) void k_bfs(StepParams P, int which) {
 
 __global__ __launch_bounds__(kThreads) void k_control(StepParams P) {
     control(P);
-    if (threadIdx.x < 4) P.list_count[threadIdx.x] = 0;  // the next superstep compacts afresh
+    if (threadIdx.x < 4) {
+        // keep this superstep's list sizes (read by the timing mode), then
+        // clear them: the next superstep compacts afresh
+        P.list_count[4 + threadIdx.x] = P.list_count[threadIdx.x];
+        P.list_count[threadIdx.x] = 0;
+    }
 }
 
 // Nested masks to one byte per pixel: the number of lambdas whose minimal

@@ -124,6 +124,7 @@ def load_library() -> ctypes.CDLL:
                                                ctypes.POINTER(ctypes.c_int32)]),
         "pmf_get_stats": (ctypes.c_int, [P, ctypes.POINTER(Stats)]),
         "pmf_slot_stats": (ctypes.c_int, [P, P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]),
+        "pmf_get_trace": (ctypes.c_int64, [P, P, ctypes.c_int64]),
         "pmf_extract_levels": (ctypes.c_int, [P, ctypes.c_int32, P]),
         "pmf_session_open": (ctypes.c_int, [P, ctypes.c_int32, ctypes.c_size_t]),
         "pmf_session_submit": (ctypes.c_int, [P, ctypes.POINTER(InstanceC), ctypes.c_int32, P, P,
@@ -211,6 +212,26 @@ def pmf_slot_stats(handle, max_slots: int = 1 << 16) -> np.ndarray:
     if rc != PMF_OK:
         raise PmfError(rc, "pmf_slot_stats")
     return out[:min(n.value, max_slots)]
+
+
+PMF_TRACE_COLS = 8
+TRACE_FIELDS = ("sweep_tiles4", "sweep_tiles8", "pass_tiles4", "pass_tiles8", "sweep_ns", "pass_ns",
+                "control_ns", "reserved")
+
+
+def pmf_get_trace(handle) -> np.ndarray:
+    """int64 [supersteps, 8] trace of the last solve run in timing mode (columns
+    TRACE_FIELDS); empty without timing mode."""
+    lib = load_library()
+    rows = lib.pmf_get_trace(handle, None, 0)
+    if rows < 0:
+        raise PmfError(int(-rows), "pmf_get_trace")
+    out = np.zeros((rows, PMF_TRACE_COLS), dtype=np.int64)
+    if rows:
+        got = lib.pmf_get_trace(handle, out.ctypes.data, rows)
+        if got != rows:
+            raise PmfError(PMF_EDEVICE, "pmf_get_trace")
+    return out
 
 
 def pmf_get_stats(handle) -> Dict[str, int]:

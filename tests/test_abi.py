@@ -69,6 +69,7 @@ def test_null_handle_is_rejected(lib):
     assert pmf.pmf_solve_batch(None, [_fake()], 0x10, 0) == pmf.PMF_EINVAL
     assert pmf.pmf_extract_cut(None, 0, 0, 0x10) == pmf.PMF_EINVAL
     assert pmf.pmf_destroy(None) == pmf.PMF_EINVAL
+    assert pmf.load_library().pmf_get_trace(None, None, 0) == -pmf.PMF_EINVAL
 
 
 def test_query_bytes_scales_with_size(lib):

@@ -250,3 +250,25 @@ def test_slot_stats_describe_the_split(pmf):
     assert (st[:, 0] == 1).all() and (st[:, 5] == 1).all()
     assert (st[:, 1] > 0).all() and (st[:, 4] >= 4).all()  # >= 2 relabel + 2 cut passes
     s.close()
+
+
+def test_timing_trace_matches_stats(pmf):
+    """Timing mode records one trace row per superstep; its kernel times add up
+    to the counters, and the results equal those of the default mode."""
+    import torch
+    insts = W.config0()
+    dev = pmf.to_device(insts)
+    ref = pmf.Solver()
+    f0, s0 = ref.solve(dev)
+    assert len(pmf.pmf_get_trace(ref.handle)) == 0
+    t = pmf.Solver(timing=1)
+    f1, s1 = t.solve(dev)
+    torch.cuda.synchronize()
+    assert torch.equal(f0, f1) and torch.equal(s0, s1)
+    tr = pmf.pmf_get_trace(t.handle)
+    st = t.stats()
+    assert tr.shape == (st["supersteps"], pmf.PMF_TRACE_COLS)
+    assert tr[:, 4].sum() == st["sweep_ns"] and tr[:, 5].sum() == st["bfs_ns"]
+    assert (tr[:, :4] >= 0).all() and tr[:, 0].sum() > 0 and tr[:, 2].sum() > 0
+    ref.close()
+    t.close()
