@@ -127,6 +127,9 @@ def main():
     ap.add_argument("--steps-per-sync", type=int, default=0)
     ap.add_argument("--lambda-chunk", type=int, default=0)
     ap.add_argument("--exchange-rounds", type=int, default=0)
+    ap.add_argument("--tail-tiles", type=int, default=-1, help="0 disables the short-superstep settings")
+    ap.add_argument("--tail-inner-iters", type=int, default=0)
+    ap.add_argument("--tail-exchange-rounds", type=int, default=0)
     ap.add_argument("--tune", action="store_true",
                     help="autotune the speed knobs on this workload before timing (results must not change)")
     ap.add_argument("--cpu-sample", type=int, default=48)
@@ -162,9 +165,12 @@ def main():
         overrides.update(tile_w=args.tile_w, tile_h=1024 // args.tile_w)
     for a, f in (("inner_iters", args.inner_iters), ("sweeps_per_relabel", args.sweeps_per_relabel),
                  ("local_bfs_iters", args.local_bfs_iters), ("steps_per_sync", args.steps_per_sync),
-                 ("lambda_chunk", args.lambda_chunk), ("exchange_rounds", args.exchange_rounds)):
+                 ("lambda_chunk", args.lambda_chunk), ("exchange_rounds", args.exchange_rounds),
+                 ("tail_inner_iters", args.tail_inner_iters), ("tail_exchange_rounds", args.tail_exchange_rounds)):
         if f:
             overrides[a] = f
+    if args.tail_tiles >= 0:
+        overrides["tail_tiles"] = args.tail_tiles
 
     def log(*a):
         print("[bench]", *a, file=sys.stderr, flush=True)
@@ -251,7 +257,8 @@ def main():
                                   "step, one pmf_solve_batch call",
                       "options": {k: getattr(solver.options, k) for k in
                                   ("tile_w", "tile_h", "inner_iters", "sweeps_per_relabel",
-                                   "local_bfs_iters", "exchange_rounds", "steps_per_sync", "use_graph", "order",
+                                   "local_bfs_iters", "exchange_rounds", "tail_tiles", "tail_inner_iters",
+                                   "tail_exchange_rounds", "steps_per_sync", "use_graph", "order",
                                    "lambda_chunk")}},
            "latency_ms": {"p50": round(float(np.percentile(times, 50)) * 1e3, 2),
                           "p99": round(float(np.percentile(times, 99)) * 1e3, 2),

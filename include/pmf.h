@@ -72,7 +72,13 @@ typedef struct pmf_options {
                                 /*   parallel; >= L = one warm-started chain; 0 =   */
                                 /*   the smallest chunk whose state fits in memory  */
     int32_t exchange_rounds;    /* relabel/cut passes: halo re-reads per tile visit  */
-    int32_t reserved[4];
+    int32_t tail_tiles;         /* a superstep whose sweep (pass) list holds fewer   */
+                                /*   tiles than this is latency bound: its sweeps   */
+                                /*   use tail_inner_iters, its relabel / cut passes */
+                                /*   tail_exchange_rounds (0 = never)               */
+    int32_t tail_inner_iters;
+    int32_t tail_exchange_rounds;
+    int32_t reserved[1];
 } pmf_options;
 
 /* One (image, seed) problem and its lambda schedule.  All pointers are device

@@ -36,6 +36,10 @@ bool valid_options(const pmf_options &o) {
     if (o.sweeps_per_relabel < 1 || o.sweeps_per_relabel > 1 << 20) return false;
     if (o.local_bfs_iters < 1 || o.local_bfs_iters > 1 << 20) return false;
     if (o.exchange_rounds < 1 || o.exchange_rounds > 64) return false;
+    if (o.tail_tiles < 0) return false;
+    if (o.tail_tiles > 0 && (o.tail_inner_iters < 1 || o.tail_inner_iters > 4096 ||
+                             o.tail_exchange_rounds < 1 || o.tail_exchange_rounds > 64))
+        return false;
     if (o.steps_per_sync < 1 || o.steps_per_sync > 1 << 16) return false;
     if (o.max_supersteps < 1) return false;
     if (o.order != 0 && o.order != 1) return false;
@@ -266,6 +270,9 @@ int open_session(pmf_handle *h, int slots, size_t pool_bytes) {
     P.sweeps_per_relabel = h->opt.sweeps_per_relabel;
     P.local_bfs_iters = h->opt.local_bfs_iters;
     P.exchange_rounds = h->opt.exchange_rounds;
+    P.tail_tiles = h->opt.tail_tiles;
+    P.tail_inner_iters = h->opt.tail_inner_iters;
+    P.tail_exchange_rounds = h->opt.tail_exchange_rounds;
     P.max_steps = h->opt.max_supersteps;
     h->pool_base = off;
     // the work list is sized for pool_bytes, so the pool must not exceed it
@@ -563,6 +570,9 @@ void pmf_default_options(pmf_options *o) {
     o->sweeps_per_relabel = 8;
     o->local_bfs_iters = 64;
     o->exchange_rounds = 4;
+    o->tail_tiles = 2048;
+    o->tail_inner_iters = 32;
+    o->tail_exchange_rounds = 16;
     o->steps_per_sync = 32;
     o->max_supersteps = 2000000;
     o->use_graph = 1;

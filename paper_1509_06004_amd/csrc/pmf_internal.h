@@ -92,6 +92,9 @@ struct StepParams {
     int32_t sweeps_per_relabel;
     int32_t local_bfs_iters;
     int32_t exchange_rounds;
+    int32_t tail_tiles;         // lists shorter than this use the two settings below
+    int32_t tail_inner_iters;
+    int32_t tail_exchange_rounds;
     int64_t max_steps;
 };
 

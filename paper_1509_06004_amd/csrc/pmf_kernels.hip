@@ -39,15 +39,6 @@
 #include "pmf.h"
 #include "pmf_internal.h"
 
-// Pixels per read group of the sweep (4- and 8-connected): the registers a
-// group holds against the LDS reads in flight.
-#ifndef PMF_SWEEP_GROUP4
-#define PMF_SWEEP_GROUP4 4
-#endif
-#ifndef PMF_SWEEP_GROUP8
-#define PMF_SWEEP_GROUP8 2
-#endif
-
 namespace pmf {
 
 __device__ constexpr int DXk(int k) {
@@ -219,22 +210,24 @@ __device__ void init_tile(const StepParams &P, const InstDesc &D, InstState *S, 
 // kSweep: tile-local push/relabel iterations in LDS.
 //
 // The tile's residuals (one record of K words per cell, so that a pixel reads
-// all of them at once), excess and heights live in LDS with a one-pixel halo.
-// Every inner iteration is one phase: each active pixel p (e > 0, h < H_INF)
-// pushes d = min(e, r) to the sink when rt > 0 and along admissible arcs
-// (h(p) = h(q) + 1), then, if excess is left and no admissible arc, relabels
-// to 1 + min h(q) over its residual arcs.  All residual and excess updates are
-// LDS atomics without return: whatever the interleaving of neighbours, every
-// update is applied exactly once, a pixel never sends more than the excess and
-// residual it read (other threads only add to those), so the bookkeeping stays
-// exact and non-negative.  Labels are only a guide here; maximality is
+// all of them at once), excess, sink residuals and heights live in LDS with a
+// one-pixel halo.  In every inner iteration each active pixel p (e > 0,
+// h < H_INF) pushes d = min(e, r) to the sink when rt > 0 and along
+// admissible arcs (h(p) = h(q) + 1), then, if excess is left and no
+// admissible arc, relabels to 1 + min h(q) over its residual arcs.  Only the
+// active pixels are processed (a small fraction of the tile once the first
+// iterations are done).  All residual and excess updates are LDS atomics
+// without return: whatever the interleaving of neighbours, every update is
+// applied exactly once, a pixel never sends more than the excess and residual
+// it read (other threads only add to those), so the bookkeeping stays exact
+// and non-negative.  Labels are only a guide here; maximality is
 // certified by the exact global relabel.  A push to a halo pixel (another
 // tile) lands in the halo cell's word of the reverse arc, i.e. exactly the
 // amount handed over; those words go to the neighbours' inboxes at the end.
 // ---------------------------------------------------------------------------
 template <int K, int TW, int TH>
 __device__ void sweep_tile(const StepParams &P, const InstDesc &D, InstState *S, int tg, int tl,
-                           int32_t *lds, int *s_red) {
+                           int iters, int32_t *lds, int *s_red) {
     using G = Geo<TW, TH>;
     constexpr int PPT = G::PPT, RPI = G::RPI, HW = G::HW, HH = G::HH, HALO = G::HALO;
     const int tid = threadIdx.x, lx = tid % TW, ly0 = tid / TW;
@@ -248,8 +241,10 @@ __device__ void sweep_tile(const StepParams &P, const InstDesc &D, InstState *S,
     const int hcap = n + 1;  // no exact distance to t exceeds n
     int32_t *sh_h = lds;             // [HALO] heights
     int32_t *sh_e = lds + HALO;      // [HALO] excess (tile cells only)
-    int32_t *sh_r = lds + 2 * HALO;  // [HALO][K] residuals; halo cells: pushes handed over
+    int32_t *sh_t = lds + 2 * HALO;  // [HALO] sink residuals (tile cells only)
+    int32_t *sh_r = lds + 3 * HALO;  // [HALO][K] residuals; halo cells: pushes handed over
     __shared__ int s_nb[9];
+    __shared__ uint16_t s_slot[kThreads * PPT];  // per wave: its active pixels' cells
 
     if (tid < 9) s_nb[tid] = 0;
     if (tid == 0) atomicAnd(&D.tile_act[tl], ~2u);  // about to drain the inbox
@@ -263,7 +258,6 @@ __device__ void sweep_tile(const StepParams &P, const InstDesc &D, InstState *S,
 #pragma unroll
         for (int k = 0; k < K; ++k) sh_r[c * K + k] = 0;
     }
-    int rt[PPT], h[PPT];
     bool valid[PPT];
 #pragma unroll
     for (int j = 0; j < PPT; ++j) {
@@ -271,18 +265,16 @@ __device__ void sweep_tile(const StepParams &P, const InstDesc &D, InstState *S,
         const int gx = x0 + lx, gy = y0 + ly;
         const int c = (ly + 1) * HW + lx + 1;
         valid[j] = gx < W && gy < H;
-        int e = 0, r[K];
+        int e = 0, rt = 0, h = kHInf, r[K];
 #pragma unroll
         for (int k = 0; k < K; ++k) r[k] = 0;
-        rt[j] = 0;
-        h[j] = kHInf;
         if (valid[j]) {
             const int p = gy * W + gx;
             e = D.e[p];
 #pragma unroll
             for (int k = 0; k < K; ++k) r[k] = D.r[(size_t)k * n + p];
-            rt[j] = D.rt[p];
-            h[j] = D.h[p];
+            rt = D.rt[p];
+            h = D.h[p];
             // drain flow pushed in by neighbour tiles
 #pragma unroll
             for (int k = 0; k < K; ++k) {
@@ -300,86 +292,88 @@ __device__ void sweep_tile(const StepParams &P, const InstDesc &D, InstState *S,
             }
         }
         sh_e[c] = e;
+        sh_t[c] = rt;
 #pragma unroll
         for (int k = 0; k < K; ++k) sh_r[c * K + k] = r[k];
-        sh_h[c] = h[j];
+        sh_h[c] = h;
     }
     __syncthreads();
 
-    // Pixels are processed in groups of GB.  A group whose pixels are all
-    // inactive in the whole wave is skipped after reading only its excess;
-    // otherwise every read of the group is issued before any is used, and the
-    // pushes and the lift are computed with selects (the only branches guard
-    // the LDS atomics of an arc, skipped when no lane pushes along it).
-    constexpr int GB = K == 8 ? PMF_SWEEP_GROUP8 : PMF_SWEEP_GROUP4;
-    static_assert(PPT % GB == 0, "group size must divide the pixels per thread");
-    for (int it = 0; it < P.inner_iters; ++it) {
-        int any = 0;
+    // Iterations.  Every pixel belongs to one wave (the PPT pixels of each of
+    // its lanes).  Per iteration a wave lists its active pixels (e > 0,
+    // h < H_INF) in a slot array of its own, then its lanes take one listed
+    // pixel each: sink push, pushes along admissible arcs in arc order, lift
+    // if excess is left.  Work is proportional to the active pixels, and
+    // waves need no barrier between iterations: every cross-pixel update is
+    // an LDS atomic, and a pixel's height and sink residual are written only
+    // by its own wave.
+    const int lane = tid & 63;
+    uint16_t *slot = s_slot + (tid >> 6) * (PPT * 64);
+    const unsigned long long below = (1ull << lane) - 1ull;
+    for (int it = 0; it < iters; ++it) {
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        int ev[PPT], hv[PPT];
 #pragma unroll
-        for (int g = 0; g < PPT; g += GB) {
-            int e[GB];
-            bool act[GB], wact = false;
-#pragma unroll
-            for (int b = 0; b < GB; ++b) {
-                e[b] = sh_e[(ly0 + (g + b) * RPI + 1) * HW + lx + 1];
-                act[b] = e[b] > 0 && h[g + b] < kHInf;
-                wact |= act[b];
-            }
-            if (__ballot(wact) == 0ull) continue;
-            int r[GB][K], hq[GB][K];
-#pragma unroll
-            for (int b = 0; b < GB; ++b) {
-                const int c = (ly0 + (g + b) * RPI + 1) * HW + lx + 1;
-#pragma unroll
-                for (int k = 0; k < K; ++k) {
-                    r[b][k] = sh_r[c * K + k];
-                    hq[b][k] = sh_h[c + DYk(k) * HW + DXk(k)];
-                }
-            }
-#pragma unroll
-            for (int b = 0; b < GB; ++b) {
-                const int j = g + b;
-                const int c = (ly0 + j * RPI + 1) * HW + lx + 1;
-                // sink first, then the admissible arcs (h(q) = h(p) - 1) in
-                // arc order, each taking min(excess left, residual)
-                int ex = act[b] ? e[b] : 0;
-                const int dt = ex < rt[j] ? ex : rt[j];
-                ex -= dt;
-                rt[j] -= dt;
-                int pushed = dt;
-                const int hm1 = h[j] - 1;
-                int mn = kHInf;
-#pragma unroll
-                for (int k = 0; k < K; ++k) {
-                    const int rk = r[b][k];
-                    const bool down = hq[b][k] == hm1;
-                    const int d = down ? (rk < ex ? rk : ex) : 0;  // residuals are never negative
-                    ex -= d;
-                    pushed += d;
-                    const int cand = rk - d > 0 ? hq[b][k] + 1 : kHInf;
-                    mn = cand < mn ? cand : mn;
-                    if (d) {
-                        const int q = c + DYk(k) * HW + DXk(k);
-                        atomicSub(&sh_r[c * K + k], d);
-                        atomicAdd(&sh_r[q * K + (k ^ 1)], d);
-                        // halo cells' excess words are never read: no test needed
-                        atomicAdd(&sh_e[q], d);
-                    }
-                }
-                if (pushed) atomicSub(&sh_e[c], pushed);
-                // excess left means the sink arc and every admissible arc are
-                // saturated: lift above the lowest residual neighbour
-                const bool lift = ex > 0;
-                const int nh = mn >= hcap ? kHInf : mn;
-                if (lift) sh_h[c] = nh;
-                h[j] = lift ? nh : h[j];
-                any |= act[b] && h[j] < kHInf;
-            }
+        for (int j = 0; j < PPT; ++j) {
+            const int c = (ly0 + j * RPI + 1) * HW + lx + 1;
+            ev[j] = sh_e[c];
+            hv[j] = sh_h[c];
         }
-        // progress check every 2 rounds (updates are atomic, so rounds need
-        // no barrier between them)
-        if ((it & 1) == 1 || it + 1 == P.inner_iters) {
-            if (!__syncthreads_or(any)) break;
+        int na = 0;
+#pragma unroll
+        for (int j = 0; j < PPT; ++j) {
+            const int c = (ly0 + j * RPI + 1) * HW + lx + 1;
+            const bool a = (ev[j] > 0) & (hv[j] < kHInf);
+            const unsigned long long m = __ballot(a);
+            if (a) slot[na + __popcll(m & below)] = (uint16_t)c;
+            na += __popcll(m);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        for (int i = lane; i < na; i += 64) {
+            const int c = slot[i];
+            int r[K], hq[K];
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                r[k] = sh_r[c * K + k];
+                hq[k] = sh_h[c + DYk(k) * HW + DXk(k)];
+            }
+            const int h = sh_h[c];
+            const int rt = sh_t[c];
+            // the excess only grew since the listing (only this lane takes it
+            // out), so it is still positive
+            int ex = sh_e[c];
+            const int dt = ex < rt ? ex : rt;
+            ex -= dt;
+            if (dt) sh_t[c] = rt - dt;
+            int pushed = dt;
+            const int hm1 = h - 1;
+            int mn = kHInf;
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                const int rk = r[k];
+                const bool down = hq[k] == hm1;
+                const int d = down ? (rk < ex ? rk : ex) : 0;  // residuals are never negative
+                ex -= d;
+                pushed += d;
+                const int cand = rk - d > 0 ? hq[k] + 1 : kHInf;
+                mn = cand < mn ? cand : mn;
+                if (d) {
+                    const int q = c + DYk(k) * HW + DXk(k);
+                    atomicSub(&sh_r[c * K + k], d);
+                    atomicAdd(&sh_r[q * K + (k ^ 1)], d);
+                    // halo cells' excess words are never read: no test needed
+                    atomicAdd(&sh_e[q], d);
+                }
+            }
+            if (pushed) atomicSub(&sh_e[c], pushed);
+            // excess left means the sink arc and every admissible arc are
+            // saturated: lift above the lowest residual neighbour
+            if (ex > 0) sh_h[c] = mn >= hcap ? kHInf : mn;
+        }
+        // progress check every 2 iterations: an iteration in which no wave
+        // listed a pixel changed nothing, so the tile is at rest
+        if ((it & 1) == 1 || it + 1 == iters) {
+            if (!__syncthreads_or(na > 0)) break;
         }
     }
     __syncthreads();
@@ -393,7 +387,9 @@ __device__ void sweep_tile(const StepParams &P, const InstDesc &D, InstState *S,
         const int p = (y0 + ly) * W + x0 + lx;
         const int c = (ly + 1) * HW + lx + 1;
         const int e = sh_e[c];
-        int rm = (rt[j] > 0 ? kRtBit : 0) | (e > 0 ? kEBit : 0);
+        const int rt = sh_t[c];
+        const int h = sh_h[c];
+        int rm = (rt > 0 ? kRtBit : 0) | (e > 0 ? kEBit : 0);
 #pragma unroll
         for (int k = 0; k < K; ++k) {
             const int r = sh_r[c * K + k];
@@ -401,10 +397,10 @@ __device__ void sweep_tile(const StepParams &P, const InstDesc &D, InstState *S,
             if (r > 0) rm |= 1 << k;
         }
         D.e[p] = e;
-        D.rt[p] = rt[j];
-        D.h[p] = h[j];
+        D.rt[p] = rt;
+        D.h[p] = h;
         D.rmask[p] = (uint16_t)rm;
-        active |= e > 0 && h[j] < kHInf;
+        active |= e > 0 && h < kHInf;
     }
     // hand pushes into halo cells to the neighbour tiles' inboxes: the word
     // k of halo cell q with q + d_k inside the tile holds what q received
@@ -461,7 +457,7 @@ __device__ __forceinline__ bool frontier_needs(const InstDesc &D, int tx, int ty
 // ---------------------------------------------------------------------------
 template <int K, int TW, int TH>
 __device__ void relabel_tile(const StepParams &P, const InstDesc &D, InstState *S, int tg, int tl,
-                             int sub, int32_t *lds, int *s_red) {
+                             int sub, int xrounds, int32_t *lds, int *s_red) {
     using G = Geo<TW, TH>;
     constexpr int PPT = G::PPT, RPI = G::RPI, HW = G::HW;
     const int tid = threadIdx.x, lx = tid % TW, ly0 = tid / TW;
@@ -538,7 +534,7 @@ __device__ void relabel_tile(const StepParams &P, const InstDesc &D, InstState *
     int dpub[PPT];
 #pragma unroll
     for (int j = 0; j < PPT; ++j) dpub[j] = d0[j];
-    const int rounds = first ? 1 : P.exchange_rounds;
+    const int rounds = first ? 1 : xrounds;
     for (int round = 0; round < rounds; ++round) {
     // Relaxation rounds; the convergence check (a barrier) runs every 4
     // rounds.  Labels only decrease and every value read is an upper bound of
@@ -628,7 +624,7 @@ __device__ void relabel_tile(const StepParams &P, const InstDesc &D, InstState *
 // ---------------------------------------------------------------------------
 template <int K, int TW, int TH>
 __device__ void cut_tile(const StepParams &P, const InstDesc &D, InstState *S, int tg, int tl, int sub,
-                         int kk, int32_t *lds, int *s_red, unsigned long long *s_sum) {
+                         int kk, int xrounds, int32_t *lds, int *s_red, unsigned long long *s_sum) {
     using G = Geo<TW, TH>;
     constexpr int PPT = G::PPT, RPI = G::RPI, HW = G::HW;
     const int tid = threadIdx.x, lx = tid % TW, ly0 = tid / TW;
@@ -697,7 +693,7 @@ __device__ void cut_tile(const StepParams &P, const InstDesc &D, InstState *S, i
     int mpub[PPT];
 #pragma unroll
     for (int j = 0; j < PPT; ++j) mpub[j] = m0[j];
-    const int rounds = first ? 1 : P.exchange_rounds;
+    const int rounds = first ? 1 : xrounds;
     for (int round = 0; round < rounds; ++round) {
     // Reachability rounds, convergence checked every 4 rounds: reached bits
     // only get set, so rounds need no barrier between them.
@@ -926,9 +922,13 @@ struct ListWalk {
 
 template <int K, int TW, int TH>
 __global__ __launch_bounds__(kThreads) void k_sweep(StepParams P, int which) {
-    __shared__ int32_t lds[(2 + K) * (TW + 2) * (TH + 2)];
+    __shared__ int32_t lds[(3 + K) * (TW + 2) * (TH + 2)];
     __shared__ int s_red[4];
     const ListWalk w(P, which);
+    // a short superstep (few tiles in both sweep lists) is latency bound: its
+    // visits may run longer at no cost in width
+    const int iters =
+        P.list_count[0] + P.list_count[1] < P.tail_tiles ? P.tail_inner_iters : P.inner_iters;
     for (int i = w.first; i < w.eighth && w.base + i < w.cnt; i += w.stride) {
         const int t = w.list[w.base + i];
         __syncthreads();  // the previous tile's LDS is no longer in use
@@ -938,7 +938,7 @@ __global__ __launch_bounds__(kThreads) void k_sweep(StepParams P, int which) {
         const InstDesc D = P.desc[slot];
         const int tl = P.tile_local[t];
         if (tl >= D.ntiles) continue;
-        sweep_tile<K, TW, TH>(P, D, S, t, tl, lds, s_red);
+        sweep_tile<K, TW, TH>(P, D, S, t, tl, iters, lds, s_red);
     }
 }
 
@@ -948,6 +948,8 @@ __global__ __launch_bounds__(kThreads) void k_bfs(StepParams P, int which) {
     __shared__ int s_red[4];
     __shared__ unsigned long long s_sum;
     const ListWalk w(P, which);
+    const int xrounds =
+        P.list_count[2] + P.list_count[3] < P.tail_tiles ? P.tail_exchange_rounds : P.exchange_rounds;
     for (int i = w.first; i < w.eighth && w.base + i < w.cnt; i += w.stride) {
         const int t = w.list[w.base + i];
         __syncthreads();
@@ -962,9 +964,9 @@ __global__ __launch_bounds__(kThreads) void k_bfs(StepParams P, int which) {
         if (phase == kInit)
             init_tile<K, TW, TH>(P, D, S, t, tl, s_red, &s_sum);
         else if (phase == kRelabel)
-            relabel_tile<K, TW, TH>(P, D, S, t, tl, sub, lds, s_red);
+            relabel_tile<K, TW, TH>(P, D, S, t, tl, sub, xrounds, lds, s_red);
         else
-            cut_tile<K, TW, TH>(P, D, S, t, tl, sub, kk, lds, s_red, &s_sum);
+            cut_tile<K, TW, TH>(P, D, S, t, tl, sub, kk, xrounds, lds, s_red, &s_sum);
     }
 }
 

@@ -48,7 +48,10 @@ class Options(ctypes.Structure):
         ("timing", ctypes.c_int32),
         ("lambda_chunk", ctypes.c_int32),
         ("exchange_rounds", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 4),
+        ("tail_tiles", ctypes.c_int32),
+        ("tail_inner_iters", ctypes.c_int32),
+        ("tail_exchange_rounds", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 1),
     ]
 
 

@@ -126,8 +126,9 @@ def test_config1_warm_chain(pmf):
 
 
 def test_options_do_not_change_results(pmf):
-    """Tile shape, inner iterations, relabel period, packing order, graph replay:
-    speed knobs only; results are identical."""
+    """Tile shape, inner iterations, relabel period, packing order, graph replay,
+    lambda chunks, exchange rounds, tail settings: speed knobs only; results
+    are identical."""
     rng = np.random.default_rng(29)
     insts = [W.tiny_random(rng, 90, 70, 4, cmax=300, L=4, p_seed=0.02, lam_max=100),
              W.tiny_random(rng, 61, 83, 8, cmax=300, L=3, p_seed=0.02, lam_max=100)]
@@ -136,7 +137,9 @@ def test_options_do_not_change_results(pmf):
                  dict(inner_iters=64, sweeps_per_relabel=32, local_bfs_iters=4), dict(order=0),
                  dict(use_graph=0, steps_per_sync=3), dict(timing=1), dict(lambda_chunk=1),
                  dict(lambda_chunk=3), dict(lambda_chunk=100), dict(exchange_rounds=1),
-                 dict(exchange_rounds=16, local_bfs_iters=2)]:
+                 dict(exchange_rounds=16, local_bfs_iters=2), dict(tail_tiles=0),
+                 dict(tail_tiles=1 << 30, tail_inner_iters=3, tail_exchange_rounds=1),
+                 dict(tail_tiles=1 << 30, tail_inner_iters=200, tail_exchange_rounds=64)]:
         say("options", opts)
         flows, status, masks, _ = solve(pmf, insts, **opts)
         assert (status == 0).all()
