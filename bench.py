@@ -130,6 +130,7 @@ def main():
     ap.add_argument("--tail-tiles", type=int, default=-1, help="0 disables the short-superstep settings")
     ap.add_argument("--tail-inner-iters", type=int, default=0)
     ap.add_argument("--tail-exchange-rounds", type=int, default=0)
+    ap.add_argument("--relabel-passes", type=int, default=-1, help="0 runs every relabel to its fixed point")
     ap.add_argument("--tune", action="store_true",
                     help="autotune the speed knobs on this workload before timing (results must not change)")
     ap.add_argument("--cpu-sample", type=int, default=48)
@@ -171,6 +172,8 @@ def main():
             overrides[a] = f
     if args.tail_tiles >= 0:
         overrides["tail_tiles"] = args.tail_tiles
+    if args.relabel_passes >= 0:
+        overrides["relabel_passes"] = args.relabel_passes
 
     def log(*a):
         print("[bench]", *a, file=sys.stderr, flush=True)
@@ -258,7 +261,7 @@ def main():
                       "options": {k: getattr(solver.options, k) for k in
                                   ("tile_w", "tile_h", "inner_iters", "sweeps_per_relabel",
                                    "local_bfs_iters", "exchange_rounds", "tail_tiles", "tail_inner_iters",
-                                   "tail_exchange_rounds", "steps_per_sync", "use_graph", "order",
+                                   "tail_exchange_rounds", "relabel_passes", "steps_per_sync", "use_graph", "order",
                                    "lambda_chunk")}},
            "latency_ms": {"p50": round(float(np.percentile(times, 50)) * 1e3, 2),
                           "p99": round(float(np.percentile(times, 99)) * 1e3, 2),

@@ -78,7 +78,10 @@ typedef struct pmf_options {
                                 /*   tail_exchange_rounds (0 = never)               */
     int32_t tail_inner_iters;
     int32_t tail_exchange_rounds;
-    int32_t reserved[1];
+    int32_t relabel_passes;     /* a global relabel that still leaves active pixels */
+                                /*   after this many passes hands over to the sweep */
+                                /*   before its fixed point (0 = never); a relabel  */
+                                /*   that certifies termination always converges    */
 } pmf_options;
 
 /* One (image, seed) problem and its lambda schedule.  All pointers are device

@@ -36,7 +36,7 @@ bool valid_options(const pmf_options &o) {
     if (o.sweeps_per_relabel < 1 || o.sweeps_per_relabel > 1 << 20) return false;
     if (o.local_bfs_iters < 1 || o.local_bfs_iters > 1 << 20) return false;
     if (o.exchange_rounds < 1 || o.exchange_rounds > 64) return false;
-    if (o.tail_tiles < 0) return false;
+    if (o.tail_tiles < 0 || o.relabel_passes < 0) return false;
     if (o.tail_tiles > 0 && (o.tail_inner_iters < 1 || o.tail_inner_iters > 4096 ||
                              o.tail_exchange_rounds < 1 || o.tail_exchange_rounds > 64))
         return false;
@@ -273,6 +273,7 @@ int open_session(pmf_handle *h, int slots, size_t pool_bytes) {
     P.tail_tiles = h->opt.tail_tiles;
     P.tail_inner_iters = h->opt.tail_inner_iters;
     P.tail_exchange_rounds = h->opt.tail_exchange_rounds;
+    P.relabel_passes = h->opt.relabel_passes;
     P.max_steps = h->opt.max_supersteps;
     h->pool_base = off;
     // the work list is sized for pool_bytes, so the pool must not exceed it

@@ -95,6 +95,7 @@ struct StepParams {
     int32_t tail_tiles;         // lists shorter than this use the two settings below
     int32_t tail_inner_iters;
     int32_t tail_exchange_rounds;
+    int32_t relabel_passes;     // cap on the passes of a relabel that leaves active pixels (0 = none)
     int64_t max_steps;
 };
 

@@ -387,8 +387,9 @@ __device__ void sweep_tile(const StepParams &P, const InstDesc &D, InstState *S,
         const int p = (y0 + ly) * W + x0 + lx;
         const int c = (ly + 1) * HW + lx + 1;
         const int e = sh_e[c];
-        const int rt = sh_t[c];
         const int h = sh_h[c];
+        active |= e > 0 && h < kHInf;
+        const int rt = sh_t[c];
         int rm = (rt > 0 ? kRtBit : 0) | (e > 0 ? kEBit : 0);
 #pragma unroll
         for (int k = 0; k < K; ++k) {
@@ -400,7 +401,6 @@ __device__ void sweep_tile(const StepParams &P, const InstDesc &D, InstState *S,
         D.rt[p] = rt;
         D.h[p] = h;
         D.rmask[p] = (uint16_t)rm;
-        active |= e > 0 && h < kHInf;
     }
     // hand pushes into halo cells to the neighbour tiles' inboxes: the word
     // k of halo cell q with q + d_k inside the tile holds what q received
@@ -801,6 +801,14 @@ __device__ void control(const StepParams &P) {
                 if (S->sub > 0 && !changed) {
                     S->relabels += 1;
                     ph = ld_agent(&S->active) == 0 ? kCut : kSweep;
+                    S->sub = 0;
+                } else if (P.relabel_passes > 0 && S->sub + 1 >= P.relabel_passes && ld_agent(&S->active) > 0) {
+                    // cut short: the pixels labelled so far hold upper bounds of
+                    // their distances and there is work for the sweep; pixels
+                    // still at H_INF wait for a later relabel.  Only a relabel
+                    // run to its fixed point may end the solve.
+                    S->relabels += 1;
+                    ph = kSweep;
                     S->sub = 0;
                 } else {
                     S->sub += 1;

@@ -51,7 +51,7 @@ class Options(ctypes.Structure):
         ("tail_tiles", ctypes.c_int32),
         ("tail_inner_iters", ctypes.c_int32),
         ("tail_exchange_rounds", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 1),
+        ("relabel_passes", ctypes.c_int32),
     ]
 
 

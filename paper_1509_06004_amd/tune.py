@@ -25,7 +25,7 @@ from typing import Dict, List, Optional, Sequence
 from . import pmf
 
 KNOBS = ("tile_w", "inner_iters", "sweeps_per_relabel", "local_bfs_iters", "exchange_rounds", "tail_tiles",
-         "tail_inner_iters", "tail_exchange_rounds", "order", "lambda_chunk")
+         "tail_inner_iters", "tail_exchange_rounds", "relabel_passes", "order", "lambda_chunk")
 SPACE = {
     "tile_w": [32, 64],
     "inner_iters": [4, 8, 16, 32],
@@ -35,6 +35,7 @@ SPACE = {
     "tail_tiles": [0, 512, 2048, 8192],
     "tail_inner_iters": [16, 32, 64],
     "tail_exchange_rounds": [4, 16, 32],
+    "relabel_passes": [0, 2, 3, 4, 6],
     "order": [0, 1],
     "lambda_chunk": [0, 1, 2, 4],
 }

@@ -139,7 +139,8 @@ def test_options_do_not_change_results(pmf):
                  dict(lambda_chunk=3), dict(lambda_chunk=100), dict(exchange_rounds=1),
                  dict(exchange_rounds=16, local_bfs_iters=2), dict(tail_tiles=0),
                  dict(tail_tiles=1 << 30, tail_inner_iters=3, tail_exchange_rounds=1),
-                 dict(tail_tiles=1 << 30, tail_inner_iters=200, tail_exchange_rounds=64)]:
+                 dict(tail_tiles=1 << 30, tail_inner_iters=200, tail_exchange_rounds=64),
+                 dict(relabel_passes=1), dict(relabel_passes=2, exchange_rounds=1, local_bfs_iters=3)]:
         say("options", opts)
         flows, status, masks, _ = solve(pmf, insts, **opts)
         assert (status == 0).all()
