@@ -93,7 +93,7 @@ size_t worklist_cap(int slots, size_t pool_bytes) { return pool_bytes / 512 + (s
 // Device bytes of the control area for `slots` slots and a work list of `wl` tiles.
 size_t control_bytes(int slots, size_t wl) {
     return align_up(sizeof(InstDesc) * (size_t)slots) + align_up(sizeof(InstState) * (size_t)slots) +
-           align_up(4 * (size_t)slots) + align_up(64) + 2 * align_up(4 * wl) + 4 * align_up(4 * wl);
+           align_up(4 * (size_t)slots) + align_up(64) + 2 * align_up(4 * wl) + align_up(4 * 8 * wl);
 }
 
 // First-fit allocator over [0, cap) with coalescing of freed ranges.
@@ -261,7 +261,7 @@ int open_session(pmf_handle *h, int slots, size_t pool_bytes) {
     P.ring_count = (int32_t *)take(64);
     P.tile_slot = (const int32_t *)take(4 * wl);
     P.tile_local = (const int32_t *)take(4 * wl);
-    P.lists = (int32_t *)take(4 * 4 * wl);
+    P.lists = (int32_t *)take(4 * 8 * wl);
     P.list_count = P.ring_count + 4;  // inside the 64-byte counter block
     P.list_cap = (int32_t)wl;
     P.ring_cap = slots;

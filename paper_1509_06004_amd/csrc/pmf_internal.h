@@ -82,7 +82,7 @@ struct StepParams {
     int32_t *ring_count;        // completions so far (ring index = count % ring_cap)
     int32_t ring_cap;
     int32_t list_cap;           // capacity of each compacted list (>= ntiles)
-    int32_t *lists;             // [4][list_cap] tiles to sweep (K=4, K=8), to pass (K=4, K=8)
+    int32_t *lists;             // [4][list_cap] {slot, tile} pairs: to sweep (K=4, K=8), to pass (K=4, K=8)
     int32_t *list_count;        // [4] entries of each list in this superstep, [4..7] those of the last one
     int32_t ntiles;
     int32_t t4_begin, t4_count; // tiles of 4-connected instances (contiguous)

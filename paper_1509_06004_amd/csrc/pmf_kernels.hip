@@ -53,6 +53,53 @@ __device__ __forceinline__ T ld_agent(const T *p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Instance arrays live in device global memory.  Their pointers are read from
+// the descriptor table, so the compiler cannot tell their address space and
+// would emit flat instructions (which count against the LDS wait counter as
+// well); gp() states it, giving global loads, stores and atomics.
+#define GLOBAL __attribute__((address_space(1)))
+template <typename T>
+__device__ __forceinline__ GLOBAL T *gp(T *p) {
+    return (GLOBAL T *)p;
+}
+// Descriptors are written by the host before any launch and only read by the
+// kernels: a workgroup-uniform descriptor read goes through the constant
+// address space, i.e. scalar loads.
+__device__ __forceinline__ InstDesc load_desc(const InstDesc *table, int slot) {
+    static_assert(sizeof(InstDesc) % 4 == 0, "descriptor read in 4-byte words");
+    const __attribute__((address_space(4))) uint32_t *src =
+        (const __attribute__((address_space(4))) uint32_t *)(table + slot);
+    InstDesc d;
+    uint32_t *dst = reinterpret_cast<uint32_t *>(&d);
+#pragma unroll
+    for (int i = 0; i < (int)(sizeof(InstDesc) / 4); ++i) dst[i] = src[i];
+    return d;
+}
+template <typename T>
+__device__ __forceinline__ T ld_agent(GLOBAL const T *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T>
+__device__ __forceinline__ void st_agent(GLOBAL T *p, T v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T>
+__device__ __forceinline__ T g_exch(GLOBAL T *p, T v) {
+    return __hip_atomic_exchange(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T>
+__device__ __forceinline__ void g_add(GLOBAL T *p, T v) {
+    (void)__hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T>
+__device__ __forceinline__ void g_or(GLOBAL T *p, T v) {
+    (void)__hip_atomic_fetch_or(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T>
+__device__ __forceinline__ void g_and(GLOBAL T *p, T v) {
+    (void)__hip_atomic_fetch_and(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 template <int TW, int TH>
 struct Geo {
     static constexpr int NT = kThreads;
@@ -124,15 +171,15 @@ __device__ __forceinline__ long long block_sum_i64(long long v, unsigned long lo
 //   rt = ct - m; r_k = n-link capacity; inbox cleared.
 // ---------------------------------------------------------------------------
 template <int K, int TW, int TH>
-__device__ void init_tile(const StepParams &P, const InstDesc &D, InstState *S, int tg, int tl,
+__device__ void init_tile(const StepParams &P, const InstDesc &D, InstState *S, int tl,
                           int *s_red, unsigned long long *s_sum) {
     using G = Geo<TW, TH>;
     const int tid = threadIdx.x, lx = tid % TW, ly0 = tid / TW;
     const int tx = tl % D.tiles_x, ty = tl / D.tiles_x;
     const int x0 = tx * TW, y0 = ty * TH;
     const int W = D.W, H = D.H, n = D.n;
-    const long long lam0 = D.lambdas[0];
-    const long long lamL = D.lambdas[D.L - 1];
+    const long long lam0 = gp(D.lambdas)[0];
+    const long long lamL = gp(D.lambdas)[D.L - 1];
     const int32_t nlmax = ((1 << 30) - 1) / K;
     int err = 0;
     long long scs = 0;
@@ -142,7 +189,7 @@ __device__ void init_tile(const StepParams &P, const InstDesc &D, InstState *S, 
         const int gx = x0 + lx, gy = y0 + ly;
         if (gx >= W || gy >= H) continue;
         const int p = gy * W + gx;
-        const int sd = D.seed ? (int)D.seed[p] : 0;
+        const int sd = D.seed ? (int)gp(D.seed)[p] : 0;
         long long cs, ct;
         if (sd == 1) {
             cs = kInf;
@@ -151,9 +198,9 @@ __device__ void init_tile(const StepParams &P, const InstDesc &D, InstState *S, 
             cs = 0;
             ct = kInf;
         } else {
-            const long long c0 = D.cap_snk0[p];
-            const long long sl = D.slope ? D.slope[p] : 1;
-            cs = D.cap_src[p];
+            const long long c0 = gp(D.cap_snk0)[p];
+            const long long sl = D.slope ? gp(D.slope)[p] : 1;
+            cs = gp(D.cap_src)[p];
             if (sd != 0) err |= 1;
             if (cs < 0 || cs > kInf || c0 < 0 || sl < 0) err |= 1;
             if (c0 + sl * lamL > kInf) err |= 2;
@@ -170,37 +217,37 @@ __device__ void init_tile(const StepParams &P, const InstDesc &D, InstState *S, 
         for (int k = 0; k < K; ++k) {
             const int qx = gx + DXk(k), qy = gy + DYk(k);
             const bool on = qx >= 0 && qx < W && qy >= 0 && qy < H;
-            int c = D.nlink[(size_t)k * n + p];
+            int c = gp(D.nlink)[(size_t)k * n + p];
             if (c < 0 || (!on && c != 0)) err |= 1;
             if (c > nlmax) err |= 2;
             if (!on || c < 0) c = 0;
             if (c > nlmax) c = nlmax;
-            D.r[(size_t)k * n + p] = c;
-            D.inbox[(size_t)k * n + p] = 0;
+            gp(D.r)[(size_t)k * n + p] = c;
+            gp(D.inbox)[(size_t)k * n + p] = 0;
             if (c > 0) rm |= 1 << k;
         }
-        D.e[p] = e;
-        D.rt[p] = rt;
-        D.h[p] = rt > 0 ? 1 : kHInf;
-        D.rmask[p] = (uint16_t)rm;
+        gp(D.e)[p] = e;
+        gp(D.rt)[p] = rt;
+        gp(D.h)[p] = rt > 0 ? 1 : kHInf;
+        gp(D.rmask)[p] = (uint16_t)rm;
     }
     if (tl == 0 && tid < 64) {
         // the schedule: lambda_0 >= 0, non-decreasing (also across the start
         // of a chunk of a longer schedule)
         for (int i = tid; i < D.L; i += 64) {
-            const int li = D.lambdas[i];
-            if (li < 0 || (i > 0 && li < D.lambdas[i - 1])) err |= 1;
+            const int li = gp(D.lambdas)[i];
+            if (li < 0 || (i > 0 && li < gp(D.lambdas)[i - 1])) err |= 1;
         }
-        if (tid == 0 && D.check_prev && D.lambdas[-1] > D.lambdas[0]) err |= 1;
+        if (tid == 0 && D.check_prev && gp(D.lambdas)[-1] > gp(D.lambdas)[0]) err |= 1;
     }
     const long long tot = block_sum_i64(scs, s_sum);
     if (tid == 0) {
         if (tot) atomicAdd((unsigned long long *)&S->sum_cs, (unsigned long long)tot);
         count_px(&S->px_init, tile_pixels<TW, TH>(W, H, x0, y0));
-        D.tile_act[tl] = 0;
-        D.tile_cnt[tl] = 0;
-        D.tile_chg[tl] = 1;
-        D.tile_chg[D.ntiles + tl] = 1;
+        gp(D.tile_act)[tl] = 0;
+        gp(D.tile_cnt)[tl] = 0;
+        gp(D.tile_chg)[tl] = 1;
+        gp(D.tile_chg)[D.ntiles + tl] = 1;
     }
     if (err) atomicOr(&S->err, err);
     (void)s_red;
@@ -226,15 +273,11 @@ __device__ void init_tile(const StepParams &P, const InstDesc &D, InstState *S, 
 // amount handed over; those words go to the neighbours' inboxes at the end.
 // ---------------------------------------------------------------------------
 template <int K, int TW, int TH>
-__device__ void sweep_tile(const StepParams &P, const InstDesc &D, InstState *S, int tg, int tl,
+__device__ void sweep_tile(const StepParams &P, const InstDesc &D, InstState *S, int tl,
                            int iters, int32_t *lds, int *s_red) {
     using G = Geo<TW, TH>;
     constexpr int PPT = G::PPT, RPI = G::RPI, HW = G::HW, HH = G::HH, HALO = G::HALO;
     const int tid = threadIdx.x, lx = tid % TW, ly0 = tid / TW;
-    // neighbours may set the pending bit concurrently: one read, broadcast
-    if (tid == 0) s_red[1] = (int)(ld_agent(&D.tile_act[tl]) & 3u);
-    __syncthreads();
-    if (s_red[1] == 0) return;  // nothing to push here, nothing arrived
     const int tx = tl % D.tiles_x, ty = tl / D.tiles_x;
     const int x0 = tx * TW, y0 = ty * TH;
     const int W = D.W, H = D.H, n = D.n;
@@ -247,55 +290,79 @@ __device__ void sweep_tile(const StepParams &P, const InstDesc &D, InstState *S,
     __shared__ uint16_t s_slot[kThreads * PPT];  // per wave: its active pixels' cells
 
     if (tid < 9) s_nb[tid] = 0;
-    if (tid == 0) atomicAnd(&D.tile_act[tl], ~2u);  // about to drain the inbox
-    // halo cells: heights of the neighbour tiles, zeroed hand-over words
-    for (int i = tid; i < G::RING; i += kThreads) {
-        int hx, hy;
-        G::ring(i, hx, hy);
-        const int gx = x0 + hx - 1, gy = y0 + hy - 1;
-        const int c = hy * HW + hx;
-        sh_h[c] = (gx >= 0 && gx < W && gy >= 0 && gy < H) ? D.h[gy * W + gx] : kHInf;
-#pragma unroll
-        for (int k = 0; k < K; ++k) sh_r[c * K + k] = 0;
-    }
+    if (tid == 0) g_and(&gp(D.tile_act)[tl], ~2u);  // about to drain the inbox
+    // Every global load of the visit is issued before any is used: the halo
+    // cell heights of the neighbour tiles (one ring cell per thread), the
+    // state of the thread's pixels, and the inbox words of the arcs that cross
+    // the tile border (flow pushed in by neighbour tiles), spread over all
+    // threads as (border pixel, arc) pairs.  Loads of cells outside the image
+    // read a clamped in-image address and are replaced by the defaults.
     bool valid[PPT];
+    int e[PPT], rt[PPT], h[PPT], r[PPT][K];
 #pragma unroll
     for (int j = 0; j < PPT; ++j) {
-        const int ly = ly0 + j * RPI;
-        const int gx = x0 + lx, gy = y0 + ly;
-        const int c = (ly + 1) * HW + lx + 1;
+        const int gx = x0 + lx, gy = y0 + ly0 + j * RPI;
         valid[j] = gx < W && gy < H;
-        int e = 0, rt = 0, h = kHInf, r[K];
+        const int p = min(gy, H - 1) * W + min(gx, W - 1);
+        e[j] = gp(D.e)[p];
 #pragma unroll
-        for (int k = 0; k < K; ++k) r[k] = 0;
-        if (valid[j]) {
-            const int p = gy * W + gx;
-            e = D.e[p];
+        for (int k = 0; k < K; ++k) r[j][k] = gp(D.r)[(size_t)k * n + p];
+        rt[j] = gp(D.rt)[p];
+        h[j] = gp(D.h)[p];
+    }
+    static_assert(G::RING <= kThreads, "one halo cell per thread");
+    int hx, hy;
+    G::ring(min(tid, G::RING - 1), hx, hy);
+    const int hc = hy * HW + hx;
+    const bool hin = x0 + hx - 1 >= 0 && x0 + hx - 1 < W && y0 + hy - 1 >= 0 && y0 + hy - 1 < H;
+    const int hv = gp(D.h)[min(max(y0 + hy - 1, 0), H - 1) * W + min(max(x0 + hx - 1, 0), W - 1)];
+    constexpr int NB = 2 * TW + 2 * (TH - 2);                // border pixels
+    constexpr int NBP = (NB * K + kThreads - 1) / kThreads;  // pairs per thread
+    int ibv[NBP], ibc[NBP];
+    bool ibx[NBP];
+    GLOBAL int32_t *iba[NBP];
 #pragma unroll
-            for (int k = 0; k < K; ++k) r[k] = D.r[(size_t)k * n + p];
-            rt = D.rt[p];
-            h = D.h[p];
-            // drain flow pushed in by neighbour tiles
+    for (int q = 0; q < NBP; ++q) {
+        const int i = min(tid + q * kThreads, NB * K - 1);
+        const int b = i / K, k = i - b * K;
+        const int bx = b < TW ? b : b < 2 * TW ? b - TW : b < 2 * TW + TH - 2 ? 0 : TW - 1;
+        const int by = b < TW ? 0 : b < 2 * TW ? TH - 1 : 1 + (b - 2 * TW) % (TH - 2);
+        const int nx = bx + DXk(k), ny = by + DYk(k);
+        const int gx = x0 + bx, gy = y0 + by;
+        const int qx = gx + DXk(k), qy = gy + DYk(k);
+        ibx[q] = tid + q * kThreads < NB * K && (nx < 0 || nx >= TW || ny < 0 || ny >= TH) && gx < W &&
+                 gy < H && qx >= 0 && qx < W && qy >= 0 && qy < H;
+        iba[q] = &gp(D.inbox)[(size_t)k * n + min(gy, H - 1) * W + min(gx, W - 1)];
+        ibc[q] = (((by + 1) * HW + bx + 1) << 4) | k;
+        ibv[q] = ld_agent(iba[q]);  // in-image address in every case; used only where ibx
+    }
 #pragma unroll
-            for (int k = 0; k < K; ++k) {
-                const int nx = lx + DXk(k), ny = ly + DYk(k);
-                if (nx >= 0 && nx < TW && ny >= 0 && ny < TH) continue;
-                const int qx = gx + DXk(k), qy = gy + DYk(k);
-                if (qx < 0 || qx >= W || qy < 0 || qy >= H) continue;
-                int32_t *slot = &D.inbox[(size_t)k * n + p];
-                int v = ld_agent(slot);
-                if (v) {
-                    v = atomicExch(slot, 0);
-                    e += v;
-                    r[k] += v;
-                }
-            }
+    for (int q = 0; q < NBP; ++q) {
+        ibv[q] = ibx[q] ? ibv[q] : 0;
+        if (ibv[q]) ibv[q] = g_exch(iba[q], 0);
+    }
+    if (tid < G::RING) {
+        sh_h[hc] = hin ? hv : kHInf;
+#pragma unroll
+        for (int k = 0; k < K; ++k) sh_r[hc * K + k] = 0;  // hand-over words
+    }
+#pragma unroll
+    for (int j = 0; j < PPT; ++j) {
+        const int c = (ly0 + j * RPI + 1) * HW + lx + 1;
+        sh_e[c] = valid[j] ? e[j] : 0;
+        sh_t[c] = valid[j] ? rt[j] : 0;
+#pragma unroll
+        for (int k = 0; k < K; ++k) sh_r[c * K + k] = valid[j] ? r[j][k] : 0;
+        sh_h[c] = valid[j] ? h[j] : kHInf;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < NBP; ++q) {
+        if (ibv[q]) {
+            const int c = ibc[q] >> 4, k = ibc[q] & 15;
+            atomicAdd(&sh_e[c], ibv[q]);
+            atomicAdd(&sh_r[c * K + k], ibv[q]);
         }
-        sh_e[c] = e;
-        sh_t[c] = rt;
-#pragma unroll
-        for (int k = 0; k < K; ++k) sh_r[c * K + k] = r[k];
-        sh_h[c] = h;
     }
     __syncthreads();
 
@@ -394,13 +461,13 @@ __device__ void sweep_tile(const StepParams &P, const InstDesc &D, InstState *S,
 #pragma unroll
         for (int k = 0; k < K; ++k) {
             const int r = sh_r[c * K + k];
-            D.r[(size_t)k * n + p] = r;
+            gp(D.r)[(size_t)k * n + p] = r;
             if (r > 0) rm |= 1 << k;
         }
-        D.e[p] = e;
-        D.rt[p] = rt;
-        D.h[p] = h;
-        D.rmask[p] = (uint16_t)rm;
+        gp(D.e)[p] = e;
+        gp(D.rt)[p] = rt;
+        gp(D.h)[p] = h;
+        gp(D.rmask)[p] = (uint16_t)rm;
     }
     // hand pushes into halo cells to the neighbour tiles' inboxes: the word
     // k of halo cell q with q + d_k inside the tile holds what q received
@@ -415,7 +482,7 @@ __device__ void sweep_tile(const StepParams &P, const InstDesc &D, InstState *S,
             if (ix < 1 || ix > TW || iy < 1 || iy > TH) continue;
             const int v = sh_r[c * K + k];
             if (v > 0 && gx >= 0 && gx < W && gy >= 0 && gy < H) {
-                atomicAdd(&D.inbox[(size_t)k * n + gy * W + gx], v);
+                g_add(&gp(D.inbox)[(size_t)k * n + gy * W + gx], v);
                 const int dtx = hx == 0 ? 0 : (hx == HW - 1 ? 2 : 1);
                 const int dty = hy == 0 ? 0 : (hy == HH - 1 ? 2 : 1);
                 s_nb[dty * 3 + dtx] = 1;
@@ -426,20 +493,20 @@ __device__ void sweep_tile(const StepParams &P, const InstDesc &D, InstState *S,
     if (tid < 9 && tid != 4 && s_nb[tid]) {
         const int ntx = tx + (tid % 3) - 1, nty = ty + (tid / 3) - 1;
         if (ntx >= 0 && ntx < D.tiles_x && nty >= 0 && nty < D.tiles_y)
-            atomicOr(&D.tile_act[nty * D.tiles_x + ntx], 2u);
+            g_or(&gp(D.tile_act)[nty * D.tiles_x + ntx], 2u);
     }
     if (tid == 0) {
         if (tile_active)
-            atomicOr(&D.tile_act[tl], 1u);
+            g_or(&gp(D.tile_act)[tl], 1u);
         else
-            atomicAnd(&D.tile_act[tl], ~1u);
+            g_and(&gp(D.tile_act)[tl], ~1u);
         count_px(&S->px_sweep, tile_pixels<TW, TH>(W, H, x0, y0));
     }
 }
 
 // Whether this tile or one of its neighbours changed a label in the previous pass.
 __device__ __forceinline__ bool frontier_needs(const InstDesc &D, int tx, int ty, int prev) {
-    const uint8_t *chg = D.tile_chg + (size_t)prev * D.ntiles;
+    GLOBAL const uint8_t *chg = gp(D.tile_chg) + (size_t)prev * D.ntiles;
     bool need = false;
 #pragma unroll
     for (int dy = -1; dy <= 1; ++dy)
@@ -456,7 +523,7 @@ __device__ __forceinline__ bool frontier_needs(const InstDesc &D, int tx, int ty
 // kRelabel: one pass of the exact global relabel (distance to t).
 // ---------------------------------------------------------------------------
 template <int K, int TW, int TH>
-__device__ void relabel_tile(const StepParams &P, const InstDesc &D, InstState *S, int tg, int tl,
+__device__ void relabel_tile(const StepParams &P, const InstDesc &D, InstState *S, int tl,
                              int sub, int xrounds, int32_t *lds, int *s_red) {
     using G = Geo<TW, TH>;
     constexpr int PPT = G::PPT, RPI = G::RPI, HW = G::HW;
@@ -465,11 +532,7 @@ __device__ void relabel_tile(const StepParams &P, const InstDesc &D, InstState *
     const int x0 = tx * TW, y0 = ty * TH;
     const int W = D.W, H = D.H, n = D.n;
     const bool first = sub == 0;
-    const int cur = sub & 1, prev = cur ^ 1;
-    if (!first && !frontier_needs(D, tx, ty, prev)) {
-        if (tid == 0) D.tile_chg[(size_t)cur * D.ntiles + tl] = 0;
-        return;
-    }
+    const int cur = sub & 1;  // tile_chg parity written by this pass
     int32_t *sh_d = lds;
     int d[PPT], d0[PPT];
     uint32_t rm[PPT];
@@ -481,7 +544,7 @@ __device__ void relabel_tile(const StepParams &P, const InstDesc &D, InstState *
         d[j] = kHInf;
         if (gx < W && gy < H) {
             const int p = gy * W + gx;
-            rm[j] = D.rmask[p];
+            rm[j] = gp(D.rmask)[p];
             if (first) {
                 // fold flow that neighbour tiles pushed into this pixel
                 int ein = 0;
@@ -492,22 +555,22 @@ __device__ void relabel_tile(const StepParams &P, const InstDesc &D, InstState *
                     if (nx >= 0 && nx < TW && ny >= 0 && ny < TH) continue;
                     const int qx = gx + DXk(k), qy = gy + DYk(k);
                     if (qx < 0 || qx >= W || qy < 0 || qy >= H) continue;
-                    const int v = D.inbox[(size_t)k * n + p];
+                    const int v = gp(D.inbox)[(size_t)k * n + p];
                     if (v) {
-                        D.inbox[(size_t)k * n + p] = 0;
-                        D.r[(size_t)k * n + p] += v;
+                        gp(D.inbox)[(size_t)k * n + p] = 0;
+                        gp(D.r)[(size_t)k * n + p] += v;
                         ein += v;
                         radd |= 1u << k;
                     }
                 }
                 if (ein) {
-                    D.e[p] += ein;
+                    gp(D.e)[p] += ein;
                     rm[j] |= radd | kEBit;
-                    D.rmask[p] = (uint16_t)rm[j];
+                    gp(D.rmask)[p] = (uint16_t)rm[j];
                 }
                 d[j] = (rm[j] & kRtBit) ? 1 : kHInf;
             } else {
-                d[j] = D.h[p];
+                d[j] = gp(D.h)[p];
             }
         }
         d0[j] = d[j];
@@ -520,7 +583,7 @@ __device__ void relabel_tile(const StepParams &P, const InstDesc &D, InstState *
         int v = kHInf;
         if (gx >= 0 && gx < W && gy >= 0 && gy < H) {
             const int q = gy * W + gx;
-            v = first ? ((D.rmask[q] & kRtBit) ? 1 : kHInf) : D.h[q];
+            v = first ? ((gp(D.rmask)[q] & kRtBit) ? 1 : kHInf) : gp(D.h)[q];
         }
         sh_d[hy * HW + hx] = v;
     }
@@ -575,7 +638,7 @@ __device__ void relabel_tile(const StepParams &P, const InstDesc &D, InstState *
         const int ly = ly0 + j * RPI;
         const int gx = x0 + lx, gy = y0 + ly;
         if (gx < W && gy < H && d[j] < dpub[j]) {
-            __hip_atomic_store(&D.h[gy * W + gx], d[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            st_agent(&gp(D.h)[gy * W + gx], d[j]);
             dpub[j] = d[j];
         }
     }
@@ -585,7 +648,7 @@ __device__ void relabel_tile(const StepParams &P, const InstDesc &D, InstState *
         G::ring(i, hx, hy);
         const int gx = x0 + hx - 1, gy = y0 + hy - 1;
         if (gx < 0 || gx >= W || gy < 0 || gy >= H) continue;
-        const int v = ld_agent(&D.h[gy * W + gx]);
+        const int v = ld_agent(&gp(D.h)[gy * W + gx]);
         if (v < sh_d[hy * HW + hx]) {
             sh_d[hy * HW + hx] = v;
             got = 1;
@@ -602,17 +665,17 @@ __device__ void relabel_tile(const StepParams &P, const InstDesc &D, InstState *
         act[j] = (rm[j] & kEBit) && d[j] < kHInf;  // rm = 0 outside the image
         if (gx >= W || gy >= H) continue;
         if (first || d[j] != d0[j]) changed = 1;
-        if (first || d[j] != dpub[j]) D.h[gy * W + gx] = d[j];
+        if (first || d[j] != dpub[j]) gp(D.h)[gy * W + gx] = d[j];
     }
     const int tchg = __syncthreads_or(changed);
     const int tcnt = block_count_ballot(act, s_red);
     if (tid == 0) {
-        D.tile_chg[(size_t)cur * D.ntiles + tl] = (uint8_t)(tchg ? 1 : 0);
-        const int delta = first ? tcnt : tcnt - D.tile_cnt[tl];
-        D.tile_cnt[tl] = tcnt;
+        gp(D.tile_chg)[(size_t)cur * D.ntiles + tl] = (uint8_t)(tchg ? 1 : 0);
+        const int delta = first ? tcnt : tcnt - gp(D.tile_cnt)[tl];
+        gp(D.tile_cnt)[tl] = tcnt;
         if (delta) atomicAdd(&S->active, delta);
         if (tchg) atomicOr(&S->changed, 1);
-        D.tile_act[tl] = tcnt > 0 ? 1u : 0u;
+        gp(D.tile_act)[tl] = tcnt > 0 ? 1u : 0u;
         count_px(&S->px_relabel, tile_pixels<TW, TH>(W, H, x0, y0));
     }
 }
@@ -623,7 +686,7 @@ __device__ void relabel_tile(const StepParams &P, const InstDesc &D, InstState *
 // to the next lambda (warm start).
 // ---------------------------------------------------------------------------
 template <int K, int TW, int TH>
-__device__ void cut_tile(const StepParams &P, const InstDesc &D, InstState *S, int tg, int tl, int sub,
+__device__ void cut_tile(const StepParams &P, const InstDesc &D, InstState *S, int tl, int sub,
                          int kk, int xrounds, int32_t *lds, int *s_red, unsigned long long *s_sum) {
     using G = Geo<TW, TH>;
     constexpr int PPT = G::PPT, RPI = G::RPI, HW = G::HW;
@@ -632,17 +695,13 @@ __device__ void cut_tile(const StepParams &P, const InstDesc &D, InstState *S, i
     const int x0 = tx * TW, y0 = ty * TH;
     const int W = D.W, H = D.H, n = D.n;
     const bool first = sub == 0;
-    const int cur = sub & 1, prev = cur ^ 1;
-    if (!first && !frontier_needs(D, tx, ty, prev)) {
-        if (tid == 0) D.tile_chg[(size_t)cur * D.ntiles + tl] = 0;
-        return;
-    }
-    uint8_t *mask = D.masks + (size_t)kk * n;
+    const int cur = sub & 1;  // tile_chg parity written by this pass
+    GLOBAL uint8_t *mask = gp(D.masks) + (size_t)kk * n;
     // one LDS word per cell: the residual bits, and bit 15 = reached
     constexpr int kReached = 1 << 15;
     int32_t *sh_w = lds;
     const bool raise = first && kk + 1 < D.L;
-    const int dlam = raise ? D.lambdas[kk + 1] - D.lambdas[kk] : 0;
+    const int dlam = raise ? gp(D.lambdas)[kk + 1] - gp(D.lambdas)[kk] : 0;
     int m[PPT], m0[PPT], rmv[PPT];
     long long se = 0;
 #pragma unroll
@@ -653,17 +712,17 @@ __device__ void cut_tile(const StepParams &P, const InstDesc &D, InstState *S, i
         m[j] = 0;
         if (gx < W && gy < H) {
             const int p = gy * W + gx;
-            rmv[j] = D.rmask[p];
+            rmv[j] = gp(D.rmask)[p];
             if (first) {
                 m[j] = (rmv[j] & kEBit) ? 1 : 0;
-                if (m[j]) se += D.e[p];
+                if (m[j]) se += gp(D.e)[p];
                 if (dlam > 0) {
-                    const int sd = D.seed ? (int)D.seed[p] : 0;
-                    const int sl = sd == 0 ? (D.slope ? D.slope[p] : 1) : 0;
+                    const int sd = D.seed ? (int)gp(D.seed)[p] : 0;
+                    const int sl = sd == 0 ? (D.slope ? gp(D.slope)[p] : 1) : 0;
                     if (sl > 0) {
-                        const int nrt = D.rt[p] + sl * dlam;
-                        D.rt[p] = nrt;
-                        if (nrt > 0 && !(rmv[j] & kRtBit)) D.rmask[p] = (uint16_t)(rmv[j] | kRtBit);
+                        const int nrt = gp(D.rt)[p] + sl * dlam;
+                        gp(D.rt)[p] = nrt;
+                        if (nrt > 0 && !(rmv[j] & kRtBit)) gp(D.rmask)[p] = (uint16_t)(rmv[j] | kRtBit);
                     }
                 }
             } else {
@@ -680,7 +739,7 @@ __device__ void cut_tile(const StepParams &P, const InstDesc &D, InstState *S, i
         int w = 0;
         if (gx >= 0 && gx < W && gy >= 0 && gy < H) {
             const int q = gy * W + gx;
-            const int rq = D.rmask[q];
+            const int rq = gp(D.rmask)[q];
             const int mq = first ? ((rq & kEBit) ? 1 : 0) : mask[q];
             w = rq | (mq ? kReached : 0);
         }
@@ -731,7 +790,7 @@ __device__ void cut_tile(const StepParams &P, const InstDesc &D, InstState *S, i
         const int ly = ly0 + j * RPI;
         const int gx = x0 + lx, gy = y0 + ly;
         if (gx < W && gy < H && m[j] && !mpub[j]) {
-            __hip_atomic_store(&mask[gy * W + gx], (uint8_t)1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            st_agent(&mask[gy * W + gx], (uint8_t)1);
             mpub[j] = 1;
         }
     }
@@ -762,7 +821,7 @@ __device__ void cut_tile(const StepParams &P, const InstDesc &D, InstState *S, i
     long long tse = 0;
     if (first) tse = block_sum_i64(se, s_sum);
     if (tid == 0) {
-        D.tile_chg[(size_t)cur * D.ntiles + tl] = (uint8_t)(tchg ? 1 : 0);
+        gp(D.tile_chg)[(size_t)cur * D.ntiles + tl] = (uint8_t)(tchg ? 1 : 0);
         if (tchg) atomicOr(&S->changed, 1);
         if (tse) atomicAdd((unsigned long long *)&S->sum_e, (unsigned long long)tse);
         count_px(&S->px_cut, tile_pixels<TW, TH>(W, H, x0, y0));
@@ -826,7 +885,7 @@ __device__ void control(const StepParams &P) {
                 S->passes += 1;
                 if (S->sub > 0 && !changed) {
                     const int k = S->k;
-                    D->flows[k] = ld_agent(&S->sum_cs) - ld_agent(&S->sum_e);
+                    gp(D->flows)[k] = ld_agent(&S->sum_cs) - ld_agent(&S->sum_e);
                     S->sum_e = 0;
                     S->k = k + 1;
                     if (k + 1 >= D->L) {
@@ -849,9 +908,9 @@ __device__ void control(const StepParams &P) {
         if (done) {
             if (status != PMF_OK) {
                 const int from = status == PMF_ETIMEOUT ? S->k : 0;
-                for (int k = from; k < D->L; ++k) D->flows[k] = -1;
+                for (int k = from; k < D->L; ++k) gp(D->flows)[k] = -1;
             }
-            if (D->status) *D->status = status;
+            if (D->status) *gp(D->status) = status;
             ph = kDone;
             const int at = atomicAdd(P.ring_count, 1);
             P.ring[at % P.ring_cap] = i;
@@ -862,7 +921,7 @@ __device__ void control(const StepParams &P) {
 
 // Append `value` to `list` for every lane whose `want` is set: one atomic per
 // wave on the list counter, lanes packed in lane order.
-__device__ __forceinline__ void wave_append(bool want, int32_t *list, int32_t *count, int value) {
+__device__ __forceinline__ void wave_append(bool want, int2 *list, int32_t *count, int2 value) {
     const unsigned long long m = __ballot(want);
     if (m == 0ull) return;
     const int lane = threadIdx.x & 63;
@@ -877,21 +936,26 @@ __device__ __forceinline__ void wave_append(bool want, int32_t *list, int32_t *c
 // a sweep (instance sweeping, pixels active or inflow pending) and the tiles
 // that need a relabel / cut / init pass (first pass of a phase, or a change in
 // the 3x3 tile neighbourhood during the previous pass) go to four lists
-// (sweep K=4, sweep K=8, pass K=4, pass K=8).  Skipped pass tiles record "no
-// change" for the current pass here, as a processed tile would.
+// (sweep K=4, sweep K=8, pass K=4, pass K=8) as {instance slot, tile} pairs.
+// Skipped pass tiles record "no change" for the current pass here, as a
+// processed tile would.  The tile kernels rely on these tests: a listed tile
+// is in range, its instance in the listed phase (phases change only in the
+// control kernel), a listed sweep tile has work, a listed pass tile needs
+// the pass.
 __global__ __launch_bounds__(kThreads) void k_compact(StepParams P) {
     const int t = blockIdx.x * kThreads + threadIdx.x;
     bool sw = false, bf = false, is8 = false;
+    int slot = 0, tl = 0;
     if (t < P.ntiles) {
-        const int slot = P.tile_slot[t];
-        const int tl = P.tile_local[t];
+        slot = P.tile_slot[t];
+        tl = P.tile_local[t];
         const InstState *S = &P.st[slot];
         const InstDesc *D = &P.desc[slot];
         const int phase = S->phase;
         is8 = t >= P.t8_begin;
         if (tl < D->ntiles) {
             if (phase == kSweep) {
-                sw = (D->tile_act[tl] & 3u) != 0u;
+                sw = (gp(D->tile_act)[tl] & 3u) != 0u;
             } else if (phase == kInit) {
                 bf = true;
             } else if (phase == kRelabel || phase == kCut) {
@@ -901,30 +965,37 @@ __global__ __launch_bounds__(kThreads) void k_compact(StepParams P) {
                 } else {
                     const int tx = tl % D->tiles_x, ty = tl / D->tiles_x;
                     bf = frontier_needs(*D, tx, ty, (sub & 1) ^ 1);
-                    if (!bf) D->tile_chg[(size_t)(sub & 1) * D->ntiles + tl] = 0;
+                    if (!bf) gp(D->tile_chg)[(size_t)(sub & 1) * D->ntiles + tl] = 0;
                 }
             }
         }
     }
-    wave_append(sw && !is8, P.lists, P.list_count + 0, t);
-    wave_append(sw && is8, P.lists + (size_t)P.list_cap, P.list_count + 1, t);
-    wave_append(bf && !is8, P.lists + 2 * (size_t)P.list_cap, P.list_count + 2, t);
-    wave_append(bf && is8, P.lists + 3 * (size_t)P.list_cap, P.list_count + 3, t);
+    const int2 en = make_int2(slot, tl);
+    int2 *lists = reinterpret_cast<int2 *>(P.lists);
+    wave_append(sw && !is8, lists, P.list_count + 0, en);
+    wave_append(sw && is8, lists + (size_t)P.list_cap, P.list_count + 1, en);
+    wave_append(bf && !is8, lists + 2 * (size_t)P.list_cap, P.list_count + 2, en);
+    wave_append(bf && is8, lists + 3 * (size_t)P.list_cap, P.list_count + 3, en);
 }
 
 // Workgroup b of a list-driven launch takes items of its XCD's eighth of the
 // list (b & 7 picks the eighth, b >> 3 strides inside it), so that
 // consecutive items -- neighbouring tiles of one image -- share an L2.
 struct ListWalk {
-    const int32_t *list;
+    const int2 *list;
     int cnt, eighth, stride, base, first;
     __device__ ListWalk(const StepParams &P, int which) {
         cnt = P.list_count[which];
-        list = P.lists + (size_t)which * P.list_cap;
+        list = reinterpret_cast<const int2 *>(P.lists) + (size_t)which * P.list_cap;
         eighth = (cnt + 7) >> 3;
         stride = (int)(gridDim.x >> 3);
         base = (int)(blockIdx.x & 7) * eighth;
         first = (int)(blockIdx.x >> 3);
+    }
+    // item i of this workgroup, the same for every thread (scalar registers)
+    __device__ int2 next(int i) const {
+        const int2 en = list[base + i];
+        return make_int2(__builtin_amdgcn_readfirstlane(en.x), __builtin_amdgcn_readfirstlane(en.y));
     }
 };
 
@@ -938,15 +1009,10 @@ __global__ __launch_bounds__(kThreads) void k_sweep(StepParams P, int which) {
     const int iters =
         P.list_count[0] + P.list_count[1] < P.tail_tiles ? P.tail_inner_iters : P.inner_iters;
     for (int i = w.first; i < w.eighth && w.base + i < w.cnt; i += w.stride) {
-        const int t = w.list[w.base + i];
+        const int2 en = w.next(i);
         __syncthreads();  // the previous tile's LDS is no longer in use
-        const int slot = P.tile_slot[t];
-        InstState *S = &P.st[slot];
-        if (S->phase != kSweep) continue;
-        const InstDesc D = P.desc[slot];
-        const int tl = P.tile_local[t];
-        if (tl >= D.ntiles) continue;
-        sweep_tile<K, TW, TH>(P, D, S, t, tl, iters, lds, s_red);
+        const InstDesc D = load_desc(P.desc, en.x);
+        sweep_tile<K, TW, TH>(P, D, &P.st[en.x], en.y, iters, lds, s_red);
     }
 }
 
@@ -959,22 +1025,18 @@ __global__ __launch_bounds__(kThreads) void k_bfs(StepParams P, int which) {
     const int xrounds =
         P.list_count[2] + P.list_count[3] < P.tail_tiles ? P.tail_exchange_rounds : P.exchange_rounds;
     for (int i = w.first; i < w.eighth && w.base + i < w.cnt; i += w.stride) {
-        const int t = w.list[w.base + i];
+        const int2 en = w.next(i);
         __syncthreads();
-        const int slot = P.tile_slot[t];
-        InstState *S = &P.st[slot];
-        const int phase = S->phase;
-        if (phase != kInit && phase != kRelabel && phase != kCut) continue;
-        const InstDesc D = P.desc[slot];
-        const int tl = P.tile_local[t];
-        if (tl >= D.ntiles) continue;
-        const int sub = S->sub, kk = S->k;
+        InstState *S = &P.st[en.x];
+        const int phase = S->phase, sub = S->sub, kk = S->k;
+        const InstDesc D = load_desc(P.desc, en.x);
+        const int tl = en.y;
         if (phase == kInit)
-            init_tile<K, TW, TH>(P, D, S, t, tl, s_red, &s_sum);
+            init_tile<K, TW, TH>(P, D, S, tl, s_red, &s_sum);
         else if (phase == kRelabel)
-            relabel_tile<K, TW, TH>(P, D, S, t, tl, sub, xrounds, lds, s_red);
+            relabel_tile<K, TW, TH>(P, D, S, tl, sub, xrounds, lds, s_red);
         else
-            cut_tile<K, TW, TH>(P, D, S, t, tl, sub, kk, xrounds, lds, s_red, &s_sum);
+            cut_tile<K, TW, TH>(P, D, S, tl, sub, kk, xrounds, lds, s_red, &s_sum);
     }
 }
 
