@@ -533,60 +533,94 @@ __device__ void relabel_tile(const StepParams &P, const InstDesc &D, InstState *
     const int W = D.W, H = D.H, n = D.n;
     const bool first = sub == 0;
     const int cur = sub & 1;  // tile_chg parity written by this pass
-    int32_t *sh_d = lds;
-    int d[PPT], d0[PPT];
+    int32_t *sh_d = lds;              // [HALO] labels
+    int32_t *sh_in = lds + G::HALO;   // first pass: inflow folded into each tile cell
+    int32_t *sh_ib = lds + 2 * G::HALO;  // first pass: arcs whose residual the inflow raised
+    // Every global load is issued before any is used (cells outside the
+    // image read a clamped in-image address and take the defaults): the
+    // pixels' residual masks (and labels after the first pass), one halo cell
+    // per thread, and in the first pass the inbox words of the arcs that cross
+    // the tile border with the residuals they raise, spread over all threads
+    // as (border pixel, arc) pairs.
+    bool valid[PPT];
     uint32_t rm[PPT];
+    int d[PPT], d0[PPT];
 #pragma unroll
     for (int j = 0; j < PPT; ++j) {
-        const int ly = ly0 + j * RPI;
-        const int gx = x0 + lx, gy = y0 + ly;
-        rm[j] = 0;
-        d[j] = kHInf;
-        if (gx < W && gy < H) {
-            const int p = gy * W + gx;
-            rm[j] = gp(D.rmask)[p];
-            if (first) {
-                // fold flow that neighbour tiles pushed into this pixel
-                int ein = 0;
-                uint32_t radd = 0;
+        const int gx = x0 + lx, gy = y0 + ly0 + j * RPI;
+        valid[j] = gx < W && gy < H;
+        const int p = min(gy, H - 1) * W + min(gx, W - 1);
+        rm[j] = gp(D.rmask)[p];
+        d[j] = first ? 0 : gp(D.h)[p];
+    }
+    int hx, hy;
+    G::ring(min(tid, G::RING - 1), hx, hy);
+    const bool hin = x0 + hx - 1 >= 0 && x0 + hx - 1 < W && y0 + hy - 1 >= 0 && y0 + hy - 1 < H;
+    const int hq = min(max(y0 + hy - 1, 0), H - 1) * W + min(max(x0 + hx - 1, 0), W - 1);
+    const int hv = first ? (int)gp(D.rmask)[hq] : gp(D.h)[hq];
+    if (first) {
+        // fold flow that neighbour tiles pushed into the border pixels
+        constexpr int NB = 2 * TW + 2 * (TH - 2);
+        constexpr int NBP = (NB * K + kThreads - 1) / kThreads;
+        int ibv[NBP], ibr[NBP], ibc[NBP];
+        bool ibx[NBP];
+        size_t iba[NBP];
 #pragma unroll
-                for (int k = 0; k < K; ++k) {
-                    const int nx = lx + DXk(k), ny = ly + DYk(k);
-                    if (nx >= 0 && nx < TW && ny >= 0 && ny < TH) continue;
-                    const int qx = gx + DXk(k), qy = gy + DYk(k);
-                    if (qx < 0 || qx >= W || qy < 0 || qy >= H) continue;
-                    const int v = gp(D.inbox)[(size_t)k * n + p];
-                    if (v) {
-                        gp(D.inbox)[(size_t)k * n + p] = 0;
-                        gp(D.r)[(size_t)k * n + p] += v;
-                        ein += v;
-                        radd |= 1u << k;
-                    }
-                }
-                if (ein) {
-                    gp(D.e)[p] += ein;
-                    rm[j] |= radd | kEBit;
-                    gp(D.rmask)[p] = (uint16_t)rm[j];
-                }
-                d[j] = (rm[j] & kRtBit) ? 1 : kHInf;
-            } else {
-                d[j] = gp(D.h)[p];
+        for (int q = 0; q < NBP; ++q) {
+            const int i = min(tid + q * kThreads, NB * K - 1);
+            const int b = i / K, k = i - b * K;
+            const int bx = b < TW ? b : b < 2 * TW ? b - TW : b < 2 * TW + TH - 2 ? 0 : TW - 1;
+            const int by = b < TW ? 0 : b < 2 * TW ? TH - 1 : 1 + (b - 2 * TW) % (TH - 2);
+            const int nx = bx + DXk(k), ny = by + DYk(k);
+            const int gx = x0 + bx, gy = y0 + by;
+            const int qx = gx + DXk(k), qy = gy + DYk(k);
+            ibx[q] = tid + q * kThreads < NB * K && (nx < 0 || nx >= TW || ny < 0 || ny >= TH) && gx < W &&
+                     gy < H && qx >= 0 && qx < W && qy >= 0 && qy < H;
+            iba[q] = (size_t)k * n + min(gy, H - 1) * W + min(gx, W - 1);
+            ibc[q] = (((by + 1) * HW + bx + 1) << 4) | k;
+            ibv[q] = gp(D.inbox)[iba[q]];
+            ibr[q] = gp(D.r)[iba[q]];
+        }
+#pragma unroll
+        for (int j = 0; j < PPT; ++j) {
+            const int c = (ly0 + j * RPI + 1) * HW + lx + 1;
+            sh_in[c] = 0;
+            sh_ib[c] = 0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < NBP; ++q) {
+            const int v = ibx[q] ? ibv[q] : 0;
+            if (v) {
+                const int c = ibc[q] >> 4, k = ibc[q] & 15;
+                gp(D.inbox)[iba[q]] = 0;
+                gp(D.r)[iba[q]] = ibr[q] + v;
+                atomicAdd(&sh_in[c], v);
+                atomicOr(&sh_ib[c], 1 << k);
             }
         }
-        d0[j] = d[j];
-        sh_d[(ly + 1) * HW + lx + 1] = d[j];
-    }
-    for (int i = tid; i < G::RING; i += kThreads) {
-        int hx, hy;
-        G::ring(i, hx, hy);
-        const int gx = x0 + hx - 1, gy = y0 + hy - 1;
-        int v = kHInf;
-        if (gx >= 0 && gx < W && gy >= 0 && gy < H) {
-            const int q = gy * W + gx;
-            v = first ? ((gp(D.rmask)[q] & kRtBit) ? 1 : kHInf) : gp(D.h)[q];
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < PPT; ++j) {
+            const int c = (ly0 + j * RPI + 1) * HW + lx + 1;
+            const int ein = sh_in[c];
+            if (ein && valid[j]) {
+                const int p = (y0 + ly0 + j * RPI) * W + x0 + lx;
+                g_add(&gp(D.e)[p], ein);
+                rm[j] |= (uint32_t)sh_ib[c] | kEBit;
+                gp(D.rmask)[p] = (uint16_t)rm[j];
+            }
         }
-        sh_d[hy * HW + hx] = v;
     }
+#pragma unroll
+    for (int j = 0; j < PPT; ++j) {
+        rm[j] = valid[j] ? rm[j] : 0u;
+        d[j] = !valid[j] ? kHInf : first ? ((rm[j] & kRtBit) ? 1 : kHInf) : d[j];
+        d0[j] = d[j];
+        sh_d[(ly0 + j * RPI + 1) * HW + lx + 1] = d[j];
+    }
+    if (tid < G::RING)
+        sh_d[hy * HW + hx] = !hin ? kHInf : first ? ((hv & kRtBit) ? 1 : kHInf) : hv;
     __syncthreads();
     // After the first pass of a relabel every stored label is an upper bound
     // of the true distance that only decreases, so the tile may publish its
@@ -702,49 +736,58 @@ __device__ void cut_tile(const StepParams &P, const InstDesc &D, InstState *S, i
     int32_t *sh_w = lds;
     const bool raise = first && kk + 1 < D.L;
     const int dlam = raise ? gp(D.lambdas)[kk + 1] - gp(D.lambdas)[kk] : 0;
-    int m[PPT], m0[PPT], rmv[PPT];
+    // Every global load is issued before any is used (cells outside the image
+    // read a clamped in-image address and take the defaults).
+    int m[PPT], m0[PPT], rmv[PPT], ev[PPT], rtv[PPT], sdv[PPT], slv[PPT];
+    bool valid[PPT];
     long long se = 0;
 #pragma unroll
     for (int j = 0; j < PPT; ++j) {
-        const int ly = ly0 + j * RPI;
-        const int gx = x0 + lx, gy = y0 + ly;
-        rmv[j] = 0;
+        const int gx = x0 + lx, gy = y0 + ly0 + j * RPI;
+        valid[j] = gx < W && gy < H;
+        const int p = min(gy, H - 1) * W + min(gx, W - 1);
+        rmv[j] = gp(D.rmask)[p];
         m[j] = 0;
-        if (gx < W && gy < H) {
-            const int p = gy * W + gx;
-            rmv[j] = gp(D.rmask)[p];
-            if (first) {
-                m[j] = (rmv[j] & kEBit) ? 1 : 0;
-                if (m[j]) se += gp(D.e)[p];
-                if (dlam > 0) {
-                    const int sd = D.seed ? (int)gp(D.seed)[p] : 0;
-                    const int sl = sd == 0 ? (D.slope ? gp(D.slope)[p] : 1) : 0;
-                    if (sl > 0) {
-                        const int nrt = gp(D.rt)[p] + sl * dlam;
-                        gp(D.rt)[p] = nrt;
-                        if (nrt > 0 && !(rmv[j] & kRtBit)) gp(D.rmask)[p] = (uint16_t)(rmv[j] | kRtBit);
-                    }
-                }
-            } else {
-                m[j] = mask[p];
+        ev[j] = rtv[j] = sdv[j] = 0;
+        slv[j] = 1;
+        if (first) {
+            ev[j] = gp(D.e)[p];
+            if (dlam > 0) {
+                rtv[j] = gp(D.rt)[p];
+                if (D.seed) sdv[j] = gp(D.seed)[p];
+                if (D.slope) slv[j] = gp(D.slope)[p];
+            }
+        } else {
+            m[j] = mask[p];
+        }
+    }
+    int hx, hy;
+    G::ring(min(tid, G::RING - 1), hx, hy);
+    const bool hin = x0 + hx - 1 >= 0 && x0 + hx - 1 < W && y0 + hy - 1 >= 0 && y0 + hy - 1 < H;
+    const int hq = min(max(y0 + hy - 1, 0), H - 1) * W + min(max(x0 + hx - 1, 0), W - 1);
+    const int hrm = gp(D.rmask)[hq];
+    const int hmk = first ? ((hrm & kEBit) ? 1 : 0) : mask[hq];
+#pragma unroll
+    for (int j = 0; j < PPT; ++j) {
+        if (!valid[j]) {
+            rmv[j] = 0;
+            m[j] = 0;
+        } else if (first) {
+            m[j] = (rmv[j] & kEBit) ? 1 : 0;
+            if (m[j]) se += ev[j];
+            // raise the sink residuals to the next lambda (warm start)
+            const int sl = sdv[j] == 0 ? slv[j] : 0;
+            if (dlam > 0 && sl > 0) {
+                const int p = (y0 + ly0 + j * RPI) * W + x0 + lx;
+                const int nrt = rtv[j] + sl * dlam;
+                gp(D.rt)[p] = nrt;
+                if (nrt > 0 && !(rmv[j] & kRtBit)) gp(D.rmask)[p] = (uint16_t)(rmv[j] | kRtBit);
             }
         }
         m0[j] = m[j];
-        sh_w[(ly + 1) * HW + lx + 1] = rmv[j] | (m[j] ? kReached : 0);
+        sh_w[(ly0 + j * RPI + 1) * HW + lx + 1] = rmv[j] | (m[j] ? kReached : 0);
     }
-    for (int i = tid; i < G::RING; i += kThreads) {
-        int hx, hy;
-        G::ring(i, hx, hy);
-        const int gx = x0 + hx - 1, gy = y0 + hy - 1;
-        int w = 0;
-        if (gx >= 0 && gx < W && gy >= 0 && gy < H) {
-            const int q = gy * W + gx;
-            const int rq = gp(D.rmask)[q];
-            const int mq = first ? ((rq & kEBit) ? 1 : 0) : mask[q];
-            w = rq | (mq ? kReached : 0);
-        }
-        sh_w[hy * HW + hx] = w;
-    }
+    if (tid < G::RING) sh_w[hy * HW + hx] = hin ? (hrm | (hmk ? kReached : 0)) : 0;
     __syncthreads();
     // Exchange rounds as in the relabel pass: after the first pass every stored
     // reached bit is final once set, so newer bits of neighbour tiles written
@@ -1018,7 +1061,7 @@ __global__ __launch_bounds__(kThreads) void k_sweep(StepParams P, int which) {
 
 template <int K, int TW, int TH>
 __global__ __launch_bounds__(kThreads) void k_bfs(StepParams P, int which) {
-    __shared__ int32_t lds[2 * (TW + 2) * (TH + 2)];
+    __shared__ int32_t lds[3 * (TW + 2) * (TH + 2)];
     __shared__ int s_red[4];
     __shared__ unsigned long long s_sum;
     const ListWalk w(P, which);
