@@ -217,39 +217,50 @@ def main():
     status_np = status.cpu().numpy()
     assert (status_np == 0).all(), status_np
 
-    # roofline of the dominant kernel (the push/relabel sweep): one extra solve
-    # in the library's timing mode, which brackets every kernel with HIP events
-    # on the solver's stream
+    # roofline of the dominant kernel (k_step: the sweeps and the relabel / cut
+    # / init passes of one superstep): one extra solve in the library's timing
+    # mode, which brackets every launch with HIP events on the solver's stream,
+    # and one in its split mode (sweeps and passes launched apart) for shares
     tsolver = pmf.Solver(timing=1, **overrides)
     tsolver.solve(dev)
     torch.cuda.synchronize()
     ts = tsolver.stats()
     tsolver.close()
+    ssolver = pmf.Solver(timing=2, **overrides)
+    ssolver.solve(dev)
+    torch.cuda.synchronize()
+    ss = ssolver.stats()
+    ssolver.close()
     bpx = bytes_per_px(4)
-    sweep_s = ts["sweep_ns"] * 1e-9
-    n_sweep = max(ts["sweep_launches"], 1)
-    per_launch_bytes = ts["px_sweep"] * bpx["sweep"] / n_sweep
-    avg_launch_s = sweep_s / n_sweep
+    work_bytes = (ts["px_sweep"] * bpx["sweep"] + ts["px_relabel"] * bpx["relabel"] + ts["px_cut"] * bpx["cut"]
+                  + ts["px_init"] * bpx["init"])
+    n_work = max(ts["work_launches"], 1)
+    per_launch_bytes = work_bytes / n_work
+    avg_launch_s = ts["work_ns"] * 1e-9 / n_work
     achieved = per_launch_bytes / avg_launch_s / 1e9
-    bfs_bytes = ts["px_relabel"] * bpx["relabel"] + ts["px_cut"] * bpx["cut"] + ts["px_init"] * bpx["init"]
     tw = solver.options.tile_w
+    kname = "k_step<4, %d, %d>" % (tw, 1024 // tw)
     # HBM bytes per launch from the committed counter summary, while it still
     # describes the current kernel source
     from paper_1509_06004_amd import rocprof_summary
-    prof = rocprof_summary.read_summary(os.path.join(ROOT, "profiles", "k_sweep_500x375_4conn_traffic.txt"))
+    prof = rocprof_summary.read_summary(os.path.join(ROOT, "profiles", "k_step_500x375_4conn_traffic.txt"))
     traffic = None
     if (prof.get("kernel_source_sha256") == rocprof_summary.source_hash()
-            and "traffic_bytes_per_launch" in prof and "k_sweep<4,%d,%d>" % (solver.options.tile_w, 1024 // solver.options.tile_w)
-            in prof.get("traffic_kernel", "").replace(" ", "")):
+            and "traffic_bytes_per_launch" in prof
+            and kname.replace(" ", "") in prof.get("traffic_kernel", "").replace(" ", "")):
         traffic = float(prof["traffic_bytes_per_launch"])
+    split_total = max(ss["sweep_ns"] + ss["pass_ns"] + ss["control_ns"], 1)
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-            "kernel": "k_sweep<4, %d, %d>" % (tw, 1024 // tw), "avg_launch_us": round(avg_launch_s * 1e6, 2),
-            "alg_bytes_per_launch": int(per_launch_bytes), "launches": int(n_sweep),
+            "kernel": kname, "avg_launch_us": round(avg_launch_s * 1e6, 2),
+            "alg_bytes_per_launch": int(per_launch_bytes), "launches": int(n_work),
             "bytes_per_px": bpx,
-            "other_kernels": {"k_bfs_GBs": round(bfs_bytes / max(ts["bfs_ns"], 1), 1),
-                              "k_bfs_share": round(ts["bfs_ns"] / max(ts["sweep_ns"] + ts["bfs_ns"] + ts["control_ns"], 1), 3),
-                              "k_sweep_share": round(ts["sweep_ns"] / max(ts["sweep_ns"] + ts["bfs_ns"] + ts["control_ns"], 1), 3)}}
+            "split": {"sweep_GBs": round(ss["px_sweep"] * bpx["sweep"] / max(ss["sweep_ns"], 1), 1),
+                      "pass_GBs": round((ss["px_relabel"] * bpx["relabel"] + ss["px_cut"] * bpx["cut"]
+                                         + ss["px_init"] * bpx["init"]) / max(ss["pass_ns"], 1), 1),
+                      "sweep_share": round(ss["sweep_ns"] / split_total, 3),
+                      "pass_share": round(ss["pass_ns"] / split_total, 3),
+                      "control_share": round(ss["control_ns"] / split_total, 3)}}
 
     out = {"metric": METRIC, "value": round(value, 2), "unit": "solves/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(total / args.steps * 1e3, 2),

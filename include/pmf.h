@@ -66,7 +66,9 @@ typedef struct pmf_options {
     int32_t order;              /* 0: FIFO packing order, 1: LPT (largest first)     */
     int64_t mem_budget;         /* bytes the library may allocate (0 = no limit)     */
     int32_t max_slots;          /* instance slots of a serving session (0 = 4096)    */
-    int32_t timing;             /* 1: no graph; time every kernel with HIP events    */
+    int32_t timing;             /* 1: no graph; time every launch with HIP events;   */
+                                /*   2: the same, with sweeps and passes launched   */
+                                /*   separately (timed apart)                       */
     int32_t lambda_chunk;       /* pmf_solve_batch: lambdas per device instance.     */
                                 /*   1 = every lambda solved from scratch, all in   */
                                 /*   parallel; >= L = one warm-started chain; 0 =   */
@@ -130,10 +132,12 @@ typedef struct pmf_stats {
     int64_t px_sweep;         /*   init, push/relabel sweeps, global-relabel passes */
     int64_t px_relabel;       /*   and cut passes (the unit of the algorithmic      */
     int64_t px_cut;           /*   byte counts)                                     */
-    int64_t sweep_ns;         /* with opt.timing: GPU time of the sweep kernels,    */
-    int64_t bfs_ns;           /*   of the init/relabel/cut kernels and of the       */
-    int64_t control_ns;       /*   phase-machine kernel                             */
-    int64_t sweep_launches;   /* launches of the sweep kernels                      */
+    int64_t work_ns;          /* with opt.timing: GPU time of the tile-work         */
+                              /*   launches (sweeps and passes),                    */
+    int64_t sweep_ns;         /*   with opt.timing = 2 that of the sweeps and of    */
+    int64_t pass_ns;          /*   the init/relabel/cut passes apart,               */
+    int64_t control_ns;       /*   and that of the phase-machine kernel             */
+    int64_t work_launches;    /* launches of the tile-work kernels                  */
 } pmf_stats;
 
 /* Fill *opt with defaults. */
@@ -253,11 +257,12 @@ int pmf_slot_stats(pmf_handle *h, int64_t *out, int32_t max_slots, int32_t *n_sl
 /* Counters of the last solve. */
 int pmf_get_stats(pmf_handle *h, pmf_stats *out);
 
-/* Superstep trace of the last solve or session run with options.timing = 1
+/* Superstep trace of the last solve or session run with options.timing > 0
  * (empty otherwise): one row of PMF_TRACE_COLS int64 per superstep, { tiles
  * swept (4-connected instances), tiles swept (8-connected), tiles passed by
- * the relabel / cut / init kernels (4-connected), the same (8-connected),
- * sweep kernel ns, relabel / cut / init kernel ns, control kernel ns, 0 }.
+ * the relabel / cut / init passes (4-connected), the same (8-connected),
+ * sweep ns and pass ns (timing = 2, else 0), control kernel ns, tile-work
+ * ns }.
  * Copies min(rows, max_rows) rows to out (host) and returns the number of
  * rows recorded, or -PMF_EINVAL for a null handle, negative max_rows, or a
  * null out with max_rows > 0. */

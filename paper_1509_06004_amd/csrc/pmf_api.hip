@@ -43,6 +43,7 @@ bool valid_options(const pmf_options &o) {
     if (o.steps_per_sync < 1 || o.steps_per_sync > 1 << 16) return false;
     if (o.max_supersteps < 1) return false;
     if (o.order != 0 && o.order != 1) return false;
+    if (o.timing < 0 || o.timing > 2) return false;
     if (o.mem_budget < 0 || o.max_slots < 0) return false;
     return true;
 }
@@ -93,7 +94,7 @@ size_t worklist_cap(int slots, size_t pool_bytes) { return pool_bytes / 512 + (s
 // Device bytes of the control area for `slots` slots and a work list of `wl` tiles.
 size_t control_bytes(int slots, size_t wl) {
     return align_up(sizeof(InstDesc) * (size_t)slots) + align_up(sizeof(InstState) * (size_t)slots) +
-           align_up(4 * (size_t)slots) + align_up(64) + 2 * align_up(4 * wl) + align_up(4 * 8 * wl);
+           align_up(4 * (size_t)slots) + align_up(256) + 2 * align_up(4 * wl) + align_up(4 * 8 * wl);
 }
 
 // First-fit allocator over [0, cap) with coalescing of freed ranges.
@@ -258,11 +259,11 @@ int open_session(pmf_handle *h, int slots, size_t pool_bytes) {
     P.desc = (InstDesc *)take(sizeof(InstDesc) * (size_t)slots);
     P.st = (InstState *)take(sizeof(InstState) * (size_t)slots);
     P.ring = (int32_t *)take(4 * (size_t)slots);
-    P.ring_count = (int32_t *)take(64);
+    P.ring_count = (int32_t *)take(256);
     P.tile_slot = (const int32_t *)take(4 * wl);
     P.tile_local = (const int32_t *)take(4 * wl);
     P.lists = (int32_t *)take(4 * 8 * wl);
-    P.list_count = P.ring_count + 4;  // inside the 64-byte counter block
+    P.list_count = P.ring_count + 4;  // counter block: [0] ring, [4..11] lists
     P.list_cap = (int32_t)wl;
     P.ring_cap = slots;
     P.nslots = slots;
@@ -291,7 +292,7 @@ int open_session(pmf_handle *h, int slots, size_t pool_bytes) {
     h->stats.device_bytes = (int64_t)h->arena_bytes;
     // every slot starts idle; the completion counter at zero
     if (hipMemsetAsync(P.st, 0, sizeof(InstState) * (size_t)slots, h->stream) != hipSuccess ||
-        hipMemsetAsync(P.ring_count, 0, 64, h->stream) != hipSuccess)
+        hipMemsetAsync(P.ring_count, 0, 256, h->stream) != hipSuccess)
         return PMF_EDEVICE;
     h->open = true;
     return PMF_OK;
@@ -439,13 +440,19 @@ int submit(pmf_handle *h, const pmf_instance *inst, int n, int64_t *flows_out, i
 // and one trace row (list sizes of that superstep and the three times).
 void read_kernel_events(pmf_handle *h) {
     float a = 0.f, b = 0.f, c = 0.f;
-    if (hipEventElapsedTime(&a, h->kev[0], h->kev[1]) == hipSuccess) h->stats.sweep_ns += (int64_t)(a * 1e6);
-    if (hipEventElapsedTime(&b, h->kev[1], h->kev[2]) == hipSuccess) h->stats.bfs_ns += (int64_t)(b * 1e6);
-    if (hipEventElapsedTime(&c, h->kev[2], h->kev[3]) == hipSuccess) h->stats.control_ns += (int64_t)(c * 1e6);
+    if (hipEventElapsedTime(&a, h->kev[0], h->kev[1]) != hipSuccess) a = 0.f;
+    if (hipEventElapsedTime(&b, h->kev[1], h->kev[2]) != hipSuccess) b = 0.f;
+    if (hipEventElapsedTime(&c, h->kev[2], h->kev[3]) != hipSuccess) c = 0.f;
+    const bool split = h->opt.timing == 2;
+    const int64_t na = (int64_t)(a * 1e6), nb = (int64_t)(b * 1e6), nc = (int64_t)(c * 1e6);
+    const int64_t sw = split ? na : 0, ps = split ? nb : 0, work = na + nb;
+    h->stats.work_ns += work;
+    h->stats.sweep_ns += sw;
+    h->stats.pass_ns += ps;
+    h->stats.control_ns += nc;
     int32_t cnt[4] = {0, 0, 0, 0};
     if (hipMemcpy(cnt, h->P.list_count + 4, sizeof(cnt), hipMemcpyDeviceToHost) != hipSuccess) return;
-    const int64_t row[PMF_TRACE_COLS] = {cnt[0], cnt[1], cnt[2], cnt[3], (int64_t)(a * 1e6), (int64_t)(b * 1e6),
-                                         (int64_t)(c * 1e6), 0};
+    const int64_t row[PMF_TRACE_COLS] = {cnt[0], cnt[1], cnt[2], cnt[3], sw, ps, nc, work};
     h->trace.insert(h->trace.end(), row, row + PMF_TRACE_COLS);
 }
 
@@ -479,12 +486,13 @@ int run_steps(pmf_handle *h, int steps, std::vector<int> *finished) {
         if (hipEventRecord(h->ev0, s) != hipSuccess) return PMF_EDEVICE;
         if (use_graph) {
             if (hipGraphLaunch(h->graph, s) != hipSuccess) return PMF_EDEVICE;
-            h->stats.sweep_launches += (int64_t)steps * ((P.t4_count > 0) + (P.t8_count > 0));
+            h->stats.work_launches += (int64_t)steps * ((P.t4_count > 0) + (P.t8_count > 0));
         } else {
             for (int i = 0; i < steps; ++i) {
-                const int ns = launch_superstep(P, h->tw, s, timing ? (void *const *)h->kev : nullptr);
+                const int ns = launch_superstep(P, h->tw, s, timing ? (void *const *)h->kev : nullptr,
+                                                h->opt.timing == 2);
                 if (ns < 0) return PMF_EDEVICE;
-                h->stats.sweep_launches += ns;
+                h->stats.work_launches += ns;
                 if (timing && i + 1 < steps) {
                     // the per-kernel events are reused: read them before the next superstep
                     if (hipStreamSynchronize(s) != hipSuccess) return PMF_EDEVICE;

@@ -99,12 +99,15 @@ struct StepParams {
     int64_t max_steps;
 };
 
-// Enqueue one superstep (sweep, relabel/cut and control kernels) over every
-// tile (defined in pmf_kernels.hip).  With `events` (4 hipEvent_t), events
-// 0..3 are recorded before the sweeps, after them, after the relabel/cut
-// kernels and after the control kernel.  Returns the number of sweep kernels
-// launched, or -1 on a launch error.
-int launch_superstep(const StepParams &p, int tile_w, void *stream, void *const *events = nullptr);
+// Enqueue one superstep (compaction, tile work and control kernels) over
+// every tile (defined in pmf_kernels.hip).  The sweeps and the relabel / cut
+// / init passes of a connectivity share one launch.  With `events` (4
+// hipEvent_t), events 0..3 are recorded before the tile-work launches, after
+// them (with `split`: after the sweeps, the sweeps and passes then being
+// separate launches), after the passes and after the control kernel.  Returns the number of tile-work kernels launched, or -1 on
+// a launch error.
+int launch_superstep(const StepParams &p, int tile_w, void *stream, void *const *events = nullptr,
+                     bool split = false);
 
 // out[p] (+)= number of the L masks that hold pixel p (n pixels).
 int launch_levels(const uint8_t *masks, int L, int n, uint8_t *out, bool accumulate, void *stream);

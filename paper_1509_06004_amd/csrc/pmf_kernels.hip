@@ -1021,65 +1021,54 @@ __global__ __launch_bounds__(kThreads) void k_compact(StepParams P) {
     wave_append(bf && is8, lists + 3 * (size_t)P.list_cap, P.list_count + 3, en);
 }
 
-// Workgroup b of a list-driven launch takes items of its XCD's eighth of the
-// list (b & 7 picks the eighth, b >> 3 strides inside it), so that
-// consecutive items -- neighbouring tiles of one image -- share an L2.
-struct ListWalk {
-    const int2 *list;
-    int cnt, eighth, stride, base, first;
-    __device__ ListWalk(const StepParams &P, int which) {
-        cnt = P.list_count[which];
-        list = reinterpret_cast<const int2 *>(P.lists) + (size_t)which * P.list_cap;
-        eighth = (cnt + 7) >> 3;
-        stride = (int)(gridDim.x >> 3);
-        base = (int)(blockIdx.x & 7) * eighth;
-        first = (int)(blockIdx.x >> 3);
-    }
-    // item i of this workgroup, the same for every thread (scalar registers)
-    __device__ int2 next(int i) const {
-        const int2 en = list[base + i];
-        return make_int2(__builtin_amdgcn_readfirstlane(en.x), __builtin_amdgcn_readfirstlane(en.y));
-    }
-};
+// Item i of a list, the same for every thread of the workgroup (scalar registers).
+__device__ __forceinline__ int2 list_item(const StepParams &P, int which, int i) {
+    const int2 en = reinterpret_cast<const int2 *>(P.lists)[(size_t)which * P.list_cap + i];
+    return make_int2(__builtin_amdgcn_readfirstlane(en.x), __builtin_amdgcn_readfirstlane(en.y));
+}
 
+// Tile work of one superstep for one connectivity: the items of sweep list
+// `ws` and of pass list `wp` (-1: none).  An instance is either sweeping or
+// in a pass, so the two kinds of items never touch the same instance and may
+// run side by side.  Workgroup b takes items of its XCD's eighth of each list
+// (b & 7 picks the eighth: consecutive items are neighbouring tiles of one
+// image, which then share an L2), round robin over the XCD's workgroups.
 template <int K, int TW, int TH>
-__global__ __launch_bounds__(kThreads) void k_sweep(StepParams P, int which) {
-    __shared__ int32_t lds[(3 + K) * (TW + 2) * (TH + 2)];
+__global__ __launch_bounds__(kThreads) void k_step(StepParams P, int ws, int wp) {
+    __shared__ int32_t lds[(3 + K) * (TW + 2) * (TH + 2)];  // sweep layout; passes use 3 planes
     __shared__ int s_red[4];
-    const ListWalk w(P, which);
-    // a short superstep (few tiles in both sweep lists) is latency bound: its
+    __shared__ unsigned long long s_sum;
+    const int ns = ws >= 0 ? P.list_count[ws] : 0;
+    const int np = wp >= 0 ? P.list_count[wp] : 0;
+    const int x = (int)(blockIdx.x & 7), stride = (int)(gridDim.x >> 3), first = (int)(blockIdx.x >> 3);
+    const int es = (ns + 7) >> 3, ep = (np + 7) >> 3;
+    const int s_lo = x * es, s_n = max(0, min(ns, s_lo + es) - s_lo);
+    const int p_lo = x * ep, p_n = max(0, min(np, p_lo + ep) - p_lo);
+    // a short superstep (few tiles in a kind of list) is latency bound: its
     // visits may run longer at no cost in width
     const int iters =
         P.list_count[0] + P.list_count[1] < P.tail_tiles ? P.tail_inner_iters : P.inner_iters;
-    for (int i = w.first; i < w.eighth && w.base + i < w.cnt; i += w.stride) {
-        const int2 en = w.next(i);
-        __syncthreads();  // the previous tile's LDS is no longer in use
-        const InstDesc D = load_desc(P.desc, en.x);
-        sweep_tile<K, TW, TH>(P, D, &P.st[en.x], en.y, iters, lds, s_red);
-    }
-}
-
-template <int K, int TW, int TH>
-__global__ __launch_bounds__(kThreads) void k_bfs(StepParams P, int which) {
-    __shared__ int32_t lds[3 * (TW + 2) * (TH + 2)];
-    __shared__ int s_red[4];
-    __shared__ unsigned long long s_sum;
-    const ListWalk w(P, which);
     const int xrounds =
         P.list_count[2] + P.list_count[3] < P.tail_tiles ? P.tail_exchange_rounds : P.exchange_rounds;
-    for (int i = w.first; i < w.eighth && w.base + i < w.cnt; i += w.stride) {
-        const int2 en = w.next(i);
-        __syncthreads();
-        InstState *S = &P.st[en.x];
-        const int phase = S->phase, sub = S->sub, kk = S->k;
-        const InstDesc D = load_desc(P.desc, en.x);
-        const int tl = en.y;
-        if (phase == kInit)
-            init_tile<K, TW, TH>(P, D, S, tl, s_red, &s_sum);
-        else if (phase == kRelabel)
-            relabel_tile<K, TW, TH>(P, D, S, tl, sub, xrounds, lds, s_red);
-        else
-            cut_tile<K, TW, TH>(P, D, S, tl, sub, kk, xrounds, lds, s_red, &s_sum);
+    for (int i = first; i < s_n + p_n; i += stride) {
+        __syncthreads();  // the previous item's LDS is no longer in use
+        if (i < s_n) {
+            const int2 en = list_item(P, ws, s_lo + i);
+            const InstDesc D = load_desc(P.desc, en.x);
+            sweep_tile<K, TW, TH>(P, D, &P.st[en.x], en.y, iters, lds, s_red);
+        } else {
+            const int2 en = list_item(P, wp, p_lo + i - s_n);
+            InstState *S = &P.st[en.x];
+            const int phase = S->phase, sub = S->sub, kk = S->k;
+            const InstDesc D = load_desc(P.desc, en.x);
+            const int tl = en.y;
+            if (phase == kInit)
+                init_tile<K, TW, TH>(P, D, S, tl, s_red, &s_sum);
+            else if (phase == kRelabel)
+                relabel_tile<K, TW, TH>(P, D, S, tl, sub, xrounds, lds, s_red);
+            else
+                cut_tile<K, TW, TH>(P, D, S, tl, sub, kk, xrounds, lds, s_red, &s_sum);
+        }
     }
 }
 
@@ -1141,32 +1130,35 @@ int launch_finalize(const int32_t *sub_status, const int64_t *meta, int n_user, 
 static int list_grid(int tiles) { return 8 * ((std::min(tiles, 2048) + 7) / 8); }
 
 template <int TW, int TH>
-static int launch_tw(const StepParams &p, hipStream_t s, void *const *ev) {
+static int launch_tw(const StepParams &p, hipStream_t s, void *const *ev, bool split) {
     const dim3 block(kThreads);
-    int sweeps = 0;
+    int n = 0;
     if (p.ntiles == 0) return 0;
     hipLaunchKernelGGL(k_compact, dim3((p.ntiles + kThreads - 1) / kThreads), block, 0, s, p);
     if (ev) (void)hipEventRecord((hipEvent_t)ev[0], s);
-    if (p.t4_count) {
-        hipLaunchKernelGGL((k_sweep<4, TW, TH>), dim3(list_grid(p.t4_count)), block, 0, s, p, 0);
-        ++sweeps;
+    if (split) {
+        // sweeps and passes as separate launches (timed apart)
+        if (p.t4_count) hipLaunchKernelGGL((k_step<4, TW, TH>), dim3(list_grid(p.t4_count)), block, 0, s, p, 0, -1);
+        if (p.t8_count) hipLaunchKernelGGL((k_step<8, TW, TH>), dim3(list_grid(p.t8_count)), block, 0, s, p, 1, -1);
+        if (ev) (void)hipEventRecord((hipEvent_t)ev[1], s);
+        if (p.t4_count) hipLaunchKernelGGL((k_step<4, TW, TH>), dim3(list_grid(p.t4_count)), block, 0, s, p, -1, 2);
+        if (p.t8_count) hipLaunchKernelGGL((k_step<8, TW, TH>), dim3(list_grid(p.t8_count)), block, 0, s, p, -1, 3);
+        n = 2 * ((p.t4_count > 0) + (p.t8_count > 0));
+    } else {
+        if (p.t4_count) hipLaunchKernelGGL((k_step<4, TW, TH>), dim3(list_grid(p.t4_count)), block, 0, s, p, 0, 2);
+        if (p.t8_count) hipLaunchKernelGGL((k_step<8, TW, TH>), dim3(list_grid(p.t8_count)), block, 0, s, p, 1, 3);
+        n = (p.t4_count > 0) + (p.t8_count > 0);
+        if (ev) (void)hipEventRecord((hipEvent_t)ev[1], s);
     }
-    if (p.t8_count) {
-        hipLaunchKernelGGL((k_sweep<8, TW, TH>), dim3(list_grid(p.t8_count)), block, 0, s, p, 1);
-        ++sweeps;
-    }
-    if (ev) (void)hipEventRecord((hipEvent_t)ev[1], s);
-    if (p.t4_count) hipLaunchKernelGGL((k_bfs<4, TW, TH>), dim3(list_grid(p.t4_count)), block, 0, s, p, 2);
-    if (p.t8_count) hipLaunchKernelGGL((k_bfs<8, TW, TH>), dim3(list_grid(p.t8_count)), block, 0, s, p, 3);
     if (ev) (void)hipEventRecord((hipEvent_t)ev[2], s);
     hipLaunchKernelGGL(k_control, dim3(1), block, 0, s, p);
     if (ev) (void)hipEventRecord((hipEvent_t)ev[3], s);
-    return sweeps;
+    return n;
 }
 
-int launch_superstep(const StepParams &p, int tile_w, void *stream, void *const *events) {
+int launch_superstep(const StepParams &p, int tile_w, void *stream, void *const *events, bool split) {
     hipStream_t s = (hipStream_t)stream;
-    const int n = tile_w == 64 ? launch_tw<64, 16>(p, s, events) : launch_tw<32, 32>(p, s, events);
+    const int n = tile_w == 64 ? launch_tw<64, 16>(p, s, events, split) : launch_tw<32, 32>(p, s, events, split);
     return hipGetLastError() == hipSuccess ? n : -1;
 }
 

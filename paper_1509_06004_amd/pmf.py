@@ -94,10 +94,11 @@ class Stats(ctypes.Structure):
         ("px_sweep", ctypes.c_int64),
         ("px_relabel", ctypes.c_int64),
         ("px_cut", ctypes.c_int64),
+        ("work_ns", ctypes.c_int64),
         ("sweep_ns", ctypes.c_int64),
-        ("bfs_ns", ctypes.c_int64),
+        ("pass_ns", ctypes.c_int64),
         ("control_ns", ctypes.c_int64),
-        ("sweep_launches", ctypes.c_int64),
+        ("work_launches", ctypes.c_int64),
     ]
 
 
@@ -219,7 +220,7 @@ def pmf_slot_stats(handle, max_slots: int = 1 << 16) -> np.ndarray:
 
 PMF_TRACE_COLS = 8
 TRACE_FIELDS = ("sweep_tiles4", "sweep_tiles8", "pass_tiles4", "pass_tiles8", "sweep_ns", "pass_ns",
-                "control_ns", "reserved")
+                "control_ns", "work_ns")
 
 
 def pmf_get_trace(handle) -> np.ndarray:

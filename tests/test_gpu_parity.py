@@ -135,7 +135,7 @@ def test_options_do_not_change_results(pmf):
     ref = None
     for opts in [dict(), dict(tile_w=64, tile_h=16), dict(inner_iters=1, sweeps_per_relabel=1),
                  dict(inner_iters=64, sweeps_per_relabel=32, local_bfs_iters=4), dict(order=0),
-                 dict(use_graph=0, steps_per_sync=3), dict(timing=1), dict(lambda_chunk=1),
+                 dict(use_graph=0, steps_per_sync=3), dict(timing=1), dict(timing=2), dict(lambda_chunk=1),
                  dict(lambda_chunk=3), dict(lambda_chunk=100), dict(exchange_rounds=1),
                  dict(exchange_rounds=16, local_bfs_iters=2), dict(tail_tiles=0),
                  dict(tail_tiles=1 << 30, tail_inner_iters=3, tail_exchange_rounds=1),
@@ -257,22 +257,29 @@ def test_slot_stats_describe_the_split(pmf):
 
 
 def test_timing_trace_matches_stats(pmf):
-    """Timing mode records one trace row per superstep; its kernel times add up
-    to the counters, and the results equal those of the default mode."""
+    """Timing modes record one trace row per superstep; its kernel times add up
+    to the counters, and the results equal those of the default mode.  Mode 2
+    (sweeps and passes launched apart) splits the tile-work time."""
     import torch
     insts = W.config0()
     dev = pmf.to_device(insts)
     ref = pmf.Solver()
     f0, s0 = ref.solve(dev)
     assert len(pmf.pmf_get_trace(ref.handle)) == 0
-    t = pmf.Solver(timing=1)
-    f1, s1 = t.solve(dev)
-    torch.cuda.synchronize()
-    assert torch.equal(f0, f1) and torch.equal(s0, s1)
-    tr = pmf.pmf_get_trace(t.handle)
-    st = t.stats()
-    assert tr.shape == (st["supersteps"], pmf.PMF_TRACE_COLS)
-    assert tr[:, 4].sum() == st["sweep_ns"] and tr[:, 5].sum() == st["bfs_ns"]
-    assert (tr[:, :4] >= 0).all() and tr[:, 0].sum() > 0 and tr[:, 2].sum() > 0
+    for mode in (1, 2):
+        t = pmf.Solver(timing=mode)
+        f1, s1 = t.solve(dev)
+        torch.cuda.synchronize()
+        assert torch.equal(f0, f1) and torch.equal(s0, s1)
+        tr = pmf.pmf_get_trace(t.handle)
+        st = t.stats()
+        assert tr.shape == (st["supersteps"], pmf.PMF_TRACE_COLS)
+        assert tr[:, 7].sum() == st["work_ns"] > 0 and tr[:, 6].sum() == st["control_ns"]
+        assert tr[:, 4].sum() == st["sweep_ns"] and tr[:, 5].sum() == st["pass_ns"]
+        if mode == 1:
+            assert st["sweep_ns"] == 0 and st["pass_ns"] == 0
+        else:
+            assert st["sweep_ns"] > 0 and st["pass_ns"] > 0 and st["sweep_ns"] + st["pass_ns"] == st["work_ns"]
+        assert (tr[:, :4] >= 0).all() and tr[:, 0].sum() > 0 and tr[:, 2].sum() > 0
+        t.close()
     ref.close()
-    t.close()
