@@ -139,6 +139,9 @@ def main():
     ap.add_argument("--no-8conn", action="store_true")
     ap.add_argument("--no-verify", action="store_true")
     ap.add_argument("--no-roofline", action="store_true")
+    ap.add_argument("--no-split", action="store_true",
+                    help="skip the split-timing solve (profiled runs: every k_step launch is then fused as in "
+                         "the timed solves)")
     ap.add_argument("--serve-qps", type=float, default=50.0)
     ap.add_argument("--serve-seconds", type=float, default=8.0)
     ap.add_argument("--serve-warmup", type=float, default=2.0)
@@ -226,11 +229,13 @@ def main():
     torch.cuda.synchronize()
     ts = tsolver.stats()
     tsolver.close()
-    ssolver = pmf.Solver(timing=2, **overrides)
-    ssolver.solve(dev)
-    torch.cuda.synchronize()
-    ss = ssolver.stats()
-    ssolver.close()
+    ss = None
+    if not args.no_split:
+        ssolver = pmf.Solver(timing=2, **overrides)
+        ssolver.solve(dev)
+        torch.cuda.synchronize()
+        ss = ssolver.stats()
+        ssolver.close()
     bpx = bytes_per_px(4)
     work_bytes = (ts["px_sweep"] * bpx["sweep"] + ts["px_relabel"] * bpx["relabel"] + ts["px_cut"] * bpx["cut"]
                   + ts["px_init"] * bpx["init"])
@@ -249,18 +254,19 @@ def main():
             and "traffic_bytes_per_launch" in prof
             and kname.replace(" ", "") in prof.get("traffic_kernel", "").replace(" ", "")):
         traffic = float(prof["traffic_bytes_per_launch"])
-    split_total = max(ss["sweep_ns"] + ss["pass_ns"] + ss["control_ns"], 1)
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
             "kernel": kname, "avg_launch_us": round(avg_launch_s * 1e6, 2),
             "alg_bytes_per_launch": int(per_launch_bytes), "launches": int(n_work),
-            "bytes_per_px": bpx,
-            "split": {"sweep_GBs": round(ss["px_sweep"] * bpx["sweep"] / max(ss["sweep_ns"], 1), 1),
-                      "pass_GBs": round((ss["px_relabel"] * bpx["relabel"] + ss["px_cut"] * bpx["cut"]
-                                         + ss["px_init"] * bpx["init"]) / max(ss["pass_ns"], 1), 1),
-                      "sweep_share": round(ss["sweep_ns"] / split_total, 3),
-                      "pass_share": round(ss["pass_ns"] / split_total, 3),
-                      "control_share": round(ss["control_ns"] / split_total, 3)}}
+            "bytes_per_px": bpx}
+    if ss is not None:
+        split_total = max(ss["sweep_ns"] + ss["pass_ns"] + ss["control_ns"], 1)
+        roof["split"] = {"sweep_GBs": round(ss["px_sweep"] * bpx["sweep"] / max(ss["sweep_ns"], 1), 1),
+                         "pass_GBs": round((ss["px_relabel"] * bpx["relabel"] + ss["px_cut"] * bpx["cut"]
+                                            + ss["px_init"] * bpx["init"]) / max(ss["pass_ns"], 1), 1),
+                         "sweep_share": round(ss["sweep_ns"] / split_total, 3),
+                         "pass_share": round(ss["pass_ns"] / split_total, 3),
+                         "control_share": round(ss["control_ns"] / split_total, 3)}
 
     out = {"metric": METRIC, "value": round(value, 2), "unit": "solves/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(total / args.steps * 1e3, 2),
