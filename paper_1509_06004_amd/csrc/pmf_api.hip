@@ -94,7 +94,7 @@ size_t worklist_cap(int slots, size_t pool_bytes) { return pool_bytes / 512 + (s
 // Device bytes of the control area for `slots` slots and a work list of `wl` tiles.
 size_t control_bytes(int slots, size_t wl) {
     return align_up(sizeof(InstDesc) * (size_t)slots) + align_up(sizeof(InstState) * (size_t)slots) +
-           align_up(4 * (size_t)slots) + align_up(256) + 2 * align_up(4 * wl) + align_up(4 * 8 * wl);
+           align_up(4 * (size_t)slots) + align_up(256) + align_up(4 * (size_t)slots) + align_up(4 * 8 * wl);
 }
 
 // First-fit allocator over [0, cap) with coalescing of freed ranges.
@@ -260,8 +260,7 @@ int open_session(pmf_handle *h, int slots, size_t pool_bytes) {
     P.st = (InstState *)take(sizeof(InstState) * (size_t)slots);
     P.ring = (int32_t *)take(4 * (size_t)slots);
     P.ring_count = (int32_t *)take(256);
-    P.tile_slot = (const int32_t *)take(4 * wl);
-    P.tile_local = (const int32_t *)take(4 * wl);
+    P.wl_slot = (const int32_t *)take(4 * (size_t)slots);
     P.lists = (int32_t *)take(4 * 8 * wl);
     P.list_count = P.ring_count + 4;  // counter block: [0] ring, [4..11] lists
     P.list_cap = (int32_t)wl;
@@ -311,30 +310,20 @@ int rebuild_worklist(pmf_handle *h) {
         if (x.K != y.K) return x.K < y.K;
         return lpt ? x.work > y.work : false;
     });
-    std::vector<int32_t> ts, tl;
-    int32_t t4 = 0;
-    for (int i : ids) {
-        const Slot &s = h->slots[i];
-        for (int t = 0; t < s.ntiles; ++t) {
-            ts.push_back(i);
-            tl.push_back(t);
-        }
-        if (s.K == 4) t4 += s.ntiles;
-    }
-    if (ts.size() > h->wl_cap) return PMF_ENOMEM;
+    int64_t t4 = 0, t8 = 0;
+    for (int i : ids) (h->slots[i].K == 4 ? t4 : t8) += h->slots[i].ntiles;
+    if ((size_t)(t4 + t8) > h->wl_cap) return PMF_ENOMEM;
     StepParams &P = h->P;
-    P.ntiles = (int32_t)ts.size();
-    P.t4_begin = 0;
-    P.t4_count = t4;
-    P.t8_begin = t4;
-    P.t8_count = P.ntiles - t4;
-    if (!ts.empty()) {
-        if (hipMemcpyAsync((void *)P.tile_slot, ts.data(), 4 * ts.size(), hipMemcpyHostToDevice, h->stream) !=
-                hipSuccess ||
-            hipMemcpyAsync((void *)P.tile_local, tl.data(), 4 * tl.size(), hipMemcpyHostToDevice, h->stream) !=
-                hipSuccess)
+    P.ntiles = (int32_t)(t4 + t8);
+    P.t4_count = (int32_t)t4;
+    P.t8_count = (int32_t)t8;
+    P.nwl = (int32_t)ids.size();
+    if (!ids.empty()) {
+        std::vector<int32_t> wl(ids.begin(), ids.end());
+        if (hipMemcpyAsync((void *)P.wl_slot, wl.data(), 4 * wl.size(), hipMemcpyHostToDevice, h->stream) !=
+            hipSuccess)
             return PMF_EDEVICE;
-        // pageable sources: the copies must finish before the vectors go
+        // pageable source: the copy must finish before the vector goes
         if (hipStreamSynchronize(h->stream) != hipSuccess) return PMF_EDEVICE;
     }
     drop_graph(h);

@@ -76,8 +76,8 @@ struct alignas(16) InstState {
 struct StepParams {
     InstDesc *desc;             // [nslots]
     InstState *st;              // [nslots]
-    const int32_t *tile_slot;   // work list: instance slot of each tile
-    const int32_t *tile_local;  // work list: tile index inside its instance
+    const int32_t *wl_slot;     // work list: slots of the live instances, 4-connected first
+    int32_t nwl;                // entries of wl_slot
     int32_t *ring;              // completion ring: slots in order of completion
     int32_t *ring_count;        // completions so far (ring index = count % ring_cap)
     int32_t ring_cap;
@@ -85,8 +85,8 @@ struct StepParams {
     int32_t *lists;             // [4][list_cap] {slot, tile} pairs: to sweep (K=4, K=8), to pass (K=4, K=8)
     int32_t *list_count;        // [4] entries of each list in this superstep, [4..7] those of the last one
     int32_t ntiles;
-    int32_t t4_begin, t4_count; // tiles of 4-connected instances (contiguous)
-    int32_t t8_begin, t8_count; // tiles of 8-connected instances (contiguous)
+    int32_t t4_count;           // tiles of the 4-connected instances of the work list
+    int32_t t8_count;           // tiles of the 8-connected ones
     int32_t nslots;
     int32_t inner_iters;
     int32_t sweeps_per_relabel;

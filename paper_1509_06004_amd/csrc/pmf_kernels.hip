@@ -873,13 +873,17 @@ __device__ void cut_tile(const StepParams &P, const InstDesc &D, InstState *S, i
 }
 
 // ---------------------------------------------------------------------------
-// Phase machine, run by the last workgroup of every superstep.
+// Phase machine of every instance of the work list (one thread each), run
+// after the tile work of every superstep.
 // ---------------------------------------------------------------------------
 __device__ void control(const StepParams &P) {
-    for (int i = threadIdx.x; i < P.nslots; i += kThreads) {
+    const int w = (int)(blockIdx.x * kThreads + threadIdx.x);
+    if (w >= P.nwl) return;
+    {
+        const int i = P.wl_slot[w];
         InstState *S = &P.st[i];
         int ph = ld_agent(&S->phase);
-        if (ph == kIdle || ph == kDone) continue;
+        if (ph == kIdle || ph == kDone) return;
         const InstDesc *D = &P.desc[i];
         S->steps += 1;
         bool done = false;
@@ -975,50 +979,46 @@ __device__ __forceinline__ void wave_append(bool want, int2 *list, int32_t *coun
     if (want) list[base + __popcll(m & ((1ull << lane) - 1ull))] = value;
 }
 
-// Work compaction, one thread per tile of the work list: the tiles that need
-// a sweep (instance sweeping, pixels active or inflow pending) and the tiles
-// that need a relabel / cut / init pass (first pass of a phase, or a change in
-// the 3x3 tile neighbourhood during the previous pass) go to four lists
-// (sweep K=4, sweep K=8, pass K=4, pass K=8) as {instance slot, tile} pairs.
-// Skipped pass tiles record "no change" for the current pass here, as a
-// processed tile would.  The tile kernels rely on these tests: a listed tile
+// Work compaction, one workgroup per instance of the work list: the tiles
+// that need a sweep (instance sweeping, pixels active or inflow pending) and
+// the tiles that need a relabel / cut / init pass (first pass of a phase, or a
+// change in the 3x3 tile neighbourhood during the previous pass) go to four
+// lists (sweep K=4, sweep K=8, pass K=4, pass K=8) as {instance slot, tile}
+// pairs.  Skipped pass tiles record "no change" for the current pass here, as
+// a processed tile would.  The tile kernels rely on these tests: a listed tile
 // is in range, its instance in the listed phase (phases change only in the
 // control kernel), a listed sweep tile has work, a listed pass tile needs
 // the pass.
 __global__ __launch_bounds__(kThreads) void k_compact(StepParams P) {
-    const int t = blockIdx.x * kThreads + threadIdx.x;
-    bool sw = false, bf = false, is8 = false;
-    int slot = 0, tl = 0;
-    if (t < P.ntiles) {
-        slot = P.tile_slot[t];
-        tl = P.tile_local[t];
-        const InstState *S = &P.st[slot];
-        const InstDesc *D = &P.desc[slot];
-        const int phase = S->phase;
-        is8 = t >= P.t8_begin;
-        if (tl < D->ntiles) {
+    const int slot = __builtin_amdgcn_readfirstlane(P.wl_slot[blockIdx.x]);
+    const InstState *S = &P.st[slot];
+    const int phase = __builtin_amdgcn_readfirstlane(S->phase);
+    if (phase != kSweep && phase != kInit && phase != kRelabel && phase != kCut) return;
+    const int sub = __builtin_amdgcn_readfirstlane(S->sub);
+    const InstDesc D = load_desc(P.desc, slot);
+    const bool is8 = D.K == 8;
+    int2 *lists = reinterpret_cast<int2 *>(P.lists);
+    int2 *sl = lists + (is8 ? 1 : 0) * (size_t)P.list_cap;
+    int2 *pl = lists + (is8 ? 3 : 2) * (size_t)P.list_cap;
+    int32_t *sc = P.list_count + (is8 ? 1 : 0), *pc = P.list_count + (is8 ? 3 : 2);
+    for (int t0 = 0; t0 < D.ntiles; t0 += kThreads) {
+        const int tl = t0 + (int)threadIdx.x;
+        bool sw = false, bf = false;
+        if (tl < D.ntiles) {
             if (phase == kSweep) {
-                sw = (gp(D->tile_act)[tl] & 3u) != 0u;
-            } else if (phase == kInit) {
+                sw = (gp(D.tile_act)[tl] & 3u) != 0u;
+            } else if (phase == kInit || sub == 0) {
                 bf = true;
-            } else if (phase == kRelabel || phase == kCut) {
-                const int sub = S->sub;
-                if (sub == 0) {
-                    bf = true;
-                } else {
-                    const int tx = tl % D->tiles_x, ty = tl / D->tiles_x;
-                    bf = frontier_needs(*D, tx, ty, (sub & 1) ^ 1);
-                    if (!bf) gp(D->tile_chg)[(size_t)(sub & 1) * D->ntiles + tl] = 0;
-                }
+            } else {
+                const int tx = tl % D.tiles_x, ty = tl / D.tiles_x;
+                bf = frontier_needs(D, tx, ty, (sub & 1) ^ 1);
+                if (!bf) gp(D.tile_chg)[(size_t)(sub & 1) * D.ntiles + tl] = 0;
             }
         }
+        const int2 en = make_int2(slot, tl);
+        wave_append(sw, sl, sc, en);
+        wave_append(bf, pl, pc, en);
     }
-    const int2 en = make_int2(slot, tl);
-    int2 *lists = reinterpret_cast<int2 *>(P.lists);
-    wave_append(sw && !is8, lists, P.list_count + 0, en);
-    wave_append(sw && is8, lists + (size_t)P.list_cap, P.list_count + 1, en);
-    wave_append(bf && !is8, lists + 2 * (size_t)P.list_cap, P.list_count + 2, en);
-    wave_append(bf && is8, lists + 3 * (size_t)P.list_cap, P.list_count + 3, en);
 }
 
 // Item i of a list, the same for every thread of the workgroup (scalar registers).
@@ -1074,7 +1074,7 @@ __global__ __launch_bounds__(kThreads) void k_step(StepParams P, int ws, int wp)
 
 __global__ __launch_bounds__(kThreads) void k_control(StepParams P) {
     control(P);
-    if (threadIdx.x < 4) {
+    if (blockIdx.x == 0 && threadIdx.x < 4) {
         // keep this superstep's list sizes (read by the timing mode), then
         // clear them: the next superstep compacts afresh
         P.list_count[4 + threadIdx.x] = P.list_count[threadIdx.x];
@@ -1134,7 +1134,7 @@ static int launch_tw(const StepParams &p, hipStream_t s, void *const *ev, bool s
     const dim3 block(kThreads);
     int n = 0;
     if (p.ntiles == 0) return 0;
-    hipLaunchKernelGGL(k_compact, dim3((p.ntiles + kThreads - 1) / kThreads), block, 0, s, p);
+    hipLaunchKernelGGL(k_compact, dim3(p.nwl), block, 0, s, p);
     if (ev) (void)hipEventRecord((hipEvent_t)ev[0], s);
     if (split) {
         // sweeps and passes as separate launches (timed apart)
@@ -1151,7 +1151,7 @@ static int launch_tw(const StepParams &p, hipStream_t s, void *const *ev, bool s
         if (ev) (void)hipEventRecord((hipEvent_t)ev[1], s);
     }
     if (ev) (void)hipEventRecord((hipEvent_t)ev[2], s);
-    hipLaunchKernelGGL(k_control, dim3(1), block, 0, s, p);
+    hipLaunchKernelGGL(k_control, dim3((p.nwl + kThreads - 1) / kThreads), block, 0, s, p);
     if (ev) (void)hipEventRecord((hipEvent_t)ev[3], s);
     return n;
 }
