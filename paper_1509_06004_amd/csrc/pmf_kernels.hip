@@ -879,91 +879,93 @@ __device__ void cut_tile(const StepParams &P, const InstDesc &D, InstState *S, i
 __device__ void control(const StepParams &P) {
     const int w = (int)(blockIdx.x * kThreads + threadIdx.x);
     if (w >= P.nwl) return;
-    {
-        const int i = P.wl_slot[w];
-        InstState *S = &P.st[i];
-        int ph = ld_agent(&S->phase);
-        if (ph == kIdle || ph == kDone) return;
-        const InstDesc *D = &P.desc[i];
-        S->steps += 1;
-        bool done = false;
-        int status = PMF_OK;
-        const int changed = ld_agent(&S->changed);
-        switch (ph) {
-            case kInit: {
-                const int err = ld_agent(&S->err);
-                if (err) {
+    const int i = P.wl_slot[w];
+    // The state and the descriptor fields used here are read in one batch:
+    // this kernel runs alone after the tile kernels of the superstep, whose
+    // writes it sees at the launch boundary.
+    InstState S = P.st[i];
+    const InstDesc *Dp = &P.desc[i];
+    const int L = Dp->L;
+    int64_t *flows = Dp->flows;
+    int32_t *status_out = Dp->status;
+    int ph = S.phase;
+    if (ph == kIdle || ph == kDone) return;
+    S.steps += 1;
+    bool done = false;
+    int status = PMF_OK;
+    switch (ph) {
+        case kInit:
+            if (S.err) {
+                done = true;
+                status = (S.err & 1) ? PMF_EINVAL : PMF_EOVERFLOW;
+            } else {
+                ph = kRelabel;
+                S.sub = 0;
+                S.active = 0;
+            }
+            break;
+        case kRelabel:
+            S.passes += 1;
+            if (S.sub > 0 && !S.changed) {
+                S.relabels += 1;
+                ph = S.active == 0 ? kCut : kSweep;
+                S.sub = 0;
+            } else if (P.relabel_passes > 0 && S.sub + 1 >= P.relabel_passes && S.active > 0) {
+                // cut short: the pixels labelled so far hold upper bounds of
+                // their distances and there is work for the sweep; pixels
+                // still at H_INF wait for a later relabel.  Only a relabel
+                // run to its fixed point may end the solve.
+                S.relabels += 1;
+                ph = kSweep;
+                S.sub = 0;
+            } else {
+                S.sub += 1;
+            }
+            break;
+        case kSweep:
+            S.sweeps += 1;
+            if (++S.sub >= P.sweeps_per_relabel) {
+                ph = kRelabel;
+                S.sub = 0;
+                S.active = 0;
+            }
+            break;
+        case kCut:
+            S.passes += 1;
+            if (S.sub > 0 && !S.changed) {
+                const int k = S.k;
+                gp(flows)[k] = S.sum_cs - S.sum_e;
+                S.sum_e = 0;
+                S.k = k + 1;
+                if (k + 1 >= L) {
                     done = true;
-                    status = (err & 1) ? PMF_EINVAL : PMF_EOVERFLOW;
                 } else {
                     ph = kRelabel;
-                    S->sub = 0;
-                    S->active = 0;
+                    S.sub = 0;
+                    S.active = 0;
                 }
-                break;
+            } else {
+                S.sub += 1;
             }
-            case kRelabel:
-                S->passes += 1;
-                if (S->sub > 0 && !changed) {
-                    S->relabels += 1;
-                    ph = ld_agent(&S->active) == 0 ? kCut : kSweep;
-                    S->sub = 0;
-                } else if (P.relabel_passes > 0 && S->sub + 1 >= P.relabel_passes && ld_agent(&S->active) > 0) {
-                    // cut short: the pixels labelled so far hold upper bounds of
-                    // their distances and there is work for the sweep; pixels
-                    // still at H_INF wait for a later relabel.  Only a relabel
-                    // run to its fixed point may end the solve.
-                    S->relabels += 1;
-                    ph = kSweep;
-                    S->sub = 0;
-                } else {
-                    S->sub += 1;
-                }
-                break;
-            case kSweep:
-                S->sweeps += 1;
-                if (++S->sub >= P.sweeps_per_relabel) {
-                    ph = kRelabel;
-                    S->sub = 0;
-                    S->active = 0;
-                }
-                break;
-            case kCut:
-                S->passes += 1;
-                if (S->sub > 0 && !changed) {
-                    const int k = S->k;
-                    gp(D->flows)[k] = ld_agent(&S->sum_cs) - ld_agent(&S->sum_e);
-                    S->sum_e = 0;
-                    S->k = k + 1;
-                    if (k + 1 >= D->L) {
-                        done = true;
-                    } else {
-                        ph = kRelabel;
-                        S->sub = 0;
-                        S->active = 0;
-                    }
-                } else {
-                    S->sub += 1;
-                }
-                break;
-        }
-        S->changed = 0;
-        if (!done && S->steps >= P.max_steps) {
-            done = true;
-            status = PMF_ETIMEOUT;
-        }
-        if (done) {
-            if (status != PMF_OK) {
-                const int from = status == PMF_ETIMEOUT ? S->k : 0;
-                for (int k = from; k < D->L; ++k) gp(D->flows)[k] = -1;
-            }
-            if (D->status) *gp(D->status) = status;
-            ph = kDone;
-            const int at = atomicAdd(P.ring_count, 1);
-            P.ring[at % P.ring_cap] = i;
-        }
-        S->phase = ph;
+            break;
     }
+    S.changed = 0;
+    if (!done && S.steps >= P.max_steps) {
+        done = true;
+        status = PMF_ETIMEOUT;
+    }
+    if (done) {
+        if (status != PMF_OK) {
+            const int from = status == PMF_ETIMEOUT ? S.k : 0;
+            for (int k = from; k < L; ++k) gp(flows)[k] = -1;
+        }
+        if (status_out) *gp(status_out) = status;
+        ph = kDone;
+        const int at = atomicAdd(P.ring_count, 1);
+        P.ring[at % P.ring_cap] = i;
+    }
+    S.phase = ph;
+    P.st[i] = S;
 }
 
 // Append `value` to `list` for every lane whose `want` is set: one atomic per
