@@ -39,15 +39,19 @@ def bytes_per_px(K: int) -> dict:
     """Algorithmic bytes per pixel visit of each phase (the solver's own state):
     sweep: read + write r_k, e, rt, h (int32) + write the residual bit word;
     relabel pass: read bit word + read/write h; cut pass: bit word + mask r/w;
-    init: read n-links and terminal inputs, write the whole state."""
-    return {"sweep": 2 * (K + 3) * 4 + 2, "relabel": 2 + 4 + 4, "cut": 2 + 1 + 1,
-            "init": K * 4 + 13 + K * 4 + K * 4 + 12 + 2}
+    init: read n-links and terminal inputs, write the whole state (exchanged:
+    also the reverse n-links); orientation count: terminal inputs; exchanged
+    cut: h, bit word, e, rt read, mask written."""
+    init = K * 4 + 13 + K * 4 + K * 4 + 12 + 2
+    return {"sweep": 2 * (K + 3) * 4 + 2, "relabel": 2 + 4 + 4, "cut": 2 + 1 + 1, "init": init,
+            "orient": 13, "init_x": init + K * 4, "cut_x": 4 + 2 + 4 + 4 + 1}
 
 
 def alg_bytes(st: dict, K: int) -> float:
     b = bytes_per_px(K)
     return (st["px_sweep"] * b["sweep"] + st["px_relabel"] * b["relabel"] + st["px_cut"] * b["cut"]
-            + st["px_init"] * b["init"])
+            + st["px_init"] * b["init"] + st["px_orient"] * b["orient"] + st["px_init_x"] * b["init_x"]
+            + st["px_cut_x"] * b["cut_x"])
 
 
 def add_stats(acc: dict, st: dict):
@@ -131,6 +135,8 @@ def main():
     ap.add_argument("--tail-inner-iters", type=int, default=0)
     ap.add_argument("--tail-exchange-rounds", type=int, default=0)
     ap.add_argument("--relabel-passes", type=int, default=-1, help="0 runs every relabel to its fixed point")
+    ap.add_argument("--orientation", type=int, default=-1,
+                    help="s-t swap rule: 0 as given, 1 paper's rule, 2 inverse rule, 3 always")
     ap.add_argument("--tune", action="store_true",
                     help="autotune the speed knobs on this workload before timing (results must not change)")
     ap.add_argument("--cpu-sample", type=int, default=48)
@@ -177,6 +183,8 @@ def main():
         overrides["tail_tiles"] = args.tail_tiles
     if args.relabel_passes >= 0:
         overrides["relabel_passes"] = args.relabel_passes
+    if args.orientation >= 0:
+        overrides["orientation"] = args.orientation
 
     def log(*a):
         print("[bench]", *a, file=sys.stderr, flush=True)
@@ -237,8 +245,7 @@ def main():
         ss = ssolver.stats()
         ssolver.close()
     bpx = bytes_per_px(4)
-    work_bytes = (ts["px_sweep"] * bpx["sweep"] + ts["px_relabel"] * bpx["relabel"] + ts["px_cut"] * bpx["cut"]
-                  + ts["px_init"] * bpx["init"])
+    work_bytes = alg_bytes(ts, 4)
     n_work = max(ts["work_launches"], 1)
     per_launch_bytes = work_bytes / n_work
     avg_launch_s = ts["work_ns"] * 1e-9 / n_work
@@ -262,8 +269,8 @@ def main():
     if ss is not None:
         split_total = max(ss["sweep_ns"] + ss["pass_ns"] + ss["control_ns"], 1)
         roof["split"] = {"sweep_GBs": round(ss["px_sweep"] * bpx["sweep"] / max(ss["sweep_ns"], 1), 1),
-                         "pass_GBs": round((ss["px_relabel"] * bpx["relabel"] + ss["px_cut"] * bpx["cut"]
-                                            + ss["px_init"] * bpx["init"]) / max(ss["pass_ns"], 1), 1),
+                         "pass_GBs": round((alg_bytes(ss, 4) - ss["px_sweep"] * bpx["sweep"])
+                                           / max(ss["pass_ns"], 1), 1),
                          "sweep_share": round(ss["sweep_ns"] / split_total, 3),
                          "pass_share": round(ss["pass_ns"] / split_total, 3),
                          "control_share": round(ss["control_ns"] / split_total, 3)}
@@ -278,7 +285,8 @@ def main():
                       "options": {k: getattr(solver.options, k) for k in
                                   ("tile_w", "tile_h", "inner_iters", "sweeps_per_relabel",
                                    "local_bfs_iters", "exchange_rounds", "tail_tiles", "tail_inner_iters",
-                                   "tail_exchange_rounds", "relabel_passes", "steps_per_sync", "use_graph", "order",
+                                   "tail_exchange_rounds", "relabel_passes", "orientation", "steps_per_sync",
+                                   "use_graph", "order",
                                    "lambda_chunk")}},
            "latency_ms": {"p50": round(float(np.percentile(times, 50)) * 1e3, 2),
                           "p99": round(float(np.percentile(times, 99)) * 1e3, 2),

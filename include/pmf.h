@@ -84,6 +84,13 @@ typedef struct pmf_options {
                                 /*   after this many passes hands over to the sweep */
                                 /*   before its fixed point (0 = never); a relabel  */
                                 /*   that certifies termination always converges    */
+    int32_t orientation;        /* s-t swap (paper Sec. 3.2): solve each instance   */
+                                /*   as given (0), with source and sink exchanged   */
+                                /*   and arcs reversed when more pixels have cs < ct */
+                                /*   than cs > ct at lambda_0 (1, the paper's rule), */
+                                /*   when more have cs > ct (2), or always (3).     */
+                                /*   Results are the same in every case.            */
+    int32_t reserved2;
 } pmf_options;
 
 /* One (image, seed) problem and its lambda schedule.  All pointers are device
@@ -138,6 +145,9 @@ typedef struct pmf_stats {
     int64_t pass_ns;          /*   the init/relabel/cut passes apart,               */
     int64_t control_ns;       /*   and that of the phase-machine kernel             */
     int64_t work_launches;    /* launches of the tile-work kernels                  */
+    int64_t px_orient;        /* pixel visits of the orientation count, of the init */
+    int64_t px_init_x;        /*   and of the cut passes of exchanged instances     */
+    int64_t px_cut_x;         /*   (not in px_init / px_cut)                        */
 } pmf_stats;
 
 /* Fill *opt with defaults. */

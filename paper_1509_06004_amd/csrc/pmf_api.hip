@@ -37,6 +37,7 @@ bool valid_options(const pmf_options &o) {
     if (o.local_bfs_iters < 1 || o.local_bfs_iters > 1 << 20) return false;
     if (o.exchange_rounds < 1 || o.exchange_rounds > 64) return false;
     if (o.tail_tiles < 0 || o.relabel_passes < 0) return false;
+    if (o.orientation < kOrientAsGiven || o.orientation > kOrientExchange) return false;
     if (o.tail_tiles > 0 && (o.tail_inner_iters < 1 || o.tail_inner_iters > 4096 ||
                              o.tail_exchange_rounds < 1 || o.tail_exchange_rounds > 64))
         return false;
@@ -274,6 +275,7 @@ int open_session(pmf_handle *h, int slots, size_t pool_bytes) {
     P.tail_inner_iters = h->opt.tail_inner_iters;
     P.tail_exchange_rounds = h->opt.tail_exchange_rounds;
     P.relabel_passes = h->opt.relabel_passes;
+    P.orientation = h->opt.orientation;
     P.max_steps = h->opt.max_supersteps;
     h->pool_base = off;
     // the work list is sized for pool_bytes, so the pool must not exceed it
@@ -397,7 +399,9 @@ int submit(pmf_handle *h, const pmf_instance *inst, int n, int64_t *flows_out, i
         D.status = status_out ? status_out + i : nullptr;
         lam_base += I.L;
         std::memset(&st[i], 0, sizeof(InstState));
-        st[i].phase = kInit;
+        const int pol = h->opt.orientation;
+        st[i].phase = (pol == kOrientMoreSink || pol == kOrientMoreSource) ? kOrient : kInit;
+        st[i].swap = pol == kOrientExchange ? 1 : 0;
         Slot &s = h->slots[id];
         s = Slot();
         s.live = true;
@@ -545,6 +549,9 @@ int run_steps(pmf_handle *h, int steps, std::vector<int> *finished) {
         h->stats.px_sweep += x.px_sweep;
         h->stats.px_relabel += x.px_relabel;
         h->stats.px_cut += x.px_cut;
+        h->stats.px_orient += x.px_orient;
+        h->stats.px_init_x += x.px_init_x;
+        h->stats.px_cut_x += x.px_cut_x;
         h->stats.sweep_visits += x.sweeps;
         h->stats.global_relabels += x.relabels;
         h->stats.bfs_passes += x.passes;
@@ -571,6 +578,7 @@ void pmf_default_options(pmf_options *o) {
     o->tail_tiles = 2048;
     o->tail_inner_iters = 32;
     o->tail_exchange_rounds = 16;
+    o->orientation = kOrientMoreSource;
     o->steps_per_sync = 32;
     o->max_supersteps = 2000000;
     o->use_graph = 1;

@@ -29,6 +29,18 @@ enum Phase : int32_t {
     kSweep = 3,  // tile-local push/relabel sweeps
     kCut = 4,    // forward residual reachability from excess pixels (passes until stable)
     kDone = 5,
+    kOrient = 6, // count pixels with cs > ct and cs < ct at lambda_0 (one pass, before kInit)
+};
+
+// Orientation policies (pmf_options.orientation): solve the graph as given, or
+// with source and sink exchanged and every arc reversed (same flow value, and
+// the minimal source set of the original is read off the reversed graph's
+// converged labels).
+enum Orientation : int32_t {
+    kOrientAsGiven = 0,
+    kOrientMoreSink = 1,    // exchange when more pixels have cs < ct than cs > ct
+    kOrientMoreSource = 2,  // exchange when more pixels have cs > ct than cs < ct
+    kOrientExchange = 3,    // always exchange
 };
 
 struct alignas(16) InstDesc {
@@ -71,6 +83,12 @@ struct alignas(16) InstState {
     int64_t steps;    // supersteps spent (budget)
     int64_t passes;   // relaxation passes (statistics)
     int64_t px_init, px_sweep, px_relabel, px_cut;  // pixel visits per phase
+    int32_t swap;     // 1: solved with source and sink exchanged (decided once per instance)
+    int32_t cnt_pos;  // kOrient: pixels with cs > ct at lambda_0
+    int32_t cnt_neg;  // kOrient: pixels with cs < ct at lambda_0
+    int32_t pad;
+    int64_t sum_raise;  // exchanged instances: source capacity added for the next lambda
+    int64_t px_orient, px_init_x, px_cut_x;  // pixel visits: orientation count, exchanged init and cut
 };
 
 struct StepParams {
@@ -96,6 +114,7 @@ struct StepParams {
     int32_t tail_inner_iters;
     int32_t tail_exchange_rounds;
     int32_t relabel_passes;     // cap on the passes of a relabel that leaves active pixels (0 = none)
+    int32_t orientation;        // Orientation policy
     int64_t max_steps;
 };
 

@@ -165,8 +165,74 @@ __device__ __forceinline__ long long block_sum_i64(long long v, unsigned long lo
 }
 
 // ---------------------------------------------------------------------------
+// Terminal capacities of in-image pixel p (row-major index into the caller's
+// arrays) at lambda: seeds are frozen (fg: cs = INF, ct = 0; bg: cs = 0,
+// ct = INF), a free pixel has cs = cap_src and ct = cap_snk0 + slope * lambda.
+// Values are clamped to [0, INF]; err collects invalid values (bit 0) and
+// sink capacities that would exceed INF at the last lambda (bit 1).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void terminal_caps(const InstDesc &D, int p, long long lam, long long lamL,
+                                              long long &cs, long long &ct, int &err) {
+    const int sd = D.seed ? (int)gp(D.seed)[p] : 0;
+    if (sd == 1) {
+        cs = kInf;
+        ct = 0;
+    } else if (sd == 2) {
+        cs = 0;
+        ct = kInf;
+    } else {
+        const long long c0 = gp(D.cap_snk0)[p];
+        const long long sl = D.slope ? gp(D.slope)[p] : 1;
+        cs = gp(D.cap_src)[p];
+        if (sd != 0) err |= 1;
+        if (cs < 0 || cs > kInf || c0 < 0 || sl < 0) err |= 1;
+        if (c0 + sl * lamL > kInf) err |= 2;
+        ct = c0 + sl * lam;
+        cs = cs < 0 ? 0 : (cs > kInf ? kInf : cs);
+        ct = ct < 0 ? 0 : (ct > kInf ? kInf : ct);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// kOrient: count the pixels whose source capacity exceeds their sink capacity
+// at lambda_0 and those where it is the other way round (paper Sec. 3.2: the
+// s-t swap is chosen from these counts), one pass before kInit.
+// ---------------------------------------------------------------------------
+template <int K, int TW, int TH>
+__device__ void orient_tile(const StepParams &P, const InstDesc &D, InstState *S, int tl, int *s_red) {
+    using G = Geo<TW, TH>;
+    const int tid = threadIdx.x, lx = tid % TW, ly0 = tid / TW;
+    const int tx = tl % D.tiles_x, ty = tl / D.tiles_x;
+    const int x0 = tx * TW, y0 = ty * TH;
+    const int W = D.W, H = D.H;
+    const long long lam0 = gp(D.lambdas)[0];
+    int err = 0;
+    bool pos[G::PPT], neg[G::PPT];
+#pragma unroll
+    for (int j = 0; j < G::PPT; ++j) {
+        const int gx = x0 + lx, gy = y0 + ly0 + j * G::RPI;
+        pos[j] = neg[j] = false;
+        if (gx >= W || gy >= H) continue;
+        long long cs, ct;
+        terminal_caps(D, gy * W + gx, lam0, lam0, cs, ct, err);
+        pos[j] = cs > ct;
+        neg[j] = cs < ct;
+    }
+    const int np = block_count_ballot(pos, s_red);
+    const int nn = block_count_ballot(neg, s_red);
+    if (tid == 0) {
+        if (np) atomicAdd(&S->cnt_pos, np);
+        if (nn) atomicAdd(&S->cnt_neg, nn);
+        count_px(&S->px_orient, tile_pixels<TW, TH>(W, H, x0, y0));
+    }
+    (void)P;
+}
+
+// ---------------------------------------------------------------------------
 // kInit: terminal-arc normalisation at lambda_0 and validation of the inputs.
-//   cs, ct per pixel from (seed, cap_src, cap_snk0, slope, lambda_0);
+//   cs, ct per pixel from (seed, cap_src, cap_snk0, slope, lambda_0), exchanged
+//   when the instance is solved with source and sink swapped (every n-link
+//   then reversed: the residual of p -> q is the capacity of q -> p);
 //   the common part m = min(cs, ct) goes straight from s to t: e = cs - m,
 //   rt = ct - m; r_k = n-link capacity; inbox cleared.
 // ---------------------------------------------------------------------------
@@ -180,6 +246,7 @@ __device__ void init_tile(const StepParams &P, const InstDesc &D, InstState *S, 
     const int W = D.W, H = D.H, n = D.n;
     const long long lam0 = gp(D.lambdas)[0];
     const long long lamL = gp(D.lambdas)[D.L - 1];
+    const bool swap = __builtin_amdgcn_readfirstlane(S->swap) != 0;
     const int32_t nlmax = ((1 << 30) - 1) / K;
     int err = 0;
     long long scs = 0;
@@ -189,24 +256,12 @@ __device__ void init_tile(const StepParams &P, const InstDesc &D, InstState *S, 
         const int gx = x0 + lx, gy = y0 + ly;
         if (gx >= W || gy >= H) continue;
         const int p = gy * W + gx;
-        const int sd = D.seed ? (int)gp(D.seed)[p] : 0;
         long long cs, ct;
-        if (sd == 1) {
-            cs = kInf;
-            ct = 0;
-        } else if (sd == 2) {
-            cs = 0;
-            ct = kInf;
-        } else {
-            const long long c0 = gp(D.cap_snk0)[p];
-            const long long sl = D.slope ? gp(D.slope)[p] : 1;
-            cs = gp(D.cap_src)[p];
-            if (sd != 0) err |= 1;
-            if (cs < 0 || cs > kInf || c0 < 0 || sl < 0) err |= 1;
-            if (c0 + sl * lamL > kInf) err |= 2;
-            ct = c0 + sl * lam0;
-            cs = cs < 0 ? 0 : (cs > kInf ? kInf : cs);
-            ct = ct < 0 ? 0 : (ct > kInf ? kInf : ct);
+        terminal_caps(D, p, lam0, lamL, cs, ct, err);
+        if (swap) {
+            const long long t = cs;
+            cs = ct;
+            ct = t;
         }
         const long long m = cs < ct ? cs : ct;
         const int e = (int)(cs - m);
@@ -217,9 +272,10 @@ __device__ void init_tile(const StepParams &P, const InstDesc &D, InstState *S, 
         for (int k = 0; k < K; ++k) {
             const int qx = gx + DXk(k), qy = gy + DYk(k);
             const bool on = qx >= 0 && qx < W && qy >= 0 && qy < H;
-            int c = gp(D.nlink)[(size_t)k * n + p];
+            int c = gp(D.nlink)[(size_t)k * n + p];  // validated here, once per arc
             if (c < 0 || (!on && c != 0)) err |= 1;
             if (c > nlmax) err |= 2;
+            if (swap) c = on ? gp(D.nlink)[(size_t)(k ^ 1) * n + qy * W + qx] : 0;
             if (!on || c < 0) c = 0;
             if (c > nlmax) c = nlmax;
             gp(D.r)[(size_t)k * n + p] = c;
@@ -243,7 +299,7 @@ __device__ void init_tile(const StepParams &P, const InstDesc &D, InstState *S, 
     const long long tot = block_sum_i64(scs, s_sum);
     if (tid == 0) {
         if (tot) atomicAdd((unsigned long long *)&S->sum_cs, (unsigned long long)tot);
-        count_px(&S->px_init, tile_pixels<TW, TH>(W, H, x0, y0));
+        count_px(swap ? &S->px_init_x : &S->px_init, tile_pixels<TW, TH>(W, H, x0, y0));
         gp(D.tile_act)[tl] = 0;
         gp(D.tile_cnt)[tl] = 0;
         gp(D.tile_chg)[tl] = 1;
@@ -715,6 +771,77 @@ __device__ void relabel_tile(const StepParams &P, const InstDesc &D, InstState *
 }
 
 // ---------------------------------------------------------------------------
+// kCut for an instance solved with source and sink exchanged.  The minimal
+// source set of the original graph is the set of pixels that can reach the
+// exchanged sink in the residual graph of the maximum preflow (the minimal
+// sink side of the exchanged graph), i.e. those with a finite label after the
+// converged relabel: one pass, no reachability search.  The pass also sums
+// the excess (F = sum cs - sum e in either orientation) and raises the
+// exchanged source capacities to the next lambda: the increase of a free
+// pixel's source arc first cancels against its sink residual, the rest
+// becomes excess; the preflow stays valid.  The added capacity joins sum cs
+// once this lambda's flow has been taken.
+// ---------------------------------------------------------------------------
+template <int K, int TW, int TH>
+__device__ void cut_tile_swapped(const StepParams &P, const InstDesc &D, InstState *S, int tl, int kk,
+                                 unsigned long long *s_sum) {
+    using G = Geo<TW, TH>;
+    constexpr int PPT = G::PPT, RPI = G::RPI;
+    const int tid = threadIdx.x, lx = tid % TW, ly0 = tid / TW;
+    const int tx = tl % D.tiles_x, ty = tl / D.tiles_x;
+    const int x0 = tx * TW, y0 = ty * TH;
+    const int W = D.W, H = D.H, n = D.n;
+    GLOBAL uint8_t *mask = gp(D.masks) + (size_t)kk * n;
+    const int dlam = kk + 1 < D.L ? gp(D.lambdas)[kk + 1] - gp(D.lambdas)[kk] : 0;
+    int hv[PPT], rmv[PPT], ev[PPT], rtv[PPT], sdv[PPT], slv[PPT];
+    bool valid[PPT];
+#pragma unroll
+    for (int j = 0; j < PPT; ++j) {
+        const int gx = x0 + lx, gy = y0 + ly0 + j * RPI;
+        valid[j] = gx < W && gy < H;
+        const int p = min(gy, H - 1) * W + min(gx, W - 1);
+        hv[j] = gp(D.h)[p];
+        rmv[j] = gp(D.rmask)[p];
+        ev[j] = gp(D.e)[p];
+        rtv[j] = gp(D.rt)[p];
+        sdv[j] = 0;
+        slv[j] = 1;
+        if (dlam > 0) {
+            if (D.seed) sdv[j] = gp(D.seed)[p];
+            if (D.slope) slv[j] = gp(D.slope)[p];
+        }
+    }
+    long long se = 0, sraise = 0;
+#pragma unroll
+    for (int j = 0; j < PPT; ++j) {
+        if (!valid[j]) continue;
+        const int p = (y0 + ly0 + j * RPI) * W + x0 + lx;
+        mask[p] = hv[j] < kHInf ? 1 : 0;
+        if (rmv[j] & kEBit) se += ev[j];
+        const int sl = sdv[j] == 0 ? slv[j] : 0;
+        if (dlam > 0 && sl > 0) {
+            const int inc = (int)((long long)sl * dlam);  // <= INF: checked at init
+            sraise += inc;
+            const int d = inc < rtv[j] ? inc : rtv[j];
+            const int nrt = rtv[j] - d, ne = ev[j] + (inc - d);
+            gp(D.rt)[p] = nrt;
+            gp(D.e)[p] = ne;
+            const int rm = (rmv[j] & ~(kRtBit | kEBit)) | (nrt > 0 ? kRtBit : 0) | (ne > 0 ? kEBit : 0);
+            if (rm != rmv[j]) gp(D.rmask)[p] = (uint16_t)rm;
+        }
+    }
+    const long long tse = block_sum_i64(se, s_sum);
+    const long long tra = block_sum_i64(sraise, s_sum);
+    if (tid == 0) {
+        gp(D.tile_chg)[tl] = 0;  // the cut is complete after this pass
+        if (tse) atomicAdd((unsigned long long *)&S->sum_e, (unsigned long long)tse);
+        if (tra) atomicAdd((unsigned long long *)&S->sum_raise, (unsigned long long)tra);
+        count_px(&S->px_cut_x, tile_pixels<TW, TH>(W, H, x0, y0));
+    }
+    (void)P;
+}
+
+// ---------------------------------------------------------------------------
 // kCut: one pass of the forward residual reachability from excess pixels.
 // The first pass also sums the excess (for F) and raises the sink residuals
 // to the next lambda (warm start).
@@ -894,6 +1021,11 @@ __device__ void control(const StepParams &P) {
     bool done = false;
     int status = PMF_OK;
     switch (ph) {
+        case kOrient:
+            S.swap = P.orientation == kOrientMoreSink ? S.cnt_neg > S.cnt_pos : S.cnt_pos > S.cnt_neg;
+            ph = kInit;
+            S.sub = 0;
+            break;
         case kInit:
             if (S.err) {
                 done = true;
@@ -932,10 +1064,13 @@ __device__ void control(const StepParams &P) {
             break;
         case kCut:
             S.passes += 1;
-            if (S.sub > 0 && !S.changed) {
+            // an exchanged instance's cut takes one pass (it reads the labels)
+            if ((S.sub > 0 || S.swap) && !S.changed) {
                 const int k = S.k;
                 gp(flows)[k] = S.sum_cs - S.sum_e;
                 S.sum_e = 0;
+                S.sum_cs += S.sum_raise;  // the next lambda's source capacity (exchanged instances)
+                S.sum_raise = 0;
                 S.k = k + 1;
                 if (k + 1 >= L) {
                     done = true;
@@ -995,7 +1130,7 @@ __global__ __launch_bounds__(kThreads) void k_compact(StepParams P) {
     const int slot = __builtin_amdgcn_readfirstlane(P.wl_slot[blockIdx.x]);
     const InstState *S = &P.st[slot];
     const int phase = __builtin_amdgcn_readfirstlane(S->phase);
-    if (phase != kSweep && phase != kInit && phase != kRelabel && phase != kCut) return;
+    if (phase != kSweep && phase != kInit && phase != kOrient && phase != kRelabel && phase != kCut) return;
     const int sub = __builtin_amdgcn_readfirstlane(S->sub);
     const InstDesc D = load_desc(P.desc, slot);
     const bool is8 = D.K == 8;
@@ -1009,7 +1144,7 @@ __global__ __launch_bounds__(kThreads) void k_compact(StepParams P) {
         if (tl < D.ntiles) {
             if (phase == kSweep) {
                 sw = (gp(D.tile_act)[tl] & 3u) != 0u;
-            } else if (phase == kInit || sub == 0) {
+            } else if (phase == kInit || phase == kOrient || sub == 0) {
                 bf = true;
             } else {
                 const int tx = tl % D.tiles_x, ty = tl / D.tiles_x;
@@ -1061,13 +1196,17 @@ __global__ __launch_bounds__(kThreads) void k_step(StepParams P, int ws, int wp)
         } else {
             const int2 en = list_item(P, wp, p_lo + i - s_n);
             InstState *S = &P.st[en.x];
-            const int phase = S->phase, sub = S->sub, kk = S->k;
+            const int phase = S->phase, sub = S->sub, kk = S->k, swap = S->swap;
             const InstDesc D = load_desc(P.desc, en.x);
             const int tl = en.y;
             if (phase == kInit)
                 init_tile<K, TW, TH>(P, D, S, tl, s_red, &s_sum);
+            else if (phase == kOrient)
+                orient_tile<K, TW, TH>(P, D, S, tl, s_red);
             else if (phase == kRelabel)
                 relabel_tile<K, TW, TH>(P, D, S, tl, sub, xrounds, lds, s_red);
+            else if (swap)
+                cut_tile_swapped<K, TW, TH>(P, D, S, tl, kk, &s_sum);
             else
                 cut_tile<K, TW, TH>(P, D, S, tl, sub, kk, xrounds, lds, s_red, &s_sum);
         }

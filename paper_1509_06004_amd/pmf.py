@@ -52,6 +52,8 @@ class Options(ctypes.Structure):
         ("tail_inner_iters", ctypes.c_int32),
         ("tail_exchange_rounds", ctypes.c_int32),
         ("relabel_passes", ctypes.c_int32),
+        ("orientation", ctypes.c_int32),
+        ("reserved2", ctypes.c_int32),
     ]
 
 
@@ -99,6 +101,9 @@ class Stats(ctypes.Structure):
         ("pass_ns", ctypes.c_int64),
         ("control_ns", ctypes.c_int64),
         ("work_launches", ctypes.c_int64),
+        ("px_orient", ctypes.c_int64),
+        ("px_init_x", ctypes.c_int64),
+        ("px_cut_x", ctypes.c_int64),
     ]
 
 

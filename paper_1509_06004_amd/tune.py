@@ -3,8 +3,9 @@
 The knobs change speed, never results: tile shape, push/relabel iterations per
 tile visit, sweeps between global relabels, the bound on relaxation rounds per
 tile visit, halo exchange rounds per pass, the settings of short (latency
-bound) supersteps, packing order (FIFO or largest-first) and the lambda chunk
-(how the schedule of each instance is cut into concurrently solved pieces).  The
+bound) supersteps, the orientation (s-t swap) rule, packing order (FIFO or
+largest-first) and the lambda chunk (how the schedule of each instance is cut
+into concurrently solved pieces).  The
 tuner times solves of a calibration set on the device by coordinate descent
 from the defaults and keeps the fastest point.  Every point's flows and masks
 must equal those of the starting point bit for bit; a point that differs is
@@ -25,7 +26,7 @@ from typing import Dict, List, Optional, Sequence
 from . import pmf
 
 KNOBS = ("tile_w", "inner_iters", "sweeps_per_relabel", "local_bfs_iters", "exchange_rounds", "tail_tiles",
-         "tail_inner_iters", "tail_exchange_rounds", "relabel_passes", "order", "lambda_chunk")
+         "tail_inner_iters", "tail_exchange_rounds", "relabel_passes", "orientation", "order", "lambda_chunk")
 SPACE = {
     "tile_w": [32, 64],
     "inner_iters": [4, 8, 16, 32],
@@ -36,6 +37,7 @@ SPACE = {
     "tail_inner_iters": [16, 32, 64],
     "tail_exchange_rounds": [4, 16, 32],
     "relabel_passes": [0, 2, 3, 4, 6],
+    "orientation": [0, 1, 2, 3],
     "order": [0, 1],
     "lambda_chunk": [0, 1, 2, 4],
 }

@@ -96,6 +96,33 @@ def test_tiny_random_batch(pmf):
     check_against_oracle(insts, flows, status, masks)
 
 
+@pytest.mark.parametrize("orientation,chunk", [(3, 0), (3, 100), (1, 1), (2, 100)])
+def test_orientation_edge_cases(pmf, orientation, chunk):
+    """Solving with source and sink exchanged (always, or by either counting
+    rule; warm chains included) gives the oracle's flows and minimal source
+    sets on the golden fixtures and on tiny grids with seeds, INF n-links and
+    ties."""
+    from helpers import golden_instances
+    gold = golden_instances()
+    insts = [g[1] for g in gold]
+    flows, status, masks, _ = solve(pmf, insts, orientation=orientation, lambda_chunk=chunk)
+    for i, (name, inst, fl, ms) in enumerate(gold):
+        assert status[i] == 0
+        assert list(split(flows, insts)[i]) == list(fl), name
+        assert (masks[i] == ms).all(), name
+    rng = np.random.default_rng(71 + orientation)
+    tiny = []
+    for i in range(80):
+        Wd, Hd = int(rng.integers(1, 10)), int(rng.integers(1, 10))
+        cmax = int(rng.choice([1, 3, 20, 500]))
+        tiny.append(W.tiny_random(rng, Wd, Hd, 4 if i % 2 else 8, cmax=cmax, L=int(rng.integers(1, 5)),
+                                  p_seed=float(rng.uniform(0, 0.3)), lam_max=3 * cmax,
+                                  p_inf_nlink=0.1 if i % 7 == 0 else 0.0))
+    say("orientation", orientation, "chunk", chunk, "tiny", len(tiny))
+    flows, status, masks, _ = solve(pmf, tiny, orientation=orientation, lambda_chunk=chunk)
+    check_against_oracle(tiny, flows, status, masks)
+
+
 def test_config0(pmf):
     insts = W.config0()
     say("config0 64x64")
@@ -127,8 +154,8 @@ def test_config1_warm_chain(pmf):
 
 def test_options_do_not_change_results(pmf):
     """Tile shape, inner iterations, relabel period, packing order, graph replay,
-    lambda chunks, exchange rounds, tail settings: speed knobs only; results
-    are identical."""
+    lambda chunks, exchange rounds, tail settings, orientation (s-t swap):
+    speed knobs only; results are identical."""
     rng = np.random.default_rng(29)
     insts = [W.tiny_random(rng, 90, 70, 4, cmax=300, L=4, p_seed=0.02, lam_max=100),
              W.tiny_random(rng, 61, 83, 8, cmax=300, L=3, p_seed=0.02, lam_max=100)]
@@ -140,7 +167,9 @@ def test_options_do_not_change_results(pmf):
                  dict(exchange_rounds=16, local_bfs_iters=2), dict(tail_tiles=0),
                  dict(tail_tiles=1 << 30, tail_inner_iters=3, tail_exchange_rounds=1),
                  dict(tail_tiles=1 << 30, tail_inner_iters=200, tail_exchange_rounds=64),
-                 dict(relabel_passes=1), dict(relabel_passes=2, exchange_rounds=1, local_bfs_iters=3)]:
+                 dict(relabel_passes=1), dict(relabel_passes=2, exchange_rounds=1, local_bfs_iters=3),
+                 dict(orientation=1), dict(orientation=2), dict(orientation=3),
+                 dict(orientation=3, lambda_chunk=100), dict(orientation=2, lambda_chunk=2)]:
         say("options", opts)
         flows, status, masks, _ = solve(pmf, insts, **opts)
         assert (status == 0).all()
@@ -205,8 +234,9 @@ def test_invalid_capacities_report_status(pmf):
     badlam = W.tiny_random(rng, 20, 15, 4, cmax=20, L=2)
     badlam.lambdas[:] = [9, 3]  # decreasing schedule
     insts = [good, neg, offgrid, over, sink, badlam]
-    for chunk in (1, 2):  # the decreasing pair of badlam straddles two chunks when chunk = 1
-        flows, status, masks, _ = solve(pmf, insts, lambda_chunk=chunk)
+    # the decreasing pair of badlam straddles two chunks when chunk = 1
+    for chunk, orientation in ((1, 0), (2, 0), (1, 3), (2, 1)):
+        flows, status, masks, _ = solve(pmf, insts, lambda_chunk=chunk, orientation=orientation)
         fl = split(flows, insts)
         assert list(status) == [0, pmf.PMF_EINVAL, pmf.PMF_EINVAL, pmf.PMF_EOVERFLOW, pmf.PMF_EOVERFLOW,
                                 pmf.PMF_EINVAL], chunk
