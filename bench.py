@@ -145,6 +145,7 @@ def main():
     ap.add_argument("--no-8conn", action="store_true")
     ap.add_argument("--no-verify", action="store_true")
     ap.add_argument("--no-roofline", action="store_true")
+    ap.add_argument("--no-breakpoints", action="store_true")
     ap.add_argument("--no-split", action="store_true",
                     help="skip the split-timing solve (profiled runs: every k_step launch is then fused as in "
                          "the timed solves)")
@@ -334,6 +335,23 @@ def main():
                                "achieved_GBs": round(alg_bytes(st8, 8) / (st8["device_ns"] * 1e-9) / 1e9, 1)}
         del dev8
         log("8-conn %.1f solves/s" % (n_solves / t8))
+
+    if not args.no_breakpoints:
+        # the second workload on the same kernels: every lambda in 1..2000 at
+        # which the minimal source set of one seed's instance changes
+        bsolver = pmf.Solver(**overrides)
+        binst = pmf.to_device([insts[0]])[0]
+        pmf.pmf_parametric(bsolver.handle, binst, 1, 2000)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        bps, bfl, _ = pmf.pmf_parametric(bsolver.handle, binst, 1, 2000)
+        torch.cuda.synchronize()
+        tb = time.perf_counter() - t0
+        bsolver.close()
+        out["breakpoints"] = {"range": [1, 2000], "change_points": int(len(bps)), "ms": round(tb * 1e3, 2),
+                              "workload": "seed 0 of the headline workload: all integer lambdas in 1..2000 at "
+                                          "which S_min changes, F there and each pixel's exit lambda"}
+        log("breakpoints: %d in %.1f ms" % (len(bps), tb * 1e3))
 
     if not args.no_serve:
         if args.serve_full:

@@ -264,6 +264,28 @@ int pmf_check_instances(const pmf_instance *inst, int32_t n_inst, int32_t *first
  * consecutive slots in caller order.  *n_slots = slots in use. */
 int pmf_slot_stats(pmf_handle *h, int64_t *out, int32_t max_slots, int32_t *n_slots);
 
+/* All breakpoints of one instance over an integer lambda range (paper
+ * Sec. 2.1: the minimal source sets are nested as lambda grows and F is
+ * concave and piecewise linear in lambda).  Finds every integer lambda c in
+ * (lam_lo, lam_hi] with S_min(c) != S_min(c - 1), exactly: intervals whose end
+ * sets differ in size are split where the two end pieces of F meet, and all
+ * open intervals of a round are solved in one batched call on this handle.
+ * inst->lambdas and inst->L are ignored; the other fields are as for
+ * pmf_solve_batch (device pointers).  Blocking.
+ *   bp_out   host, max_bp entries: the change points in increasing order
+ *   f_out    host, max_bp + 1 entries or NULL: F(lam_lo), then F at each
+ *            change point
+ *   n_bp     the number of change points (even when larger than max_bp)
+ *   exit_out device, W*H int32 or NULL: per pixel (row-major) the first lambda
+ *            in [lam_lo, lam_hi] at which it is not in S_min (lam_lo if never
+ *            in it, lam_hi + 1 if it never leaves)
+ * Returns PMF_OK, PMF_ERANGE when more than max_bp change points exist (the
+ * first max_bp are written), an instance status (PMF_EINVAL, PMF_EOVERFLOW,
+ * PMF_ETIMEOUT) or PMF_ENOMEM / PMF_EDEVICE.  Replaces the handle's last
+ * solve. */
+int pmf_parametric(pmf_handle *h, const pmf_instance *inst, int32_t lam_lo, int32_t lam_hi, int32_t *bp_out,
+                   int64_t *f_out, int32_t max_bp, int32_t *n_bp, int32_t *exit_out);
+
 /* Counters of the last solve. */
 int pmf_get_stats(pmf_handle *h, pmf_stats *out);
 

@@ -6,6 +6,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstring>
 #include <functional>
 #include <map>
@@ -968,6 +969,171 @@ int64_t pmf_get_trace(pmf_handle *h, int64_t *out, int64_t max_rows) {
     const int64_t n = std::min(rows, max_rows);
     if (n > 0) std::copy(h->trace.begin(), h->trace.begin() + n * PMF_TRACE_COLS, out);
     return rows;
+}
+
+int pmf_parametric(pmf_handle *h, const pmf_instance *inst, int32_t lam_lo, int32_t lam_hi, int32_t *bp_out,
+                   int64_t *f_out, int32_t max_bp, int32_t *n_bp, int32_t *exit_out) {
+    if (!h || !inst || !n_bp || max_bp < 0 || (max_bp > 0 && !bp_out) || lam_lo < 0 || lam_hi < lam_lo)
+        return PMF_EINVAL;
+    *n_bp = 0;
+    pmf_instance base = *inst;
+    base.L = 1;
+    base.lambdas = nullptr;
+    const int n = base.W * base.H;
+    // every solved lambda: its flow, |S_min| and slope sum w(S_min), and its
+    // mask (kept on the device for the exit map)
+    struct Point {
+        int64_t F = 0, size = 0, w = 0;
+        const uint8_t *mask = nullptr;
+    };
+    std::map<int32_t, Point> pts;
+    std::vector<void *> owned;  // device allocations of this call
+    auto release = [&]() {
+        (void)hipStreamSynchronize(h->stream);
+        for (void *p : owned) (void)hipFree(p);
+        owned.clear();
+    };
+    auto dalloc = [&](size_t bytes) -> void * {
+        void *p = nullptr;
+        if (hipMalloc(&p, std::max<size_t>(bytes, 4)) != hipSuccess) {
+            (void)hipGetLastError();
+            return nullptr;
+        }
+        owned.push_back(p);
+        return p;
+    };
+    // solve the lambdas of `lams` (one instance each, one batched call)
+    auto solve = [&](const std::vector<int32_t> &lams) -> int {
+        const int m = (int)lams.size();
+        int32_t *dl = (int32_t *)dalloc(4 * (size_t)m);
+        int64_t *df = (int64_t *)dalloc(8 * (size_t)m);
+        int32_t *ds = (int32_t *)dalloc(4 * (size_t)m);
+        int64_t *dst = (int64_t *)dalloc(16 * (size_t)m);
+        uint8_t *dm = (uint8_t *)dalloc((size_t)m * n);
+        if (!dl || !df || !ds || !dst || !dm) return PMF_ENOMEM;
+        if (hipMemcpyAsync(dl, lams.data(), 4 * (size_t)m, hipMemcpyHostToDevice, h->stream) != hipSuccess ||
+            hipMemsetAsync(dst, 0, 16 * (size_t)m, h->stream) != hipSuccess)
+            return PMF_EDEVICE;
+        std::vector<pmf_instance> I(m, base);
+        for (int i = 0; i < m; ++i) I[i].lambdas = dl + i;
+        int rc = pmf_solve_batch(h, I.data(), m, df, ds);
+        if (rc != PMF_OK) return rc;
+        std::vector<int32_t> st(m);
+        if (hipMemcpy(st.data(), ds, 4 * (size_t)m, hipMemcpyDeviceToHost) != hipSuccess) return PMF_EDEVICE;
+        for (int i = 0; i < m; ++i)
+            if (st[i] != PMF_OK) return st[i];
+        for (int i = 0; i < m; ++i) {
+            rc = pmf_extract_cut(h, i, 0, dm + (size_t)i * n);
+            if (rc != PMF_OK) return rc;
+            if (launch_mask_stats(dm + (size_t)i * n, n, base.snk_slope, base.seed, dst + 2 * i, h->stream) != 0)
+                return PMF_EDEVICE;
+        }
+        std::vector<int64_t> f(m), sw(2 * (size_t)m);
+        if (hipMemcpyAsync(f.data(), df, 8 * (size_t)m, hipMemcpyDeviceToHost, h->stream) != hipSuccess ||
+            hipMemcpyAsync(sw.data(), dst, 16 * (size_t)m, hipMemcpyDeviceToHost, h->stream) != hipSuccess ||
+            hipStreamSynchronize(h->stream) != hipSuccess)
+            return PMF_EDEVICE;
+        for (int i = 0; i < m; ++i) {
+            Point &q = pts[lams[i]];
+            q.F = f[i];
+            q.size = sw[2 * i];
+            q.w = sw[2 * i + 1];
+            q.mask = dm + (size_t)i * n;
+        }
+        return PMF_OK;
+    };
+    std::vector<int32_t> ends = {lam_lo};
+    if (lam_hi > lam_lo) ends.push_back(lam_hi);
+    int rc = solve(ends);
+    if (rc != PMF_OK) {
+        release();
+        return rc;
+    }
+    // Intervals whose end sets differ hold a change point (nested sets are
+    // equal exactly when their sizes are).  Each is split where the two
+    // end-pieces of F, F(a) + w_a (x - a) and F(b) + w_b (x - b), meet: with
+    // a single change point in between, that point c satisfies c - 1 < x <= c,
+    // and two more solves isolate it.
+    std::vector<std::pair<int32_t, int32_t>> open;
+    if (lam_hi > lam_lo && pts[lam_lo].size != pts[lam_hi].size) open.push_back({lam_lo, lam_hi});
+    std::vector<int32_t> changes;
+    while (!open.empty()) {
+        std::vector<int32_t> mids;
+        std::vector<std::pair<int32_t, int32_t>> wait;
+        for (const auto &iv : open) {
+            const int32_t a = iv.first, b = iv.second;
+            if (b - a == 1) {
+                changes.push_back(b);
+                continue;
+            }
+            const Point &pa = pts[a], &pb = pts[b];
+            int64_t mid = a + (b - a) / 2;
+            if (pa.w > pb.w) {
+                // x = (F(b) - F(a) + w_a a - w_b b) / (w_a - w_b), rounded up
+                const long double x = ((long double)pb.F - pa.F + (long double)pa.w * a - (long double)pb.w * b) /
+                                      (long double)(pa.w - pb.w);
+                mid = (int64_t)std::ceil(x);
+            }
+            mid = std::min<int64_t>(std::max<int64_t>(mid, (int64_t)a + 1), (int64_t)b - 1);
+            if (pts.count((int32_t)mid)) mid = a + (b - a) / 2;  // already solved: plain bisection
+            mids.push_back((int32_t)mid);
+            wait.push_back(iv);
+        }
+        open.clear();
+        if (mids.empty()) break;
+        std::sort(mids.begin(), mids.end());
+        mids.erase(std::unique(mids.begin(), mids.end()), mids.end());
+        rc = solve(mids);
+        if (rc != PMF_OK) {
+            release();
+            return rc;
+        }
+        for (const auto &iv : wait) {
+            // the solved lambdas strictly inside (a, b) cut it into pieces
+            auto it = pts.upper_bound(iv.first);
+            int32_t prev = iv.first;
+            for (; it != pts.end() && it->first <= iv.second; ++it) {
+                if (pts[prev].size != it->second.size) open.push_back({prev, it->first});
+                prev = it->first;
+            }
+        }
+    }
+    std::sort(changes.begin(), changes.end());
+    changes.erase(std::unique(changes.begin(), changes.end()), changes.end());
+    *n_bp = (int32_t)changes.size();
+    for (int i = 0; i < (int)changes.size() && i < max_bp; ++i) bp_out[i] = changes[i];
+    if (f_out) {
+        f_out[0] = pts[lam_lo].F;
+        for (int i = 0; i < (int)changes.size() && i < max_bp; ++i) f_out[i + 1] = pts[changes[i]].F;
+    }
+    if (exit_out) {
+        // masks in ascending lambda order, gathered into one buffer
+        const int m = (int)pts.size();
+        uint8_t *all = (uint8_t *)dalloc((size_t)m * n);
+        int32_t *dl = (int32_t *)dalloc(4 * (size_t)m);
+        if (!all || !dl) {
+            release();
+            return PMF_ENOMEM;
+        }
+        std::vector<int32_t> lams;
+        int i = 0;
+        for (const auto &kv : pts) {
+            lams.push_back(kv.first);
+            if (hipMemcpyAsync(all + (size_t)i * n, kv.second.mask, n, hipMemcpyDeviceToDevice, h->stream) !=
+                hipSuccess) {
+                release();
+                return PMF_EDEVICE;
+            }
+            ++i;
+        }
+        if (hipMemcpyAsync(dl, lams.data(), 4 * (size_t)m, hipMemcpyHostToDevice, h->stream) != hipSuccess ||
+            launch_exit_lambda(all, dl, m, n, lam_hi + 1, exit_out, h->stream) != 0) {
+            release();
+            return PMF_EDEVICE;
+        }
+    }
+    release();
+    return (int)changes.size() > max_bp ? PMF_ERANGE : PMF_OK;
 }
 
 int pmf_destroy(pmf_handle *h) {

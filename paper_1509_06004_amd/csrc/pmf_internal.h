@@ -135,6 +135,15 @@ int launch_levels(const uint8_t *masks, int L, int n, uint8_t *out, bool accumul
 // user i owns chunks [first[i], first[i+1]) and flows [flow_off[i], +L[i]).
 // The merged status is EINVAL, else EOVERFLOW, else ETIMEOUT, else OK; an
 // invalid instance gets flows -1 throughout.
+// out[0] += |S|, out[1] += sum of the sink slopes of the free pixels in S, for
+// a row-major mask of n pixels (out zeroed by the caller).
+int launch_mask_stats(const uint8_t *mask, int n, const int32_t *slope, const uint8_t *seed, int64_t *out,
+                      void *stream);
+
+// out[p] = first lams[i] (ascending) whose mask i lacks pixel p, else `none`.
+int launch_exit_lambda(const uint8_t *masks, const int32_t *lams, int m, int n, int32_t none, int32_t *out,
+                       void *stream);
+
 int launch_finalize(const int32_t *sub_status, const int64_t *meta, int n_user, int64_t *flows,
                     int32_t *status_out, void *stream);
 

@@ -1260,6 +1260,57 @@ __global__ __launch_bounds__(kThreads) void k_finalize(const int32_t *sub_status
     if (status_out) status_out[i] = st;
 }
 
+// Size |S| and slope sum w(S) = sum of the sink slopes of the free pixels in
+// S (the derivative dF/dlambda on the piece of F where S is optimal) of a
+// row-major mask of n pixels, added into out[0], out[1].
+__global__ __launch_bounds__(kThreads) void k_mask_stats(const uint8_t *mask, int n, const int32_t *slope,
+                                                         const uint8_t *seed, unsigned long long *out) {
+    __shared__ unsigned long long s_sum;
+    const int p = blockIdx.x * kThreads + threadIdx.x;
+    long long in = 0, w = 0;
+    if (p < n && mask[p]) {
+        in = 1;
+        if (!seed || seed[p] == 0) w = slope ? slope[p] : 1;
+    }
+    const long long tin = block_sum_i64(in, &s_sum);
+    const long long tw = block_sum_i64(w, &s_sum);
+    if (threadIdx.x == 0) {
+        if (tin) atomicAdd(&out[0], (unsigned long long)tin);
+        if (tw) atomicAdd(&out[1], (unsigned long long)tw);
+    }
+}
+
+int launch_mask_stats(const uint8_t *mask, int n, const int32_t *slope, const uint8_t *seed, int64_t *out,
+                      void *stream) {
+    hipLaunchKernelGGL(k_mask_stats, dim3((n + kThreads - 1) / kThreads), dim3(kThreads), 0, (hipStream_t)stream,
+                       mask, n, slope, seed, (unsigned long long *)out);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+// out[p] = the first lambda of `lams` (ascending, m entries) whose mask does
+// not hold pixel p, or `none` if every mask holds it (masks: m row-major
+// planes of n bytes).  With nested masks this is the lambda at which p leaves
+// the minimal source set.
+__global__ __launch_bounds__(kThreads) void k_exit_lambda(const uint8_t *masks, const int32_t *lams, int m, int n,
+                                                          int32_t none, int32_t *out) {
+    const int p = blockIdx.x * kThreads + threadIdx.x;
+    if (p >= n) return;
+    int32_t ex = none;
+    for (int i = 0; i < m; ++i)
+        if (!masks[(size_t)i * n + p]) {
+            ex = lams[i];
+            break;
+        }
+    out[p] = ex;
+}
+
+int launch_exit_lambda(const uint8_t *masks, const int32_t *lams, int m, int n, int32_t none, int32_t *out,
+                       void *stream) {
+    hipLaunchKernelGGL(k_exit_lambda, dim3((n + kThreads - 1) / kThreads), dim3(kThreads), 0, (hipStream_t)stream,
+                       masks, lams, m, n, none, out);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
 int launch_finalize(const int32_t *sub_status, const int64_t *meta, int n_user, int64_t *flows,
                     int32_t *status_out, void *stream) {
     hipLaunchKernelGGL(k_finalize, dim3((n_user + kThreads - 1) / kThreads), dim3(kThreads), 0,

@@ -134,6 +134,8 @@ def load_library() -> ctypes.CDLL:
         "pmf_get_stats": (ctypes.c_int, [P, ctypes.POINTER(Stats)]),
         "pmf_slot_stats": (ctypes.c_int, [P, P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]),
         "pmf_get_trace": (ctypes.c_int64, [P, P, ctypes.c_int64]),
+        "pmf_parametric": (ctypes.c_int, [P, ctypes.POINTER(InstanceC), ctypes.c_int32, ctypes.c_int32, P, P,
+                                          ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), P]),
         "pmf_extract_levels": (ctypes.c_int, [P, ctypes.c_int32, P]),
         "pmf_session_open": (ctypes.c_int, [P, ctypes.c_int32, ctypes.c_size_t]),
         "pmf_session_submit": (ctypes.c_int, [P, ctypes.POINTER(InstanceC), ctypes.c_int32, P, P,
@@ -226,6 +228,26 @@ def pmf_slot_stats(handle, max_slots: int = 1 << 16) -> np.ndarray:
 PMF_TRACE_COLS = 8
 TRACE_FIELDS = ("sweep_tiles4", "sweep_tiles8", "pass_tiles4", "pass_tiles8", "sweep_ns", "pass_ns",
                 "control_ns", "work_ns")
+
+
+def pmf_parametric(handle, inst: "DeviceInstance", lam_lo: int, lam_hi: int, max_bp: int = 4096,
+                   exit_map: bool = True):
+    """All breakpoints of one instance over [lam_lo, lam_hi] (see the C
+    declaration).  Returns (change points int32 array, F at lam_lo and at each
+    change point int64 array, per-pixel exit lambda (int32 H x W device tensor,
+    or None))."""
+    bp = np.zeros(max(max_bp, 1), dtype=np.int32)
+    fo = np.zeros(max(max_bp, 1) + 1, dtype=np.int64)
+    nbp = ctypes.c_int32(0)
+    ex = torch.empty((inst.H, inst.W), dtype=torch.int32, device=inst.cap_src.device) if exit_map else None
+    c = inst.c_struct()
+    rc = load_library().pmf_parametric(handle, ctypes.byref(c), int(lam_lo), int(lam_hi), bp.ctypes.data,
+                                       fo.ctypes.data, int(max_bp), ctypes.byref(nbp),
+                                       int(ex.data_ptr()) if ex is not None else None)
+    if rc != PMF_OK:
+        raise PmfError(rc, "pmf_parametric")
+    n = nbp.value
+    return bp[:n].copy(), fo[:n + 1].copy(), ex
 
 
 def pmf_get_trace(handle) -> np.ndarray:

@@ -313,3 +313,34 @@ def test_timing_trace_matches_stats(pmf):
         assert (tr[:, :4] >= 0).all() and tr[:, 0].sum() > 0 and tr[:, 2].sum() > 0
         t.close()
     ref.close()
+
+
+def test_parametric_breakpoints(pmf):
+    """All breakpoints of an instance over an integer lambda range equal the
+    oracle's: the lambdas at which the minimal source set changes, F at each,
+    and every pixel's exit lambda, all derived from oracle solves at every
+    integer lambda of the range (free pixels with sink slope 0 included)."""
+    rng = np.random.default_rng(97)
+    cases = []
+    for i in range(10):
+        Wd, Hd = int(rng.integers(2, 12)), int(rng.integers(2, 12))
+        inst = W.tiny_random(rng, Wd, Hd, 4 if i % 2 else 8, cmax=40, L=1, p_seed=0.1)
+        cases.append((inst, int(rng.integers(0, 5)), int(rng.integers(20, 90))))
+    cases.append((W.config0()[0], 0, 250))
+    s = pmf.Solver()
+    for ci, (inst, lo, hi) in enumerate(cases):
+        lams = list(range(lo, hi + 1))
+        sols = O.solve_many([(inst, lam) for lam in lams])
+        fs = [int(f) for f, _ in sols]
+        ms = np.stack([np.asarray(m, dtype=bool).reshape(inst.H, inst.W) for _, m in sols])
+        exp_bp = [lams[i] for i in range(1, len(lams)) if (ms[i] != ms[i - 1]).any()]
+        out = ~ms  # first lambda whose set lacks the pixel
+        exp_exit = np.where(out.any(axis=0), np.array(lams)[out.argmax(axis=0)], hi + 1)
+        dev = pmf.to_device([inst])[0]
+        say("parametric case", ci, inst.W, inst.H, inst.K, "range", lo, hi, "breakpoints", len(exp_bp))
+        bp, f, ex = pmf.pmf_parametric(s.handle, dev, lo, hi)
+        assert list(bp) == exp_bp, ci
+        assert int(f[0]) == fs[0], ci
+        assert [int(x) for x in f[1:]] == [fs[b - lo] for b in exp_bp], ci
+        assert (ex.cpu().numpy() == exp_exit).all(), ci
+    s.close()
