@@ -368,11 +368,20 @@ def main():
     if not args.no_cpu:
         threads = min(os.cpu_count() or 1, 16)
         pairs, res, wall = cpu_baseline(insts, args.cpu_sample, threads)
+        # the same oracle on one core: every 6th solve of the sample, one after another
+        from oracle import oracle as O
+        one = [(insts[i], int(insts[i].lambdas[k])) for i, k in pairs[::6]]
+        t1 = time.perf_counter()
+        for inst_, lam_ in one:
+            O.fifo_pr(inst_, lam_)
+        wall1 = time.perf_counter() - t1
         out["cpu_baseline"] = {"value": round(len(pairs) / wall, 2), "unit": "solves/s", "cores": threads,
                                "kind": "oracle",
                                "sample": "%d of the %d (seed, lambda) solves, evenly spaced, each solved "
                                          "from scratch by FIFO push-relabel (int64), one per thread"
-                                         % (len(pairs), n_solves)}
+                                         % (len(pairs), n_solves),
+                               "value_1core": round(len(one) / wall1, 2),
+                               "sample_1core": "every 6th of those (%d solves), one core" % len(one)}
         log("cpu %.2f solves/s on %d threads" % (len(pairs) / wall, threads))
         if masks is not None:
             bad, cert = verify(insts, flows_np, masks, pairs, res)
