@@ -573,7 +573,7 @@ void pmf_default_options(pmf_options *o) {
     o->tile_w = 32;
     o->tile_h = 32;
     o->inner_iters = 16;
-    o->sweeps_per_relabel = 8;
+    o->sweeps_per_relabel = 12;
     o->local_bfs_iters = 64;
     o->exchange_rounds = 4;
     o->tail_tiles = 2048;
