@@ -42,7 +42,7 @@ def bytes_per_px(K: int) -> dict:
     init: read n-links and terminal inputs, write the whole state (exchanged:
     also the reverse n-links); orientation count: terminal inputs; exchanged
     cut: h, bit word, e, rt read, mask written."""
-    init = K * 4 + 13 + K * 4 + K * 4 + 12 + 2
+    init = K * 4 + 13 + K * 4 + 12 + 2
     return {"sweep": 2 * (K + 3) * 4 + 2, "relabel": 2 + 4 + 4, "cut": 2 + 1 + 1, "init": init,
             "orient": 13, "init_x": init + K * 4, "cut_x": 4 + 2 + 4 + 4 + 1}
 

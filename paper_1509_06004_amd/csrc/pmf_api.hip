@@ -79,7 +79,7 @@ BlockLayout block_layout(const pmf_instance &I, int tw, int th) {
     b.e = take(4 * px);
     b.rt = take(4 * px);
     b.h = take(4 * px);
-    b.inbox = take(4 * K * px);
+    b.inbox = take(4 * nt * (size_t)border_words(I.K, tw, th));
     b.rmask = take(2 * px);
     b.masks = take((size_t)I.L * px);
     b.tile_act = take(4 * nt);

@@ -5,11 +5,13 @@
 //   e      int32 [n]     excess of p (flow in minus flow out)
 //   rt     int32 [n]     residual capacity of the arc p -> t
 //   h      int32 [n]     height (distance label); H_INF = "cannot reach t"
-//   inbox  int32 [K][n]  flow pushed into p from p + d_k by another tile,
-//                        not yet folded into e and r (cross-tile pushes)
+//   inbox  int32 [ntiles][border_words]  flow pushed into a border pixel p
+//                        from p + d_k in another tile, not yet folded into e
+//                        and r: one word per (border pixel, arc leaving the
+//                        tile) pair
 //   rmask  uint16 [n]    bit k: r_k > 0, bit 8: rt > 0, bit 9: e > 0
 //   masks  uint8 [L][n]  minimal source side for every lambda
-// All planes are row-major with pitch W, 256-byte aligned.
+// All pixel planes are row-major with pitch W, 256-byte aligned.
 #pragma once
 
 #include <stdint.h>
@@ -21,6 +23,11 @@ constexpr int32_t kHInf = 1 << 30;      // height meaning "no residual path to t
 constexpr int kThreads = 256;           // workgroup size (4 wave64)
 constexpr int kRtBit = 1 << 8;
 constexpr int kEBit = 1 << 9;
+
+// Inbox words of one tw x th tile with K-connectivity: each border row holds
+// one word per pixel for every arc that leaves the tile through it (1 arc at
+// K = 4, 3 at K = 8), each border column likewise.
+constexpr int border_words(int K, int tw, int th) { return (K == 4 ? 2 : 6) * (tw + th); }
 
 enum Phase : int32_t {
     kIdle = 0,   // slot unused

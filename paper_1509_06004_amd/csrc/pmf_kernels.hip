@@ -128,6 +128,47 @@ struct Geo {
     }
 };
 
+// Inbox words of a tile: one per (border pixel, arc leaving the tile) pair,
+// holding flow that the tile across the arc pushed into the pixel.  Words
+// [0, AV*TW): the top row, arc a of the up-going arcs (3, 5, 7) at word
+// a*TW + x; then the bottom row with the down-going arcs (2, 4, 6); then the
+// left column with the left-going arcs (1, 5, 6) at a*TH + y; then the right
+// column with (0, 4, 7).  A corner pixel's diagonal arc that leaves through
+// the row is stored in the row, so its column word is never written.
+template <int K, int TW, int TH>
+struct Border {
+    static constexpr int AV = K == 4 ? 1 : 3;  // arcs leaving through one row
+    static constexpr int AH = K == 4 ? 1 : 3;  // arcs leaving through one column
+    static constexpr int E = 2 * AV * TW + 2 * AH * TH;
+    static_assert(E == border_words(K, TW, TH), "inbox size agrees with the host");
+    // word of arc k at tile pixel (bx, by); the arc must leave the tile
+    __device__ static inline int index(int bx, int by, int k) {
+        const int dx = DXk(k), dy = DYk(k);
+        const int ah = k < 2 ? 0 : (k == 4 || k == 5) ? 1 : 2;
+        if (dy < 0 && by == 0) return ((k - 3) >> 1) * TW + bx;
+        if (dy > 0 && by == TH - 1) return AV * TW + ((k - 2) >> 1) * TW + bx;
+        if (dx < 0) return 2 * AV * TW + ah * TH + by;
+        return 2 * AV * TW + AH * TH + ah * TH + by;
+    }
+    // the pair of word i (0 <= i < E)
+    __device__ static inline void pair(int i, int &bx, int &by, int &k) {
+        if (i < 2 * AV * TW) {
+            const int bot = i >= AV * TW;
+            const int j = i - bot * AV * TW, a = j / TW;
+            bx = j - a * TW;
+            by = bot ? TH - 1 : 0;
+            k = (bot ? 2 : 3) + 2 * a;
+        } else {
+            const int j0 = i - 2 * AV * TW;
+            const int rgt = j0 >= AH * TH;
+            const int j = j0 - rgt * AH * TH, a = j / TH;
+            by = j - a * TH;
+            bx = rgt ? TW - 1 : 0;
+            k = rgt ? (a == 0 ? 0 : a == 1 ? 4 : 7) : (a == 0 ? 1 : a == 1 ? 5 : 6);
+        }
+    }
+};
+
 // Pixels of tile (tx, ty) that lie inside the W x H image.
 template <int TW, int TH>
 __device__ __forceinline__ long long tile_pixels(int W, int H, int x0, int y0) {
@@ -279,7 +320,6 @@ __device__ void init_tile(const StepParams &P, const InstDesc &D, InstState *S, 
             if (!on || c < 0) c = 0;
             if (c > nlmax) c = nlmax;
             gp(D.r)[(size_t)k * n + p] = c;
-            gp(D.inbox)[(size_t)k * n + p] = 0;
             if (c > 0) rm |= 1 << k;
         }
         gp(D.e)[p] = e;
@@ -287,6 +327,8 @@ __device__ void init_tile(const StepParams &P, const InstDesc &D, InstState *S, 
         gp(D.h)[p] = rt > 0 ? 1 : kHInf;
         gp(D.rmask)[p] = (uint16_t)rm;
     }
+    for (int i = tid; i < Border<K, TW, TH>::E; i += kThreads)
+        gp(D.inbox)[(size_t)tl * Border<K, TW, TH>::E + i] = 0;
     if (tl == 0 && tid < 64) {
         // the schedule: lambda_0 >= 0, non-decreasing (also across the start
         // of a chunk of a longer schedule)
@@ -349,10 +391,9 @@ __device__ void sweep_tile(const StepParams &P, const InstDesc &D, InstState *S,
     if (tid == 0) g_and(&gp(D.tile_act)[tl], ~2u);  // about to drain the inbox
     // Every global load of the visit is issued before any is used: the halo
     // cell heights of the neighbour tiles (one ring cell per thread), the
-    // state of the thread's pixels, and the inbox words of the arcs that cross
-    // the tile border (flow pushed in by neighbour tiles), spread over all
-    // threads as (border pixel, arc) pairs.  Loads of cells outside the image
-    // read a clamped in-image address and are replaced by the defaults.
+    // state of the thread's pixels, and the tile's inbox words (flow pushed in
+    // by neighbour tiles), one or two per thread.  Loads of cells outside the
+    // image read a clamped in-image address and are replaced by the defaults.
     bool valid[PPT];
     int e[PPT], rt[PPT], h[PPT], r[PPT][K];
 #pragma unroll
@@ -372,30 +413,18 @@ __device__ void sweep_tile(const StepParams &P, const InstDesc &D, InstState *S,
     const int hc = hy * HW + hx;
     const bool hin = x0 + hx - 1 >= 0 && x0 + hx - 1 < W && y0 + hy - 1 >= 0 && y0 + hy - 1 < H;
     const int hv = gp(D.h)[min(max(y0 + hy - 1, 0), H - 1) * W + min(max(x0 + hx - 1, 0), W - 1)];
-    constexpr int NB = 2 * TW + 2 * (TH - 2);                // border pixels
-    constexpr int NBP = (NB * K + kThreads - 1) / kThreads;  // pairs per thread
-    int ibv[NBP], ibc[NBP];
-    bool ibx[NBP];
-    GLOBAL int32_t *iba[NBP];
+    using B = Border<K, TW, TH>;
+    constexpr int NBP = (B::E + kThreads - 1) / kThreads;  // inbox words per thread
+    GLOBAL int32_t *const inbox = gp(D.inbox) + (size_t)tl * B::E;
+    int ibv[NBP];
+#pragma unroll
+    for (int q = 0; q < NBP; ++q) ibv[q] = ld_agent(&inbox[min(tid + q * kThreads, B::E - 1)]);
+    // only nonzero words are taken (neighbour tiles may be adding to them)
 #pragma unroll
     for (int q = 0; q < NBP; ++q) {
-        const int i = min(tid + q * kThreads, NB * K - 1);
-        const int b = i / K, k = i - b * K;
-        const int bx = b < TW ? b : b < 2 * TW ? b - TW : b < 2 * TW + TH - 2 ? 0 : TW - 1;
-        const int by = b < TW ? 0 : b < 2 * TW ? TH - 1 : 1 + (b - 2 * TW) % (TH - 2);
-        const int nx = bx + DXk(k), ny = by + DYk(k);
-        const int gx = x0 + bx, gy = y0 + by;
-        const int qx = gx + DXk(k), qy = gy + DYk(k);
-        ibx[q] = tid + q * kThreads < NB * K && (nx < 0 || nx >= TW || ny < 0 || ny >= TH) && gx < W &&
-                 gy < H && qx >= 0 && qx < W && qy >= 0 && qy < H;
-        iba[q] = &gp(D.inbox)[(size_t)k * n + min(gy, H - 1) * W + min(gx, W - 1)];
-        ibc[q] = (((by + 1) * HW + bx + 1) << 4) | k;
-        ibv[q] = ld_agent(iba[q]);  // in-image address in every case; used only where ibx
-    }
-#pragma unroll
-    for (int q = 0; q < NBP; ++q) {
-        ibv[q] = ibx[q] ? ibv[q] : 0;
-        if (ibv[q]) ibv[q] = g_exch(iba[q], 0);
+        const int i = tid + q * kThreads;
+        ibv[q] = i < B::E ? ibv[q] : 0;
+        if (ibv[q]) ibv[q] = g_exch(&inbox[i], 0);
     }
     if (tid < G::RING) {
         sh_h[hc] = hin ? hv : kHInf;
@@ -415,7 +444,9 @@ __device__ void sweep_tile(const StepParams &P, const InstDesc &D, InstState *S,
 #pragma unroll
     for (int q = 0; q < NBP; ++q) {
         if (ibv[q]) {
-            const int c = ibc[q] >> 4, k = ibc[q] & 15;
+            int bx, by, k;
+            B::pair(tid + q * kThreads, bx, by, k);
+            const int c = (by + 1) * HW + bx + 1;
             atomicAdd(&sh_e[c], ibv[q]);
             atomicAdd(&sh_r[c * K + k], ibv[q]);
         }
@@ -538,9 +569,13 @@ __device__ void sweep_tile(const StepParams &P, const InstDesc &D, InstState *S,
             if (ix < 1 || ix > TW || iy < 1 || iy > TH) continue;
             const int v = sh_r[c * K + k];
             if (v > 0 && gx >= 0 && gx < W && gy >= 0 && gy < H) {
-                g_add(&gp(D.inbox)[(size_t)k * n + gy * W + gx], v);
+                // the receiving pixel, in the neighbour tile's coordinates
                 const int dtx = hx == 0 ? 0 : (hx == HW - 1 ? 2 : 1);
                 const int dty = hy == 0 ? 0 : (hy == HH - 1 ? 2 : 1);
+                const int bx = dtx == 0 ? TW - 1 : dtx == 2 ? 0 : hx - 1;
+                const int by = dty == 0 ? TH - 1 : dty == 2 ? 0 : hy - 1;
+                const int nt = (ty + dty - 1) * D.tiles_x + tx + dtx - 1;
+                g_add(&gp(D.inbox)[(size_t)nt * B::E + B::index(bx, by, k)], v);
                 s_nb[dty * 3 + dtx] = 1;
             }
         }
@@ -595,9 +630,7 @@ __device__ void relabel_tile(const StepParams &P, const InstDesc &D, InstState *
     // Every global load is issued before any is used (cells outside the
     // image read a clamped in-image address and take the defaults): the
     // pixels' residual masks (and labels after the first pass), one halo cell
-    // per thread, and in the first pass the inbox words of the arcs that cross
-    // the tile border with the residuals they raise, spread over all threads
-    // as (border pixel, arc) pairs.
+    // per thread, and in the first pass the tile's inbox words.
     bool valid[PPT];
     uint32_t rm[PPT];
     int d[PPT], d0[PPT];
@@ -615,28 +648,15 @@ __device__ void relabel_tile(const StepParams &P, const InstDesc &D, InstState *
     const int hq = min(max(y0 + hy - 1, 0), H - 1) * W + min(max(x0 + hx - 1, 0), W - 1);
     const int hv = first ? (int)gp(D.rmask)[hq] : gp(D.h)[hq];
     if (first) {
-        // fold flow that neighbour tiles pushed into the border pixels
-        constexpr int NB = 2 * TW + 2 * (TH - 2);
-        constexpr int NBP = (NB * K + kThreads - 1) / kThreads;
-        int ibv[NBP], ibr[NBP], ibc[NBP];
-        bool ibx[NBP];
-        size_t iba[NBP];
+        // fold flow that neighbour tiles pushed into the border pixels (no
+        // sweep of this instance runs in the same launch, so nobody else
+        // writes the inbox or these residuals meanwhile)
+        using B = Border<K, TW, TH>;
+        constexpr int NBP = (B::E + kThreads - 1) / kThreads;
+        GLOBAL int32_t *const inbox = gp(D.inbox) + (size_t)tl * B::E;
+        int ibv[NBP];
 #pragma unroll
-        for (int q = 0; q < NBP; ++q) {
-            const int i = min(tid + q * kThreads, NB * K - 1);
-            const int b = i / K, k = i - b * K;
-            const int bx = b < TW ? b : b < 2 * TW ? b - TW : b < 2 * TW + TH - 2 ? 0 : TW - 1;
-            const int by = b < TW ? 0 : b < 2 * TW ? TH - 1 : 1 + (b - 2 * TW) % (TH - 2);
-            const int nx = bx + DXk(k), ny = by + DYk(k);
-            const int gx = x0 + bx, gy = y0 + by;
-            const int qx = gx + DXk(k), qy = gy + DYk(k);
-            ibx[q] = tid + q * kThreads < NB * K && (nx < 0 || nx >= TW || ny < 0 || ny >= TH) && gx < W &&
-                     gy < H && qx >= 0 && qx < W && qy >= 0 && qy < H;
-            iba[q] = (size_t)k * n + min(gy, H - 1) * W + min(gx, W - 1);
-            ibc[q] = (((by + 1) * HW + bx + 1) << 4) | k;
-            ibv[q] = gp(D.inbox)[iba[q]];
-            ibr[q] = gp(D.r)[iba[q]];
-        }
+        for (int q = 0; q < NBP; ++q) ibv[q] = inbox[min(tid + q * kThreads, B::E - 1)];
 #pragma unroll
         for (int j = 0; j < PPT; ++j) {
             const int c = (ly0 + j * RPI + 1) * HW + lx + 1;
@@ -646,11 +666,14 @@ __device__ void relabel_tile(const StepParams &P, const InstDesc &D, InstState *
         __syncthreads();
 #pragma unroll
         for (int q = 0; q < NBP; ++q) {
-            const int v = ibx[q] ? ibv[q] : 0;
+            const int i = tid + q * kThreads;
+            const int v = i < B::E ? ibv[q] : 0;
             if (v) {
-                const int c = ibc[q] >> 4, k = ibc[q] & 15;
-                gp(D.inbox)[iba[q]] = 0;
-                gp(D.r)[iba[q]] = ibr[q] + v;
+                int bx, by, k;
+                B::pair(i, bx, by, k);
+                const int c = (by + 1) * HW + bx + 1;
+                inbox[i] = 0;
+                g_add(&gp(D.r)[(size_t)k * n + (y0 + by) * W + x0 + bx], v);
                 atomicAdd(&sh_in[c], v);
                 atomicOr(&sh_ib[c], 1 << k);
             }

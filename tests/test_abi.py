@@ -79,7 +79,10 @@ def test_query_bytes_scales_with_size(lib):
     eight = pmf.pmf_query_bytes([_fake(500, 375, 8, 20)])
     assert 0 < small < big < eight
     px = 500 * 375
-    # state: 2K+3 int32 planes + uint16 mask word + L uint8 masks per pixel
-    assert big >= px * ((2 * 4 + 3) * 4 + 2 + 20)
+    # state: K+3 int32 planes + uint16 mask word + L uint8 masks per pixel,
+    # and 128 inbox words per 32x32 tile at K = 4, 384 at K = 8
+    tiles = 16 * 12
+    assert big >= px * ((4 + 3) * 4 + 2 + 20) + tiles * 128 * 4
+    assert eight >= px * ((8 + 3) * 4 + 2 + 20) + tiles * 384 * 4
     with pytest.raises(pmf.PmfError):
         pmf.pmf_query_bytes([_fake(K=5)])
