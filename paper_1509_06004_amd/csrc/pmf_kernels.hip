@@ -725,16 +725,19 @@ __device__ void relabel_tile(const StepParams &P, const InstDesc &D, InstState *
 #pragma unroll
             for (int k = 0; k < K; ++k) v[j][k] = sh_d[c + DYk(k) * HW + DXk(k)];
         }
-        // branch-free: every label is rewritten (only its owner writes it);
-        // a neighbour at H_INF gives H_INF + 1, never below the label
+        // branch-free: every label is rewritten (only its owner writes it) as
+        // min(d, 1 + min over residual arcs of the neighbour's label), taken
+        // as 1 + min(d - 1, neighbour label or H_INF - 1 where the arc is
+        // saturated): one select per arc; a result never exceeds H_INF
 #pragma unroll
         for (int j = 0; j < PPT; ++j) {
-            int nd = d[j];
+            int mn = d[j] - 1;
 #pragma unroll
             for (int k = 0; k < K; ++k) {
-                const int cand = ((rm[j] >> k) & 1u) ? v[j][k] + 1 : kHInf;
-                nd = cand < nd ? cand : nd;
+                const int vk = ((rm[j] >> k) & 1u) ? v[j][k] : kHInf - 1;
+                mn = vk < mn ? vk : mn;
             }
+            const int nd = mn + 1;
             ch |= nd < d[j];
             d[j] = nd;
             sh_d[(ly0 + j * RPI + 1) * HW + lx + 1] = nd;
