@@ -59,7 +59,7 @@ typedef struct pmf_options {
     int32_t tile_h;             /* tile height: tile_w * tile_h = 1024 (0 = default) */
     int32_t inner_iters;        /* push/relabel iterations per tile visit            */
     int32_t sweeps_per_relabel; /* sweep supersteps between global relabels          */
-    int32_t local_bfs_iters;    /* bound on relaxation rounds per tile visit         */
+    int32_t local_bfs_iters;    /* bound on relaxation rounds between halo reads     */
     int32_t steps_per_sync;     /* supersteps per host completion check              */
     int64_t max_supersteps;     /* per-instance budget; exceeding it = PMF_ETIMEOUT  */
     int32_t use_graph;          /* 1: replay supersteps from a captured hipGraph     */

@@ -574,8 +574,8 @@ void pmf_default_options(pmf_options *o) {
     o->tile_h = 32;
     o->inner_iters = 16;
     o->sweeps_per_relabel = 12;
-    o->local_bfs_iters = 64;
-    o->exchange_rounds = 4;
+    o->local_bfs_iters = 16;
+    o->exchange_rounds = 2;
     o->tail_tiles = 2048;
     o->tail_inner_iters = 32;
     o->tail_exchange_rounds = 16;

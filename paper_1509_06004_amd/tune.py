@@ -31,7 +31,7 @@ SPACE = {
     "tile_w": [32, 64],
     "inner_iters": [4, 8, 16, 32],
     "sweeps_per_relabel": [2, 4, 8, 16],
-    "local_bfs_iters": [16, 64, 256],
+    "local_bfs_iters": [8, 16, 32, 64],
     "exchange_rounds": [1, 2, 4, 8],
     "tail_tiles": [0, 512, 2048, 8192],
     "tail_inner_iters": [16, 32, 64],
