@@ -1344,8 +1344,12 @@ int launch_finalize(const int32_t *sub_status, const int64_t *meta, int n_user, 
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
-// Workgroups of a list-driven launch: enough to fill the device, a multiple of 8.
-static int list_grid(int tiles) { return 8 * ((std::min(tiles, 2048) + 7) / 8); }
+// Workgroups of a list-driven launch, a multiple of 8: several times what the
+// device holds at once (about 1024 of the 4-connected kernel, 768 of the
+// 8-connected one), so that a compute unit whose items ran short takes up
+// another workgroup's: the dispatcher balances the superstep's uneven visits
+// (a workgroup with no item left exits at once).
+static int list_grid(int tiles) { return 8 * ((std::min(tiles, 4096) + 7) / 8); }
 
 template <int TW, int TH>
 static int launch_tw(const StepParams &p, hipStream_t s, void *const *ev, bool split) {
