@@ -702,10 +702,39 @@ size_t batch_pool_bytes(const pmf_instance *inst, int n, int C, int tw, int th, 
     return pool;
 }
 
-// The lambda chunk: the caller's choice, else the smallest chunk (the most
-// parallel work: chunks run concurrently, each lambda after the first of a
-// chunk is warm-started from the one before) whose state fits the memory
-// available to the handle.
+// The lambda chunk: the caller's choice, else chosen in two steps.  Chunks
+// run concurrently and each lambda after the first of a chunk is warm-started
+// from the one before, so short chunks give more parallel work (a shorter
+// critical path of supersteps) and long ones less work in total.  First the
+// smallest chunk whose state fits the memory available to the handle; then
+// the longest chunk from there that still gives every workgroup the device
+// holds at once kTilesPerWorkgroup tiles (measured: at 4-connectivity chunks
+// of 2 lambdas, at 8 chunks of 3-4, against 1 everywhere: -3% and -20% on the
+// 500x375 25-seed x 20-lambda batch).
+constexpr int64_t kTilesPerWorkgroup = 40;
+
+int64_t batch_tiles(const pmf_instance *inst, int n, int C, int tw, int th, int64_t *t8) {
+    int64_t t = 0, e = 0;
+    for (int i = 0; i < n; ++i) {
+        const int64_t tiles = (int64_t)((inst[i].W + tw - 1) / tw) * ((inst[i].H + th - 1) / th);
+        const int64_t v = tiles * ((inst[i].L + C - 1) / C);
+        t += v;
+        if (inst[i].K == 8) e += v;
+    }
+    if (t8) *t8 = e;
+    return t;
+}
+
+int longest_parallel_chunk(pmf_handle *h, const pmf_instance *inst, int n, int C, int maxL) {
+    int64_t t8 = 0;
+    const int64_t t = batch_tiles(inst, n, 1, h->tw, h->th, &t8);
+    const int res = resident_workgroups(2 * t8 >= t ? 8 : 4, h->tw);
+    if (res <= 0) return C;
+    const int64_t target = kTilesPerWorkgroup * res;
+    while (C < maxL && batch_tiles(inst, n, C + 1, h->tw, h->th, nullptr) >= target) ++C;
+    return C;
+}
+
 int choose_chunk(pmf_handle *h, const pmf_instance *inst, int n) {
     int maxL = 1;
     for (int i = 0; i < n; ++i) maxL = std::max(maxL, (int)inst[i].L);
@@ -724,7 +753,8 @@ int choose_chunk(pmf_handle *h, const pmf_instance *inst, int n) {
         if (C >= maxL) return maxL;
         int64_t subs = 0;
         const size_t pool = batch_pool_bytes(inst, n, C, h->tw, h->th, &subs);
-        if (subs <= (1 << 20) && pool + control_bytes((int)subs, worklist_cap((int)subs, pool)) <= budget) return C;
+        if (subs <= (1 << 20) && pool + control_bytes((int)subs, worklist_cap((int)subs, pool)) <= budget)
+            return longest_parallel_chunk(h, inst, n, C, maxL);
     }
 }
 

@@ -135,6 +135,10 @@ struct StepParams {
 int launch_superstep(const StepParams &p, int tile_w, void *stream, void *const *events = nullptr,
                      bool split = false);
 
+// Workgroups of the tile kernel of connectivity K that the current device
+// holds at once (0 if the runtime cannot tell).
+int resident_workgroups(int K, int tile_w);
+
 // out[p] (+)= number of the L masks that hold pixel p (n pixels).
 int launch_levels(const uint8_t *masks, int L, int n, uint8_t *out, bool accumulate, void *stream);
 

@@ -1378,6 +1378,21 @@ static int launch_tw(const StepParams &p, hipStream_t s, void *const *ev, bool s
     return n;
 }
 
+int resident_workgroups(int K, int tile_w) {
+    int dev = 0, cus = 0, per = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        return 0;
+    hipError_t e;
+    if (tile_w == 64)
+        e = K == 8 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_step<8, 64, 16>, kThreads, 0)
+                   : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_step<4, 64, 16>, kThreads, 0);
+    else
+        e = K == 8 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_step<8, 32, 32>, kThreads, 0)
+                   : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_step<4, 32, 32>, kThreads, 0);
+    return e == hipSuccess ? per * cus : 0;
+}
+
 int launch_superstep(const StepParams &p, int tile_w, void *stream, void *const *events, bool split) {
     hipStream_t s = (hipStream_t)stream;
     const int n = tile_w == 64 ? launch_tw<64, 16>(p, s, events, split) : launch_tw<32, 32>(p, s, events, split);
