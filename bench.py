@@ -100,13 +100,14 @@ def cpu_baseline(insts, n_sample: int, threads: int):
     return pairs, res, wall
 
 
-def run_serving(qps: float, seconds: float, warmup: float, templates: int, inflight: int, log) -> dict:
+def run_serving(qps: float, seconds: float, warmup: float, templates: int, inflight: int, log,
+                chunk: int = 1) -> dict:
     """The serving workload: Poisson requests (one image, 1..32 seeds, 10..30
     lambdas each) served by the continuous-batching loop on one session."""
     from paper_1509_06004_amd import workload
     from paper_1509_06004_amd.serve import PmfBackend, Server
     arrivals, pick, pool = workload.config4_stream(qps, seconds, warmup, templates=templates)
-    be = PmfBackend(max_slots=4096, supersteps=16)
+    be = PmfBackend(max_slots=4096, supersteps=16, lambda_chunk=chunk)
     srv = Server(be, max_inflight_instances=inflight)
     rep = srv.run(arrivals, lambda i: pool[pick[i]], duration_s=seconds, warmup_s=warmup, qps=qps)
     be.close()
@@ -114,6 +115,7 @@ def run_serving(qps: float, seconds: float, warmup: float, templates: int, infli
     out["workload"] = ("Poisson arrivals; request = one synthetic image 128x96..640x480 (K 4 or 8) with "
                        "1..32 seeds x 10..30 lambdas in [1, 5000], drawn from %d generated images" % templates)
     out["max_inflight_instances"] = inflight
+    out["lambda_chunk"] = chunk
     out["warmup_s"] = warmup
     log("serving qps %g: %s" % (qps, json.dumps({k: v for k, v in out.items() if k != "workload"})))
     return out
@@ -153,7 +155,9 @@ def main():
     ap.add_argument("--serve-seconds", type=float, default=8.0)
     ap.add_argument("--serve-warmup", type=float, default=2.0)
     ap.add_argument("--serve-templates", type=int, default=12)
-    ap.add_argument("--serve-inflight", type=int, default=96)
+    ap.add_argument("--serve-inflight", type=int, default=768)
+    ap.add_argument("--serve-chunk", type=int, default=0,
+                    help="lambdas per device instance in serving (0: whole schedules)")
     ap.add_argument("--serve-full", action="store_true",
                     help="serving sweep at 50, 200 and 800 requests/s, 60 s each after 5 s warm-up")
     ap.add_argument("--no-serve", action="store_true")
@@ -355,10 +359,11 @@ def main():
 
     if not args.no_serve:
         if args.serve_full:
-            out["serving"] = [run_serving(q, 60.0, 5.0, 24, args.serve_inflight, log) for q in (50.0, 200.0, 800.0)]
+            out["serving"] = [run_serving(q, 60.0, 5.0, 24, args.serve_inflight, log, args.serve_chunk)
+                              for q in (50.0, 200.0, 800.0)]
         else:
             out["serving"] = run_serving(args.serve_qps, args.serve_seconds, args.serve_warmup,
-                                         args.serve_templates, args.serve_inflight, log)
+                                         args.serve_templates, args.serve_inflight, log, args.serve_chunk)
         sv = out["serving"] if isinstance(out["serving"], dict) else out["serving"][0]
         out["latency_ms"] = dict(sv["latency_ms"], what="serving: scheduled arrival to results on host, "
                                                          "%g requests/s" % sv["qps"])

@@ -82,7 +82,7 @@ class Backend:
 class PmfBackend(Backend):
     """libpmf session on one GPU (inputs uploaded per request)."""
 
-    def __init__(self, max_slots: int = 4096, pool_bytes: int = 0, supersteps: int = 16, lambda_chunk: int = 1,
+    def __init__(self, max_slots: int = 4096, pool_bytes: int = 0, supersteps: int = 16, lambda_chunk: int = 0,
                  **options):
         import torch
         from . import pmf
@@ -97,9 +97,11 @@ class PmfBackend(Backend):
             raise pmf.PmfError(rc, "pmf_session_open")
         self.options = opts
         self.supersteps = supersteps
-        # every request instance is split into chunks of lambda_chunk lambdas,
-        # each a device instance of its own: more parallel work per request
-        self.chunk = max(1, int(lambda_chunk))
+        # every request instance is split into chunks of lambda_chunk lambdas
+        # (0: not split), each a device instance of its own: more parallel
+        # work per request, but each chunk starts cold.  A stream of requests
+        # brings parallel work of its own, so whole warm chains serve more.
+        self.chunk = int(lambda_chunk) if int(lambda_chunk) > 0 else 1 << 30
         self.groups: Dict[int, List[int]] = {}  # first device id -> device ids of one instance
         self.pool_bytes = pmf.pmf_session_query(self.handle)["free_bytes"]
         self.live: Dict[int, tuple] = {}  # id -> (device inputs, flows view, status view, L, H, W)

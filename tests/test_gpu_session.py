@@ -186,9 +186,11 @@ def test_cancel_leaves_others_intact(env):
     S.close()
 
 
-def test_serving_loop_results_exact(env):
+@pytest.mark.parametrize("chunk", [0, 2])
+def test_serving_loop_results_exact(env, chunk):
     """Requests served through the continuous-batching loop (arrivals overlap)
-    return exactly the oracle's flows and nested masks."""
+    return exactly the oracle's flows and nested masks, whole warm chains
+    (chunk 0) and schedules split into chunks of two lambdas alike."""
     from paper_1509_06004_amd.serve import PmfBackend, Server
     rng = np.random.default_rng(106)
     reqs = []
@@ -201,8 +203,8 @@ def test_serving_loop_results_exact(env):
                                      W.loguniform_lambdas(rng, int(rng.integers(2, 6)), 300.0), image=r)
                      for _ in range(int(rng.integers(1, 4)))])
     arrivals = np.sort(rng.uniform(0, 0.2, size=len(reqs)))
-    say("serving 10 requests")
-    be = PmfBackend(max_slots=256, pool_bytes=1 << 30, supersteps=8, max_supersteps=400000)
+    say("serving 10 requests, lambda chunk %d" % chunk)
+    be = PmfBackend(max_slots=256, pool_bytes=1 << 30, supersteps=8, lambda_chunk=chunk, max_supersteps=400000)
     rep = Server(be, keep_results=True).run(arrivals, lambda i: reqs[i], duration_s=5.0, drain=True)
     be.close()
     assert rep.completed == 10 and rep.failed == 0
