@@ -351,10 +351,13 @@ class Server:
         open_ = [r for r in window if r.failed is None and not np.isfinite(r.finished)]
         lat_list = [r.latency for r in ok] + [dur - r.arrival for r in open_]
         lat = np.array(lat_list) * 1e3 if lat_list else np.array([float("nan")])
-        # throughput counts the solves of every instance that finished in the
-        # measured window (finished requests only)
-        measured_solves = sum(r.solves for r in ok)
-        span = max(min(dur, end) - warmup_s, 1e-9) if not drain else max(dur - warmup_s, 1e-9)
+        # throughput counts the solves of every request that finished inside
+        # the measured time span, whenever it arrived (under overload the
+        # span is spent on requests that queued before it)
+        stop = min(dur, end) if not drain else dur
+        measured_solves = sum(r.solves for r in records
+                              if r.failed is None and np.isfinite(r.finished) and warmup_s <= r.finished <= stop)
+        span = max(stop - warmup_s, 1e-9)
         return ServeReport(qps=qps, offered=len(window), completed=len(ok),
                            failed=sum(r.failed is not None for r in window), duration_s=dur,
                            solves=measured_solves, solves_per_s=measured_solves / span,

@@ -194,3 +194,28 @@ def test_overload_reports_censored_latency():
     assert np.isfinite(rep.p99_ms) and rep.p99_ms >= rep.p50_ms
     # every unfinished request counts at least (end - arrival)
     assert rep.p50_ms >= 0.0
+
+
+def test_overload_throughput_counts_backlog_finished_in_window():
+    """Throughput counts every request that finishes inside the measured span,
+    also those that queued during the warmup; latency counts the requests that
+    arrived inside it."""
+    rng = np.random.default_rng(18)
+    reqs = [[W.tiny_random(rng, 5, 5, 4, cmax=30, L=2, p_seed=0.05)] for _ in range(30)]
+    arrivals = np.linspace(0.0, 0.05, 30)  # all arrive before the measured span ends
+    sim = SimClock()
+
+    class Slow(OracleBackend):
+        def step(self):
+            sim.t += 0.01
+            return super().step()
+
+    be = Slow(budget_bytes=1 << 30, per_step=1)
+    rep = Server(be, clock=sim.clock, sleep=sim.sleep).run(arrivals, lambda i: reqs[i], duration_s=0.1,
+                                                          warmup_s=0.03, drain=False)
+    # requests arriving in [0.03, 0.13): those at or after 0.03
+    assert rep.offered == int((arrivals >= 0.03).sum())
+    # every solve counted belongs to a request that finished inside the span,
+    # and requests from the warmup backlog are among them
+    assert rep.solves > 0 and rep.solves % 2 == 0
+    assert rep.solves > 2 * rep.completed
