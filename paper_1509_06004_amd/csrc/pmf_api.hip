@@ -498,7 +498,16 @@ int run_steps(pmf_handle *h, int steps, std::vector<int> *finished) {
         h->stats.supersteps += steps;
         h->epoch_steps += steps;
     }
+    // A batch (few slots, all admitted at once) copies the whole completion
+    // ring and every slot's state along with the completion count: one round
+    // trip per sync instead of two and a copy per finished instance.
+    const int cap = h->max_slots;
+    const bool bulk = h->batch && (size_t)cap * sizeof(InstState) <= ((size_t)1 << 20);
     if (hipMemcpyAsync(h->pinned, P.ring_count, 4, hipMemcpyDeviceToHost, s) != hipSuccess) return PMF_EDEVICE;
+    if (bulk && (hipMemcpyAsync(h->pinned_ring, P.ring, 4 * (size_t)cap, hipMemcpyDeviceToHost, s) != hipSuccess ||
+                 hipMemcpyAsync(h->pinned_state, P.st, sizeof(InstState) * (size_t)cap, hipMemcpyDeviceToHost, s) !=
+                     hipSuccess))
+        return PMF_EDEVICE;
     if (hipStreamSynchronize(s) != hipSuccess) return PMF_EDEVICE;
     h->stats.host_syncs += 1;
     if (P.ntiles > 0) {
@@ -510,36 +519,39 @@ int run_steps(pmf_handle *h, int steps, std::vector<int> *finished) {
     if (count <= h->ring_seen) return PMF_OK;
     // the new ring entries (at most two contiguous ranges), then the final
     // states of those instances (one bulk copy when many finished)
-    const int cap = h->max_slots;
     const int32_t fresh = count - h->ring_seen;
     if (fresh > cap) return PMF_EDEVICE;  // a slot can finish only once per admission
-    const int a0 = h->ring_seen % cap;
-    const int first_len = std::min(fresh, cap - a0);
-    if (hipMemcpyAsync(h->pinned_ring + a0, P.ring + a0, 4 * (size_t)first_len, hipMemcpyDeviceToHost, s) !=
-        hipSuccess)
-        return PMF_EDEVICE;
-    if (fresh > first_len &&
-        hipMemcpyAsync(h->pinned_ring, P.ring, 4 * (size_t)(fresh - first_len), hipMemcpyDeviceToHost, s) !=
+    if (!bulk) {
+        const int a0 = h->ring_seen % cap;
+        const int first_len = std::min(fresh, cap - a0);
+        if (hipMemcpyAsync(h->pinned_ring + a0, P.ring + a0, 4 * (size_t)first_len, hipMemcpyDeviceToHost, s) !=
             hipSuccess)
-        return PMF_EDEVICE;
-    if (hipStreamSynchronize(s) != hipSuccess) return PMF_EDEVICE;
+            return PMF_EDEVICE;
+        if (fresh > first_len &&
+            hipMemcpyAsync(h->pinned_ring, P.ring, 4 * (size_t)(fresh - first_len), hipMemcpyDeviceToHost, s) !=
+                hipSuccess)
+            return PMF_EDEVICE;
+        if (hipStreamSynchronize(s) != hipSuccess) return PMF_EDEVICE;
+    }
     std::vector<int> got;
     for (int32_t c = h->ring_seen; c < count; ++c) {
         const int id = h->pinned_ring[c % cap];
         if (id < 0 || id >= cap) return PMF_EDEVICE;
         got.push_back(id);
     }
-    if (got.size() > 64) {
-        if (hipMemcpyAsync(h->pinned_state, P.st, sizeof(InstState) * (size_t)cap, hipMemcpyDeviceToHost, s) !=
-            hipSuccess)
-            return PMF_EDEVICE;
-    } else {
-        for (int id : got)
-            if (hipMemcpyAsync(h->pinned_state + id, P.st + id, sizeof(InstState), hipMemcpyDeviceToHost, s) !=
+    if (!bulk) {
+        if (got.size() > 64) {
+            if (hipMemcpyAsync(h->pinned_state, P.st, sizeof(InstState) * (size_t)cap, hipMemcpyDeviceToHost, s) !=
                 hipSuccess)
                 return PMF_EDEVICE;
+        } else {
+            for (int id : got)
+                if (hipMemcpyAsync(h->pinned_state + id, P.st + id, sizeof(InstState), hipMemcpyDeviceToHost, s) !=
+                    hipSuccess)
+                    return PMF_EDEVICE;
+        }
+        if (hipStreamSynchronize(s) != hipSuccess) return PMF_EDEVICE;
     }
-    if (hipStreamSynchronize(s) != hipSuccess) return PMF_EDEVICE;
     h->ring_seen = count;
     for (int id : got) {
         Slot &sl = h->slots[id];
