@@ -7,14 +7,16 @@
 // here from its textbook definition (Goldberg-Tarjan), with exact global
 // relabelling by breadth-first search (Cherkassky-Goldberg):
 //
-//   - every launch is one *superstep*: each workgroup takes one tile
-//     (TW x TH pixels) of one instance and performs that instance's current
-//     phase on it; the last workgroup to finish advances every instance's
-//     phase machine (no host round trip, no grid barrier);
-//   - kSweep: the tile's state is loaded into registers / LDS and
-//     `inner_iters` synchronous push/relabel iterations run against halo
-//     heights; pushes that leave the tile are accumulated and handed to the
-//     neighbour tile through an atomic inbox;
+//   - a *superstep* is three launches: a compaction kernel lists the tiles
+//     that have work, a tile kernel processes them (each workgroup takes one
+//     TW x TH tile of one instance at a time and performs that instance's
+//     current phase on it), and a control kernel advances every instance's
+//     phase machine; supersteps are replayed from a captured graph with no
+//     host round trip in between;
+//   - kSweep: the tile's state is loaded into registers / LDS and up to
+//     `inner_iters` push/relabel iterations run against halo heights; pushes
+//     that leave the tile are accumulated and handed to the neighbour tile
+//     through its atomic inbox;
 //   - kRelabel: exact distances to t by tile-parallel Bellman-Ford relaxation
 //     (tile-local relaxation to a fixed point, repeated over the tiles whose
 //     neighbourhood changed).  A pass in which no label changes proves the
