@@ -720,9 +720,11 @@ size_t batch_pool_bytes(const pmf_instance *inst, int n, int C, int tw, int th, 
 // critical path of supersteps) and long ones less work in total.  First the
 // smallest chunk whose state fits the memory available to the handle; then
 // the longest chunk from there that still gives every workgroup the device
-// holds at once kTilesPerWorkgroup tiles (measured: at 4-connectivity chunks
-// of 2 lambdas, at 8 chunks of 3-4, against 1 everywhere: -3% and -20% on the
-// 500x375 25-seed x 20-lambda batch).
+// holds at once kTilesPerWorkgroup tiles, counting the resident workgroups
+// of the connectivity that holds most of the batch's tiles (measured on the
+// 500x375 25-seed x 20-lambda batch: chunks of 2 lambdas at 4-connectivity
+// and of 3-4 at 8 were fastest; the rule picks 2 and 3, -7% and -20% against
+// chunks of 1).
 constexpr int64_t kTilesPerWorkgroup = 40;
 
 int64_t batch_tiles(const pmf_instance *inst, int n, int C, int tw, int th, int64_t *t8) {
