@@ -7,7 +7,7 @@ same counter reads for a device-to-device copy of known size in the same run
 (the largest copy dispatch; the benchmark issues one of ``--calib-bytes``).
 
 The output is a short ``key: value`` text file that records the command lines,
-the kernel and the SHA-256 of the kernel source it was measured on.
+the kernel and the SHA-256 of the device-code sources it was measured on.
 """
 
 from __future__ import annotations
@@ -19,12 +19,17 @@ import sqlite3
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-KERNEL_SOURCE = os.path.join(HERE, "csrc", "pmf_kernels.hip")
+# the sources the device code is compiled from
+KERNEL_SOURCES = [os.path.join(HERE, "csrc", f) for f in ("pmf_kernels.hip", "pmf_border.h", "pmf_internal.h")]
 
 
 def source_hash() -> str:
-    with open(KERNEL_SOURCE, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()
+    h = hashlib.sha256()
+    for path in KERNEL_SOURCES:
+        h.update(os.path.basename(path).encode() + b"\0")
+        with open(path, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
 
 
 def kernel_stats(db: str):
