@@ -584,7 +584,7 @@ void pmf_default_options(pmf_options *o) {
     std::memset(o, 0, sizeof(*o));
     o->tile_w = 32;
     o->tile_h = 32;
-    o->inner_iters = 16;
+    o->inner_iters = 12;
     o->sweeps_per_relabel = 12;
     o->local_bfs_iters = 16;
     o->exchange_rounds = 2;

@@ -29,7 +29,7 @@ KNOBS = ("tile_w", "inner_iters", "sweeps_per_relabel", "local_bfs_iters", "exch
          "tail_inner_iters", "tail_exchange_rounds", "relabel_passes", "orientation", "order", "lambda_chunk")
 SPACE = {
     "tile_w": [32, 64],
-    "inner_iters": [4, 8, 16, 32],
+    "inner_iters": [4, 8, 12, 16, 32],
     "sweeps_per_relabel": [2, 4, 8, 16],
     "local_bfs_iters": [8, 16, 32, 64],
     "exchange_rounds": [1, 2, 4, 8],
