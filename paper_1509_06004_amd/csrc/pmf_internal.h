@@ -93,7 +93,7 @@ struct alignas(16) InstState {
     int32_t swap;     // 1: solved with source and sink exchanged (decided once per instance)
     int32_t cnt_pos;  // kOrient: pixels with cs > ct at lambda_0
     int32_t cnt_neg;  // kOrient: pixels with cs < ct at lambda_0
-    int32_t pad;
+    int32_t listed;   // the last compaction listed a tile of this instance to sweep
     int64_t sum_raise;  // exchanged instances: source capacity added for the next lambda
     int64_t px_orient, px_init_x, px_cut_x;  // pixel visits: orientation count, exchanged init and cut
 };

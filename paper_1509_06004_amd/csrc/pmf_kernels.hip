@@ -794,6 +794,7 @@ __device__ void cut_tile_swapped(const StepParams &P, const InstDesc &D, InstSta
         }
     }
     long long se = 0, sraise = 0;
+    int act = 0;
 #pragma unroll
     for (int j = 0; j < PPT; ++j) {
         if (!valid[j]) continue;
@@ -810,11 +811,18 @@ __device__ void cut_tile_swapped(const StepParams &P, const InstDesc &D, InstSta
             gp(D.e)[p] = ne;
             const int rm = (rmv[j] & ~(kRtBit | kEBit)) | (nrt > 0 ? kRtBit : 0) | (ne > 0 ? kEBit : 0);
             if (rm != rmv[j]) gp(D.rmask)[p] = (uint16_t)rm;
+            act |= ne > 0 && hv[j] < kHInf;
         }
     }
     const long long tse = block_sum_i64(se, s_sum);
     const long long tra = block_sum_i64(sraise, s_sum);
+    // The next lambda starts from these labels (exchanged instances skip the
+    // relabel there): the tiles with a pixel made active by the raise are the
+    // sweep's work (every other tile has none: the relabel that ended this
+    // lambda left no active pixel).
+    const int tact = __syncthreads_or(act);
     if (tid == 0) {
+        if (tact) g_or(&gp(D.tile_act)[tl], 1u);
         gp(D.tile_chg)[tl] = 0;  // the cut is complete after this pass
         if (tse) atomicAdd((unsigned long long *)&S->sum_e, (unsigned long long)tse);
         if (tra) atomicAdd((unsigned long long *)&S->sum_raise, (unsigned long long)tra);
@@ -1038,7 +1046,7 @@ __device__ void control(const StepParams &P) {
             break;
         case kSweep:
             S.sweeps += 1;
-            if (++S.sub >= P.sweeps_per_relabel) {
+            if (++S.sub >= P.sweeps_per_relabel || !S.listed) {
                 ph = kRelabel;
                 S.sub = 0;
                 S.active = 0;
@@ -1056,6 +1064,12 @@ __device__ void control(const StepParams &P) {
                 S.k = k + 1;
                 if (k + 1 >= L) {
                     done = true;
+                } else if (S.swap) {
+                    // exchanged: the raise only took sink residual away, so no
+                    // distance shrank and the converged labels stay valid
+                    // lower bounds: the next lambda sweeps from them at once
+                    ph = kSweep;
+                    S.sub = 0;
                 } else {
                     ph = kRelabel;
                     S.sub = 0;
@@ -1120,6 +1134,7 @@ __global__ __launch_bounds__(kThreads) void k_compact(StepParams P) {
     int2 *sl = lists + (is8 ? 1 : 0) * (size_t)P.list_cap;
     int2 *pl = lists + (is8 ? 3 : 2) * (size_t)P.list_cap;
     int32_t *sc = P.list_count + (is8 ? 1 : 0), *pc = P.list_count + (is8 ? 3 : 2);
+    int nsw = 0;
     for (int t0 = 0; t0 < D.ntiles; t0 += kThreads) {
         const int tl = t0 + (int)threadIdx.x;
         bool sw = false, bf = false;
@@ -1137,7 +1152,12 @@ __global__ __launch_bounds__(kThreads) void k_compact(StepParams P) {
         const int2 en = make_int2(slot, tl);
         wave_append(sw, sl, sc, en);
         wave_append(bf, pl, pc, en);
+        nsw |= sw;
     }
+    // a sweeping instance with no tile to sweep is at rest: the control
+    // kernel then starts its relabel at once
+    const int any = __syncthreads_or(nsw);
+    if (threadIdx.x == 0) P.st[slot].listed = any;
 }
 
 // Item i of a list, the same for every thread of the workgroup (scalar registers).
