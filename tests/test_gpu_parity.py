@@ -123,6 +123,25 @@ def test_orientation_edge_cases(pmf, orientation, chunk):
     check_against_oracle(tiny, flows, status, masks)
 
 
+@pytest.mark.parametrize("K", [4, 8])
+def test_warm_chains_as_given_repeated(pmf, K):
+    """Whole warm chains solved as given (never exchanged), on grids of many
+    tiles: three solves of the same batch each match the oracle at every
+    lambda (a race between tiles would surface as a wrong flow in some run)."""
+    rng = np.random.default_rng(300 + K)
+    insts = []
+    for i in range(4):
+        img = W.voronoi_image(int(rng.integers(70, 130)), int(rng.integers(60, 110)), 8, rng)
+        nl = W.nlinks(img, K)
+        H, Wd = img.shape
+        insts.append(W.seed_instance(img, nl, K, int(rng.integers(5, Wd - 5)), int(rng.integers(5, H - 5)), 5,
+                                     W.loguniform_lambdas(rng, 8, 400.0), image=i))
+    for rep in range(3):
+        say("warm chains as given K", K, "solve", rep)
+        flows, status, masks, _ = solve(pmf, insts, orientation=0, lambda_chunk=100)
+        check_against_oracle(insts, flows, status, masks)
+
+
 def test_config0(pmf):
     insts = W.config0()
     say("config0 64x64")
