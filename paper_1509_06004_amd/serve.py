@@ -78,6 +78,10 @@ class Backend:
     def release(self, ids: Sequence[int]) -> None:
         raise NotImplementedError
 
+    def reset(self) -> None:
+        """Drop every admitted instance and free all slots and memory."""
+        raise NotImplementedError
+
 
 class PmfBackend(Backend):
     """libpmf session on one GPU (inputs uploaded per request)."""
@@ -96,6 +100,9 @@ class PmfBackend(Backend):
         if rc != pmf.PMF_OK:
             raise pmf.PmfError(rc, "pmf_session_open")
         self.options = opts
+        self.max_slots, self.pool_arg = max_slots, pool_bytes
+        self.owner_of: Dict[int, int] = {}
+        self.pending: Dict[int, int] = {}
         self.supersteps = supersteps
         # every request instance is split into chunks of lambda_chunk lambdas
         # (0: not split), each a device instance of its own: more parallel
@@ -152,11 +159,9 @@ class PmfBackend(Backend):
             firsts.append(grp[0])
             off += d.L
             pos += n_ch
-        self.owner_of = getattr(self, "owner_of", {})
         for f in firsts:
             for i in self.groups[f]:
                 self.owner_of[i] = f
-        self.pending = getattr(self, "pending", {})
         for f in firsts:
             self.pending[f] = len(self.groups[f])
         return firsts
@@ -210,6 +215,15 @@ class PmfBackend(Backend):
                 self.owner_of.pop(i, None)
             self.pending.pop(f, None)
             self.live.pop(f, None)
+
+    def reset(self) -> None:
+        rc = self.pmf.pmf_session_open(self.handle, self.max_slots, self.pool_arg)
+        if rc != self.pmf.PMF_OK:
+            raise self.pmf.PmfError(rc, "pmf_session_open")
+        self.groups.clear()
+        self.live.clear()
+        self.owner_of.clear()
+        self.pending.clear()
 
     def stats(self) -> Dict[str, int]:
         return self.pmf.pmf_get_stats(self.handle)
@@ -318,10 +332,18 @@ class Server:
             try:
                 done = be.step()
             except Exception as exc:
-                # the device step failed: fail every request in flight
-                for i, rec in list(inflight.items()):
+                # the device step failed: fail every request in flight and
+                # hand its slots and memory back (if that fails too, the
+                # backend starts afresh, which frees everything)
+                failed = {rec.index: rec for rec in inflight.values()}
+                for idx, rec in failed.items():
                     rec.failed = repr(exc)
                     rec.finished = self.clock() - t0
+                    ids = ids_of.pop(idx, [])
+                    try:
+                        be.release(ids)
+                    except Exception:
+                        be.reset()
                 inflight.clear()
                 left.clear()
                 n_inflight = 0

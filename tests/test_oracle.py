@@ -306,3 +306,24 @@ def test_planted_mistake_is_caught():
         for k, lam in enumerate(inst.lambdas.tolist()):
             bad += wrong_cost(inst, lam, masks[k]) != flows[k]
     assert bad > 0
+
+
+def test_int32_headroom_brute_force():
+    """At the largest admitted n-link capacity next to INF seeds (excess up to
+    INF + K * PMF_NLINK_MAX(K)), both algorithms equal exhaustive enumeration:
+    the oracle's int64 arithmetic holds where the device's int32 state is
+    tightest."""
+    from helpers import headroom_instance
+    rng = np.random.default_rng(2024)
+    biggest = 0
+    for i in range(24):
+        K = 4 if i % 2 else 8
+        Wd, Hd = int(rng.integers(3, 5)), int(rng.integers(3, 5))
+        inst = headroom_instance(rng, Wd, Hd, K, 2)
+        for lam in inst.lambdas.tolist():
+            F, S, _ = O.brute_force(inst, lam)
+            biggest = max(biggest, F)
+            for fn in (O.fifo_pr, O.ek):
+                f, m = fn(inst, lam)
+                assert f == F and (m == S).all(), (i, fn.__name__, lam)
+    assert biggest >= (1 << 31) - 8  # some optimal cuts cost about INF + K * PMF_NLINK_MAX(K)

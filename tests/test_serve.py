@@ -77,6 +77,13 @@ class OracleBackend(Backend):
         for i in ids:
             inst, _ = self.live.pop(i)
             self.used -= self.bytes_needed([inst])
+            if i in self.queue:
+                self.queue.remove(i)
+
+    def reset(self):
+        self.live.clear()
+        self.queue.clear()
+        self.used = 0
 
 
 def make_stream(n, seed=3):
@@ -150,6 +157,29 @@ def test_failed_step_fails_only_inflight_requests():
     be = OracleBackend(budget_bytes=1 << 30, per_step=1, fail_step_at=2)
     rep = Server(be).run(arrivals, lambda i: reqs[i], duration_s=1.0, drain=True)
     assert rep.failed >= 1 and rep.completed + rep.failed == 10
+    # the failed requests' slots and memory went back to the backend
+    assert be.used == 0 and not be.live and not be.queue
+
+
+def test_failed_release_resets_backend():
+    arrivals, reqs = make_stream(10, seed=12)
+
+    class BadRelease(OracleBackend):
+        resets = 0
+
+        def release(self, ids):
+            if self.steps == self.fail_step_at:
+                raise RuntimeError("injected release failure")
+            super().release(ids)
+
+        def reset(self):
+            self.resets += 1
+            super().reset()
+
+    be = BadRelease(budget_bytes=1 << 30, per_step=1, fail_step_at=2)
+    rep = Server(be).run(arrivals, lambda i: reqs[i], duration_s=1.0, drain=True)
+    assert be.resets >= 1 and rep.failed >= 1 and rep.completed + rep.failed == 10
+    assert be.used == 0 and not be.live
 
 
 def test_request_larger_than_pool_fails_fast():
