@@ -90,7 +90,22 @@ typedef struct pmf_options {
                                 /*   than cs > ct at lambda_0 (1, the paper's rule), */
                                 /*   when more have cs > ct (2), or always (3).     */
                                 /*   Results are the same in every case.            */
-    int32_t reserved2;
+    int32_t gap;                /* 1: gap heuristic between global relabels         */
+                                /*   (Cherkassky-Goldberg): a per-instance count of */
+                                /*   pixels per label, kept by the relabel passes   */
+                                /*   and the sweeps; when a level empties, the      */
+                                /*   pixels above it cannot reach the sink and stop */
+                                /*   being active until the next global relabel.    */
+                                /*   0: off.  Costs 4 bytes of device memory per    */
+                                /*   pixel.                                         */
+    int32_t persist_tiles;      /* once a superstep lists fewer tiles than this,    */
+                                /*   supersteps run back to back inside one         */
+                                /*   cooperative (persistent) launch, separated by  */
+                                /*   grid-wide barriers, until the lists grow past  */
+                                /*   twice this, every instance is done, or the     */
+                                /*   host polls (0 = never; not with gap = 1)       */
+    int32_t persist_wgs;        /* workgroups of that launch (0 = one per compute   */
+                                /*   unit; at most what the device holds at once)   */
 } pmf_options;
 
 /* One (image, seed) problem and its lambda schedule.  All pointers are device
@@ -148,6 +163,15 @@ typedef struct pmf_stats {
     int64_t px_orient;        /* pixel visits of the orientation count, of the init */
     int64_t px_init_x;        /*   and of the cut passes of exchanged instances     */
     int64_t px_cut_x;         /*   (not in px_init / px_cut)                        */
+    int64_t gap_kills;        /* pixels the gap heuristic stopped (options.gap)     */
+    int64_t persist_launches; /* persistent launches, the supersteps they ran and,  */
+    int64_t persist_supersteps; /* with opt.timing, their GPU time                  */
+    int64_t persist_ns;
+    int64_t kernel_px[16];    /* with opt.timing: pixel visits of the tile-work     */
+                              /*   launches ([0..6]) and of the persistent launches */
+                              /*   ([8..14]) by kind: sweep, relabel pass, cut      */
+                              /*   pass, init, orientation count, exchanged init,   */
+                              /*   exchanged cut                                    */
 } pmf_stats;
 
 /* Fill *opt with defaults. */
@@ -175,6 +199,22 @@ int pmf_create(const pmf_options *opt, void *stream, void *workspace, size_t ws_
  * W, H, L < 1, NULL pointers), PMF_ENOMEM, PMF_EDEVICE. */
 int pmf_solve_batch(pmf_handle *h, const pmf_instance *inst, int32_t n_inst, int64_t *flows_out,
                     int32_t *status_out);
+
+/* pmf_solve_batch that returns once the solve is set up: the superstep loop
+ * (launches on the handle's stream and the host polls between them) runs on a
+ * thread of the library while the caller goes on.  Same arguments, results
+ * and host-side errors as pmf_solve_batch; the instance array is copied, the
+ * device arrays it points to must stay valid until pmf_wait returns.  The
+ * caller enqueues nothing on the handle's stream meanwhile (work on other
+ * streams is fine).  pmf_wait blocks until the solve is done and returns its
+ * status (what pmf_solve_batch would have returned; PMF_OK when no solve is
+ * outstanding); pmf_query_done sets *done to 1 once it is done, 0 before,
+ * without blocking.  Every other call on the handle first waits for the
+ * outstanding solve. */
+int pmf_solve_batch_async(pmf_handle *h, const pmf_instance *inst, int32_t n_inst, int64_t *flows_out,
+                          int32_t *status_out);
+int pmf_wait(pmf_handle *h);
+int pmf_query_done(pmf_handle *h, int32_t *done);
 
 /* Copy the minimal source side S_min of (instance inst, lambda index
  * lambda_idx) of the last solve -- inst is the index in the batch, or a

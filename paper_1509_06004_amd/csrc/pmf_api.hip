@@ -6,12 +6,15 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <climits>
 #include <cmath>
 #include <cstring>
 #include <functional>
+#include <atomic>
 #include <map>
 #include <new>
 #include <numeric>
+#include <thread>
 #include <vector>
 
 #include "pmf.h"
@@ -39,6 +42,8 @@ bool valid_options(const pmf_options &o) {
     if (o.exchange_rounds < 1 || o.exchange_rounds > 64) return false;
     if (o.tail_tiles < 0 || o.relabel_passes < 0) return false;
     if (o.orientation < kOrientAsGiven || o.orientation > kOrientExchange) return false;
+    if (o.gap != 0 && o.gap != 1) return false;
+    if (o.persist_tiles < 0 || o.persist_wgs < 0) return false;
     if (o.tail_tiles > 0 && (o.tail_inner_iters < 1 || o.tail_inner_iters > 4096 ||
                              o.tail_exchange_rounds < 1 || o.tail_exchange_rounds > 64))
         return false;
@@ -60,11 +65,11 @@ int check_instance(const pmf_instance &I) {
 
 // Byte offsets of one instance's planes inside its block.
 struct BlockLayout {
-    size_t r, e, rt, h, inbox, rmask, masks, tile_act, tile_chg, tile_cnt, total;
+    size_t r, e, rt, h, inbox, rmask, masks, tile_act, tile_chg, tile_cnt, hist, total;
     int tiles_x, tiles_y;
 };
 
-BlockLayout block_layout(const pmf_instance &I, int tw, int th) {
+BlockLayout block_layout(const pmf_instance &I, int tw, int th, bool gap) {
     BlockLayout b;
     b.tiles_x = (I.W + tw - 1) / tw;
     b.tiles_y = (I.H + th - 1) / th;
@@ -85,6 +90,7 @@ BlockLayout block_layout(const pmf_instance &I, int tw, int th) {
     b.tile_act = take(4 * nt);
     b.tile_chg = take(2 * nt);
     b.tile_cnt = take(4 * nt);
+    b.hist = gap ? take(4 * nt * (size_t)(tw * th)) : 0;
     b.total = off;
     return b;
 }
@@ -96,7 +102,8 @@ size_t worklist_cap(int slots, size_t pool_bytes) { return pool_bytes / 512 + (s
 // Device bytes of the control area for `slots` slots and a work list of `wl` tiles.
 size_t control_bytes(int slots, size_t wl) {
     return align_up(sizeof(InstDesc) * (size_t)slots) + align_up(sizeof(InstState) * (size_t)slots) +
-           align_up(4 * (size_t)slots) + align_up(256) + align_up(4 * (size_t)slots) + align_up(4 * 8 * wl);
+           align_up(4 * (size_t)slots) + align_up(256) + align_up(4 * (size_t)slots) + align_up(4 * 8 * wl) +
+           align_up(sizeof(StepParams));
 }
 
 // First-fit allocator over [0, cap) with coalescing of freed ranges.
@@ -169,7 +176,7 @@ struct pmf_handle {
     char *arena = nullptr;
     size_t arena_bytes = 0;
     bool own_arena = true;
-    int32_t *pinned = nullptr;  // host-visible copy of the completion counter
+    int32_t *pinned = nullptr;  // host-visible copy of the counter block (completions, list sizes, barrier)
     int32_t *pinned_ring = nullptr;
     InstState *pinned_state = nullptr;
     // session
@@ -188,12 +195,40 @@ struct pmf_handle {
     int graph_S = 0;
     pmf_stats stats;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;  // bracket every launch group (device time)
-    hipEvent_t kev[4] = {nullptr, nullptr, nullptr, nullptr};  // per-kernel timing mode
+    // timing mode: four events per superstep of a host round (after the
+    // compaction, the sweeps, the passes and the control kernel) and a device
+    // buffer for the list sizes of each of those supersteps
+    std::vector<hipEvent_t> kev;
+    int32_t *trace_lists = nullptr;
+    int trace_cap = 0;
+    int64_t *kpx = nullptr;  // timing mode: pixel visits by kind, [0..7] tile-work launches, [8..15] persistent
     std::vector<int64_t> trace;  // timing mode: PMF_TRACE_COLS values per superstep
     // pmf_solve_batch: caller instance i = slots [user_first[i], user_first[i+1]),
     // lambda k of it in slot user_first[i] + k / chunk at index k % chunk
     bool batch = false;
     int32_t chunk = 1;
+    // persistent supersteps: workgroups of the cooperative launch (0: not
+    // available), tiles listed by the last superstep (-1: not known yet), and
+    // whether a barrier wait gave up (the device state is then unusable)
+    int persist_grid[3] = {0, 0, 0};  // by work-list connectivity: 4 only, 8 only, mixed
+    size_t reserve_tail = 0;  // bytes at the end of the arena that sessions leave alone (pmf_parametric)
+    // pmf_solve_batch_async: the thread running the superstep loop, the
+    // instances it works on (a copy of the caller's array) and its status
+    std::thread worker;
+    std::vector<pmf_instance> async_inst;
+    std::atomic<int> async_done{1};
+    int async_rc = PMF_OK;
+    int64_t last_listed = -1;
+    bool poisoned = false;
+    StepParams *P_dev = nullptr;          // device copy of P read by the persistent launch
+    StepParams *pinned_params = nullptr;  // its staging copy
+    // device memory the current session is laid out in: the arena, or memory
+    // handed in for one solve (then polled through host vectors instead of
+    // the pinned buffers, so that the solve allocates nothing)
+    char *base = nullptr;
+    bool ext = false;
+    std::vector<int32_t> host_ring;
+    std::vector<InstState> host_state;
     std::vector<int32_t> user_first, user_L;
 };
 
@@ -204,6 +239,16 @@ void drop_graph(pmf_handle *h) {
         (void)hipGraphExecDestroy(h->graph);
         h->graph = nullptr;
     }
+}
+
+// Wait for an outstanding pmf_solve_batch_async (every call on a handle
+// does, so the worker thread and the caller never use the handle together);
+// returns that solve's status.
+int finish_async(pmf_handle *h) {
+    if (h->worker.joinable()) h->worker.join();
+    const int rc = h->async_rc;
+    h->async_rc = PMF_OK;
+    return rc;
 }
 
 int ensure_arena(pmf_handle *h, size_t need) {
@@ -227,17 +272,32 @@ int ensure_arena(pmf_handle *h, size_t need) {
     return PMF_OK;
 }
 
-// Lay out the control area at the start of the arena and the pool after it.
-int open_session(pmf_handle *h, int slots, size_t pool_bytes) {
+// Lay out the control area at the start of the arena and the pool after it
+// (or at the start of `ext_base`, ext_bytes of device memory handed in for
+// one solve, which must hold both: PMF_ENOMEM otherwise; host buffers for
+// polling are then ordinary host memory).
+int open_session(pmf_handle *h, int slots, size_t pool_bytes, char *ext_base = nullptr, size_t ext_bytes = 0) {
     if (slots < 1) return PMF_EINVAL;
     drop_graph(h);
     h->open = false;
     (void)hipStreamSynchronize(h->stream);
     const size_t wl = worklist_cap(slots, pool_bytes);
     const size_t ctl = control_bytes(slots, wl);
-    int rc = ensure_arena(h, ctl + pool_bytes);
-    if (rc != PMF_OK) return rc;
-    if ((int)h->slots.size() < slots || !h->pinned_ring) {
+    h->ext = ext_base != nullptr;
+    size_t base_bytes = 0;
+    if (h->ext) {
+        if (ctl + pool_bytes > ext_bytes) return PMF_ENOMEM;
+        h->base = ext_base;
+        base_bytes = ext_bytes;
+        h->host_ring.resize(slots);
+        h->host_state.resize(slots);
+    } else {
+        int rc = ensure_arena(h, ctl + pool_bytes + h->reserve_tail);
+        if (rc != PMF_OK) return rc;
+        h->base = h->arena;
+        base_bytes = h->arena_bytes - h->reserve_tail;
+    }
+    if (!h->ext && ((int)h->slots.size() < slots || !h->pinned_ring)) {
         if (h->pinned_state) (void)hipHostFree(h->pinned_state);
         if (h->pinned_ring) (void)hipHostFree(h->pinned_ring);
         h->pinned_state = nullptr;
@@ -249,7 +309,7 @@ int open_session(pmf_handle *h, int slots, size_t pool_bytes) {
             return PMF_ENOMEM;
         }
     }
-    char *A = h->arena;
+    char *A = h->base;
     size_t off = 0;
     auto take = [&](size_t bytes) {
         size_t at = off;
@@ -264,6 +324,7 @@ int open_session(pmf_handle *h, int slots, size_t pool_bytes) {
     P.ring_count = (int32_t *)take(256);
     P.wl_slot = (const int32_t *)take(4 * (size_t)slots);
     P.lists = (int32_t *)take(4 * 8 * wl);
+    h->P_dev = (StepParams *)take(sizeof(StepParams));
     P.list_count = P.ring_count + 4;  // counter block: [0] ring, [4..11] lists
     P.list_cap = (int32_t)wl;
     P.ring_cap = slots;
@@ -277,10 +338,11 @@ int open_session(pmf_handle *h, int slots, size_t pool_bytes) {
     P.tail_exchange_rounds = h->opt.tail_exchange_rounds;
     P.relabel_passes = h->opt.relabel_passes;
     P.orientation = h->opt.orientation;
+    P.gap = h->opt.gap;
     P.max_steps = h->opt.max_supersteps;
     h->pool_base = off;
     // the work list is sized for pool_bytes, so the pool must not exceed it
-    h->pool.reset(std::min(h->arena_bytes - off, pool_bytes));
+    h->pool.reset(std::min(base_bytes - off, pool_bytes));
     h->max_slots = slots;
     h->wl_cap = wl;
     h->slots.assign(slots, Slot());
@@ -289,9 +351,12 @@ int open_session(pmf_handle *h, int slots, size_t pool_bytes) {
     h->ring_seen = 0;
     h->wl_dirty = true;
     h->epoch_steps = 0;
+    h->last_listed = -1;
+    h->poisoned = false;
+    if (h->kpx && hipMemsetAsync(h->kpx, 0, 16 * sizeof(int64_t), h->stream) != hipSuccess) return PMF_EDEVICE;
     std::memset(&h->stats, 0, sizeof(h->stats));
     h->trace.clear();
-    h->stats.device_bytes = (int64_t)h->arena_bytes;
+    h->stats.device_bytes = (int64_t)base_bytes;
     // every slot starts idle; the completion counter at zero
     if (hipMemsetAsync(P.st, 0, sizeof(InstState) * (size_t)slots, h->stream) != hipSuccess ||
         hipMemsetAsync(P.ring_count, 0, 256, h->stream) != hipSuccess)
@@ -349,7 +414,7 @@ int submit(pmf_handle *h, const pmf_instance *inst, int n, int64_t *flows_out, i
     std::vector<BlockLayout> lay(n);
     int got = 0;
     for (; got < n; ++got) {
-        lay[got] = block_layout(inst[got], h->tw, h->th);
+        lay[got] = block_layout(inst[got], h->tw, h->th, h->opt.gap != 0);
         if (!h->pool.alloc(lay[got].total, &offs[got])) break;
     }
     if (got < n) {
@@ -363,7 +428,7 @@ int submit(pmf_handle *h, const pmf_instance *inst, int n, int64_t *flows_out, i
     for (int i = 0; i < n; ++i) {
         const pmf_instance &I = inst[i];
         const BlockLayout &B = lay[i];
-        char *base = h->arena + h->pool_base + offs[i];
+        char *base = h->base + h->pool_base + offs[i];
         const int id = h->free_slots.back();
         h->free_slots.pop_back();
         ids[i] = id;
@@ -396,6 +461,8 @@ int submit(pmf_handle *h, const pmf_instance *inst, int n, int64_t *flows_out, i
         D.tile_act = (uint32_t *)(base + B.tile_act);
         D.tile_chg = (uint8_t *)(base + B.tile_chg);
         D.tile_cnt = (int32_t *)(base + B.tile_cnt);
+        D.hist = h->opt.gap ? (int32_t *)(base + B.hist) : nullptr;
+        D.hsize = h->opt.gap ? D.ntiles * h->tw * h->th : 0;
         D.flows = flows_out + lam_base;
         D.status = status_out ? status_out + i : nullptr;
         lam_base += I.L;
@@ -403,6 +470,7 @@ int submit(pmf_handle *h, const pmf_instance *inst, int n, int64_t *flows_out, i
         const int pol = h->opt.orientation;
         st[i].phase = (pol == kOrientMoreSink || pol == kOrientMoreSource) ? kOrient : kInit;
         st[i].swap = pol == kOrientExchange ? 1 : 0;
+        st[i].gap = kHInf;
         Slot &s = h->slots[id];
         s = Slot();
         s.live = true;
@@ -430,28 +498,67 @@ int submit(pmf_handle *h, const pmf_instance *inst, int n, int64_t *flows_out, i
     return PMF_OK;
 }
 
-// Timing mode, after a superstep has completed: kernel times from the events
-// and one trace row (list sizes of that superstep and the three times).
-void read_kernel_events(pmf_handle *h) {
-    float a = 0.f, b = 0.f, c = 0.f;
-    if (hipEventElapsedTime(&a, h->kev[0], h->kev[1]) != hipSuccess) a = 0.f;
-    if (hipEventElapsedTime(&b, h->kev[1], h->kev[2]) != hipSuccess) b = 0.f;
-    if (hipEventElapsedTime(&c, h->kev[2], h->kev[3]) != hipSuccess) c = 0.f;
-    const bool split = h->opt.timing == 2;
-    const int64_t na = (int64_t)(a * 1e6), nb = (int64_t)(b * 1e6), nc = (int64_t)(c * 1e6);
-    const int64_t sw = split ? na : 0, ps = split ? nb : 0, work = na + nb;
-    h->stats.work_ns += work;
-    h->stats.sweep_ns += sw;
-    h->stats.pass_ns += ps;
-    h->stats.control_ns += nc;
-    int32_t cnt[4] = {0, 0, 0, 0};
-    if (hipMemcpy(cnt, h->P.list_count + 4, sizeof(cnt), hipMemcpyDeviceToHost) != hipSuccess) return;
-    const int64_t row[PMF_TRACE_COLS] = {cnt[0], cnt[1], cnt[2], cnt[3], sw, ps, nc, work};
-    h->trace.insert(h->trace.end(), row, row + PMF_TRACE_COLS);
+// Timing mode: room for the events and list sizes of `steps` supersteps.
+int ensure_timing(pmf_handle *h, int steps) {
+    if (!h->kpx) {
+        if (hipMalloc((void **)&h->kpx, 16 * sizeof(int64_t)) != hipSuccess) {
+            (void)hipGetLastError();
+            h->kpx = nullptr;
+            return PMF_ENOMEM;
+        }
+        if (hipMemsetAsync(h->kpx, 0, 16 * sizeof(int64_t), h->stream) != hipSuccess) return PMF_EDEVICE;
+    }
+    while ((int)h->kev.size() < 4 * steps) {
+        hipEvent_t e = nullptr;
+        if (hipEventCreate(&e) != hipSuccess) return PMF_EDEVICE;
+        h->kev.push_back(e);
+    }
+    if (h->trace_cap < steps) {
+        if (h->trace_lists) {
+            (void)hipStreamSynchronize(h->stream);
+            (void)hipFree(h->trace_lists);
+            h->trace_lists = nullptr;
+            h->trace_cap = 0;
+        }
+        if (hipMalloc((void **)&h->trace_lists, 16 * (size_t)steps) != hipSuccess) {
+            (void)hipGetLastError();
+            return PMF_ENOMEM;
+        }
+        h->trace_cap = steps;
+    }
+    return PMF_OK;
 }
 
-// Launch `steps` supersteps, wait, and collect the slots that finished.
-int run_steps(pmf_handle *h, int steps, std::vector<int> *finished) {
+// Timing mode, after `steps` supersteps have completed: kernel times from the
+// events and one trace row per superstep (its list sizes and the three times).
+int read_kernel_events(pmf_handle *h, int steps) {
+    std::vector<int32_t> cnt(4 * (size_t)steps);
+    if (hipMemcpy(cnt.data(), h->trace_lists, 16 * (size_t)steps, hipMemcpyDeviceToHost) != hipSuccess)
+        return PMF_EDEVICE;
+    const bool split = h->opt.timing == 2;
+    for (int i = 0; i < steps; ++i) {
+        hipEvent_t *ev = h->kev.data() + 4 * i;
+        float a = 0.f, b = 0.f, c = 0.f;
+        if (hipEventElapsedTime(&a, ev[0], ev[1]) != hipSuccess) a = 0.f;
+        if (hipEventElapsedTime(&b, ev[1], ev[2]) != hipSuccess) b = 0.f;
+        if (hipEventElapsedTime(&c, ev[2], ev[3]) != hipSuccess) c = 0.f;
+        const int64_t na = (int64_t)(a * 1e6), nb = (int64_t)(b * 1e6), nc = (int64_t)(c * 1e6);
+        const int64_t sw = split ? na : 0, ps = split ? nb : 0, work = na + nb;
+        h->stats.work_ns += work;
+        h->stats.sweep_ns += sw;
+        h->stats.pass_ns += ps;
+        h->stats.control_ns += nc;
+        const int32_t *c4 = cnt.data() + 4 * i;
+        const int64_t row[PMF_TRACE_COLS] = {c4[0], c4[1], c4[2], c4[3], sw, ps, nc, work};
+        h->trace.insert(h->trace.end(), row, row + PMF_TRACE_COLS);
+    }
+    return PMF_OK;
+}
+
+// Launch `steps` supersteps (or, in the latency-bound tail, one persistent
+// launch of up to `persist_steps`), wait, and collect the slots that finished.
+int run_steps(pmf_handle *h, int steps, std::vector<int> *finished, int persist_steps = 0) {
+    if (h->poisoned) return PMF_EDEVICE;
     if (h->wl_dirty) {
         const int rc = rebuild_worklist(h);
         if (rc != PMF_OK) return rc;
@@ -459,9 +566,33 @@ int run_steps(pmf_handle *h, int steps, std::vector<int> *finished) {
     StepParams &P = h->P;
     hipStream_t s = h->stream;
     const bool timing = h->opt.timing != 0;
-    if (P.ntiles > 0) {
+    bool persisted = false;
+    if (timing) {
+        const int rc = ensure_timing(h, steps);
+        if (rc != PMF_OK) return rc;
+    }
+    const int kset = P.t8_count == 0 ? 4 : P.t4_count == 0 ? 8 : 12;
+    int &pgrid = h->persist_grid[kset == 4 ? 0 : kset == 8 ? 1 : 2];
+    if (P.ntiles > 0 && h->opt.persist_tiles > 0 && !h->opt.gap && pgrid >= 8 && h->last_listed >= 0 &&
+        h->last_listed < h->opt.persist_tiles) {
+        const int budget = std::max(steps, persist_steps);
+        if (hipEventRecord(h->ev0, s) != hipSuccess) return PMF_EDEVICE;
+        const int exit_tiles = (int)std::min<int64_t>(2 * (int64_t)h->opt.persist_tiles, INT32_MAX);
+        *h->pinned_params = P;
+        if (timing) h->pinned_params->kpx = h->kpx + 8;
+        if (hipMemcpyAsync(h->P_dev, h->pinned_params, sizeof(StepParams), hipMemcpyHostToDevice, s) != hipSuccess)
+            return PMF_EDEVICE;
+        if (launch_persist(h->P_dev, h->tw, kset, pgrid, budget, exit_tiles, s) == 0) {
+            if (hipEventRecord(h->ev1, s) != hipSuccess) return PMF_EDEVICE;
+            persisted = true;
+            h->stats.persist_launches += 1;
+        } else {
+            pgrid = 0;  // refused (e.g. not co-resident): supersteps as separate launches
+        }
+    }
+    if (P.ntiles > 0 && !persisted) {
         // replay a captured graph once the work list has been used once
-        const bool use_graph = h->opt.use_graph && !timing && h->epoch_steps > 0;
+        const bool use_graph = h->opt.use_graph && !timing && !h->ext && h->epoch_steps > 0;
         if (use_graph && (!h->graph || h->graph_S != steps)) {
             drop_graph(h);
             hipGraph_t g = nullptr;
@@ -483,15 +614,15 @@ int run_steps(pmf_handle *h, int steps, std::vector<int> *finished) {
             h->stats.work_launches += (int64_t)steps * ((P.t4_count > 0) + (P.t8_count > 0));
         } else {
             for (int i = 0; i < steps; ++i) {
-                const int ns = launch_superstep(P, h->tw, s, timing ? (void *const *)h->kev : nullptr,
+                StepParams Pi = P;
+                if (timing) {
+                    Pi.trace_lists = h->trace_lists + 4 * i;
+                    Pi.kpx = h->kpx;
+                }
+                const int ns = launch_superstep(Pi, h->tw, s, timing ? (void *const *)(h->kev.data() + 4 * i) : nullptr,
                                                 h->opt.timing == 2);
                 if (ns < 0) return PMF_EDEVICE;
                 h->stats.work_launches += ns;
-                if (timing && i + 1 < steps) {
-                    // the per-kernel events are reused: read them before the next superstep
-                    if (hipStreamSynchronize(s) != hipSuccess) return PMF_EDEVICE;
-                    read_kernel_events(h);
-                }
             }
         }
         if (hipEventRecord(h->ev1, s) != hipSuccess) return PMF_EDEVICE;
@@ -502,20 +633,49 @@ int run_steps(pmf_handle *h, int steps, std::vector<int> *finished) {
     // ring and every slot's state along with the completion count: one round
     // trip per sync instead of two and a copy per finished instance.
     const int cap = h->max_slots;
-    const bool bulk = h->batch && (size_t)cap * sizeof(InstState) <= ((size_t)1 << 20);
-    if (hipMemcpyAsync(h->pinned, P.ring_count, 4, hipMemcpyDeviceToHost, s) != hipSuccess) return PMF_EDEVICE;
-    if (bulk && (hipMemcpyAsync(h->pinned_ring, P.ring, 4 * (size_t)cap, hipMemcpyDeviceToHost, s) != hipSuccess ||
-                 hipMemcpyAsync(h->pinned_state, P.st, sizeof(InstState) * (size_t)cap, hipMemcpyDeviceToHost, s) !=
-                     hipSuccess))
+    const bool bulk = h->batch && !h->ext && (size_t)cap * sizeof(InstState) <= ((size_t)1 << 20);
+    int32_t *ringb = h->ext ? h->host_ring.data() : h->pinned_ring;
+    InstState *stateb = h->ext ? h->host_state.data() : h->pinned_state;
+    // device-to-host copy of polled data: queued on the stream into pinned
+    // memory, or (memory handed in: ordinary host memory) synchronous once
+    // the stream is idle
+    auto d2h = [&](void *dst, const void *src, size_t bytes) -> bool {
+        if (h->ext) return hipMemcpy(dst, src, bytes, hipMemcpyDeviceToHost) == hipSuccess;
+        return hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, s) == hipSuccess;
+    };
+    // the counter block: completions, list sizes of the last superstep, barrier words
+    if (hipMemcpyAsync(h->pinned, P.ring_count, 4 * (kBarSteps + 1), hipMemcpyDeviceToHost, s) != hipSuccess)
+        return PMF_EDEVICE;
+    if (bulk && (!d2h(ringb, P.ring, 4 * (size_t)cap) || !d2h(stateb, P.st, sizeof(InstState) * (size_t)cap)))
         return PMF_EDEVICE;
     if (hipStreamSynchronize(s) != hipSuccess) return PMF_EDEVICE;
     h->stats.host_syncs += 1;
     if (P.ntiles > 0) {
         float ms = 0.f;
-        if (hipEventElapsedTime(&ms, h->ev0, h->ev1) == hipSuccess) h->stats.device_ns += (int64_t)(ms * 1e6);
-        if (timing) read_kernel_events(h);
+        if (hipEventElapsedTime(&ms, h->ev0, h->ev1) == hipSuccess) {
+            h->stats.device_ns += (int64_t)(ms * 1e6);
+            if (persisted) h->stats.persist_ns += (int64_t)(ms * 1e6);
+        }
+        if (timing && !persisted) {
+            const int rc = read_kernel_events(h, steps);
+            if (rc != PMF_OK) return rc;
+        }
+        if (timing && hipMemcpy(h->stats.kernel_px, h->kpx, 16 * sizeof(int64_t), hipMemcpyDeviceToHost) != hipSuccess)
+            return PMF_EDEVICE;
     }
-    const int32_t count = *(volatile int32_t *)h->pinned;
+    const volatile int32_t *cb = h->pinned;
+    if (persisted) {
+        if (cb[kBarAbort] != 0) {
+            h->poisoned = true;  // a superstep was left half done
+            return PMF_EDEVICE;
+        }
+        const int ran = cb[kBarSteps];
+        h->stats.supersteps += ran;
+        h->stats.persist_supersteps += ran;
+        h->epoch_steps += ran;
+    }
+    if (P.ntiles > 0) h->last_listed = (int64_t)cb[8] + cb[9] + cb[10] + cb[11];
+    const int32_t count = cb[0];
     if (count <= h->ring_seen) return PMF_OK;
     // the new ring entries (at most two contiguous ranges), then the final
     // states of those instances (one bulk copy when many finished)
@@ -524,38 +684,29 @@ int run_steps(pmf_handle *h, int steps, std::vector<int> *finished) {
     if (!bulk) {
         const int a0 = h->ring_seen % cap;
         const int first_len = std::min(fresh, cap - a0);
-        if (hipMemcpyAsync(h->pinned_ring + a0, P.ring + a0, 4 * (size_t)first_len, hipMemcpyDeviceToHost, s) !=
-            hipSuccess)
-            return PMF_EDEVICE;
-        if (fresh > first_len &&
-            hipMemcpyAsync(h->pinned_ring, P.ring, 4 * (size_t)(fresh - first_len), hipMemcpyDeviceToHost, s) !=
-                hipSuccess)
-            return PMF_EDEVICE;
+        if (!d2h(ringb + a0, P.ring + a0, 4 * (size_t)first_len)) return PMF_EDEVICE;
+        if (fresh > first_len && !d2h(ringb, P.ring, 4 * (size_t)(fresh - first_len))) return PMF_EDEVICE;
         if (hipStreamSynchronize(s) != hipSuccess) return PMF_EDEVICE;
     }
     std::vector<int> got;
     for (int32_t c = h->ring_seen; c < count; ++c) {
-        const int id = h->pinned_ring[c % cap];
+        const int id = ringb[c % cap];
         if (id < 0 || id >= cap) return PMF_EDEVICE;
         got.push_back(id);
     }
     if (!bulk) {
         if (got.size() > 64) {
-            if (hipMemcpyAsync(h->pinned_state, P.st, sizeof(InstState) * (size_t)cap, hipMemcpyDeviceToHost, s) !=
-                hipSuccess)
-                return PMF_EDEVICE;
+            if (!d2h(stateb, P.st, sizeof(InstState) * (size_t)cap)) return PMF_EDEVICE;
         } else {
             for (int id : got)
-                if (hipMemcpyAsync(h->pinned_state + id, P.st + id, sizeof(InstState), hipMemcpyDeviceToHost, s) !=
-                    hipSuccess)
-                    return PMF_EDEVICE;
+                if (!d2h(stateb + id, P.st + id, sizeof(InstState))) return PMF_EDEVICE;
         }
         if (hipStreamSynchronize(s) != hipSuccess) return PMF_EDEVICE;
     }
     h->ring_seen = count;
     for (int id : got) {
         Slot &sl = h->slots[id];
-        const InstState &x = h->pinned_state[id];
+        const InstState &x = stateb[id];
         sl.finished = true;
         sl.done_k = x.k;
         h->stats.px_init += x.px_init;
@@ -565,6 +716,7 @@ int run_steps(pmf_handle *h, int steps, std::vector<int> *finished) {
         h->stats.px_orient += x.px_orient;
         h->stats.px_init_x += x.px_init_x;
         h->stats.px_cut_x += x.px_cut_x;
+        h->stats.gap_kills += x.gap_kills;
         h->stats.sweep_visits += x.sweeps;
         h->stats.global_relabels += x.relabels;
         h->stats.bfs_passes += x.passes;
@@ -645,14 +797,21 @@ int pmf_create(const pmf_options *opt, void *stream, void *workspace, size_t ws_
         h->arena_bytes = ws_bytes;
         h->own_arena = false;
     }
-    if (hipHostMalloc((void **)&h->pinned, 64, hipHostMallocDefault) != hipSuccess ||
+    if (hipHostMalloc((void **)&h->pinned, 256, hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void **)&h->pinned_params, sizeof(StepParams), hipHostMallocDefault) != hipSuccess ||
         hipStreamCreateWithFlags(&h->capture, hipStreamNonBlocking) != hipSuccess ||
-        hipEventCreate(&h->ev0) != hipSuccess || hipEventCreate(&h->ev1) != hipSuccess ||
-        hipEventCreate(&h->kev[0]) != hipSuccess || hipEventCreate(&h->kev[1]) != hipSuccess ||
-        hipEventCreate(&h->kev[2]) != hipSuccess || hipEventCreate(&h->kev[3]) != hipSuccess) {
+        hipEventCreate(&h->ev0) != hipSuccess || hipEventCreate(&h->ev1) != hipSuccess) {
         (void)hipGetLastError();
         pmf_destroy(h);
         return PMF_EDEVICE;
+    }
+    if (o.persist_tiles > 0) {
+        int cus = 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, h->device) != hipSuccess) cus = 0;
+        const int want = o.persist_wgs > 0 ? o.persist_wgs : cus;
+        const int ksets[3] = {4, 8, 12};
+        for (int i = 0; i < 3; ++i)
+            h->persist_grid[i] = (std::min(want, persist_workgroups(h->tw, ksets[i])) / 8) * 8;
     }
     *out = h;
     return PMF_OK;
@@ -682,7 +841,7 @@ int pmf_query_bytes(const pmf_instance *inst, int32_t n, const pmf_options *opt,
     size_t pool = 0;
     for (int i = 0; i < n; ++i) {
         if (check_instance(inst[i]) != PMF_OK) return PMF_EINVAL;
-        pool += block_layout(inst[i], tw, th).total;
+        pool += block_layout(inst[i], tw, th, o.gap != 0).total;
     }
     *bytes = pool;
     return PMF_OK;
@@ -693,7 +852,7 @@ int pmf_query_bytes(const pmf_instance *inst, int32_t n, const pmf_options *opt,
 namespace {
 
 // Bytes of the pool for a batch whose schedules are cut into chunks of C lambdas.
-size_t batch_pool_bytes(const pmf_instance *inst, int n, int C, int tw, int th, int64_t *n_sub) {
+size_t batch_pool_bytes(const pmf_instance *inst, int n, int C, int tw, int th, bool gap, int64_t *n_sub) {
     size_t pool = 0;
     int64_t subs = 0;
     for (int i = 0; i < n; ++i) {
@@ -701,11 +860,11 @@ size_t batch_pool_bytes(const pmf_instance *inst, int n, int C, int tw, int th, 
         const int full = I.L / C, rest = I.L % C;
         if (full) {
             I.L = C;
-            pool += (size_t)full * block_layout(I, tw, th).total;
+            pool += (size_t)full * block_layout(I, tw, th, gap).total;
         }
         if (rest) {
             I.L = rest;
-            pool += block_layout(I, tw, th).total;
+            pool += block_layout(I, tw, th, gap).total;
         }
         subs += full + (rest ? 1 : 0);
     }
@@ -749,12 +908,14 @@ int longest_parallel_chunk(pmf_handle *h, const pmf_instance *inst, int n, int C
     return C;
 }
 
-int choose_chunk(pmf_handle *h, const pmf_instance *inst, int n) {
+int choose_chunk(pmf_handle *h, const pmf_instance *inst, int n, size_t ext_bytes) {
     int maxL = 1;
     for (int i = 0; i < n; ++i) maxL = std::max(maxL, (int)inst[i].L);
     if (h->opt.lambda_chunk > 0) return std::min((int)h->opt.lambda_chunk, maxL);
     size_t budget;
-    if (!h->own_arena) {
+    if (ext_bytes) {
+        budget = ext_bytes;
+    } else if (!h->own_arena) {
         budget = h->arena_bytes;
     } else if (h->opt.mem_budget > 0) {
         budget = (size_t)h->opt.mem_budget;
@@ -766,7 +927,7 @@ int choose_chunk(pmf_handle *h, const pmf_instance *inst, int n) {
     for (int C = 1;; C = C < 4 ? C + 1 : C * 2) {
         if (C >= maxL) return maxL;
         int64_t subs = 0;
-        const size_t pool = batch_pool_bytes(inst, n, C, h->tw, h->th, &subs);
+        const size_t pool = batch_pool_bytes(inst, n, C, h->tw, h->th, h->opt.gap != 0, &subs);
         if (subs <= (1 << 20) && pool + control_bytes((int)subs, worklist_cap((int)subs, pool)) <= budget)
             return longest_parallel_chunk(h, inst, n, C, maxL);
     }
@@ -792,15 +953,21 @@ int locate(pmf_handle *h, int32_t inst, int32_t lambda_idx, int *slot, int *k) {
 
 extern "C" {
 
-int pmf_solve_batch(pmf_handle *h, const pmf_instance *inst, int32_t n_inst, int64_t *flows_out,
-                    int32_t *status_out) {
+}  // extern "C"
+
+namespace {
+
+// pmf_solve_batch, with its state in the arena or in ext_bytes of device
+// memory at ext_base (a solve that allocates nothing).
+int solve_batch(pmf_handle *h, const pmf_instance *inst, int32_t n_inst, int64_t *flows_out, int32_t *status_out,
+                char *ext_base = nullptr, size_t ext_bytes = 0) {
     if (!h || n_inst < 0 || (n_inst > 0 && (!inst || !flows_out))) return PMF_EINVAL;
     int rc = pmf_check_instances(inst, n_inst, nullptr);
     if (rc != PMF_OK) return rc;
-    const int C = n_inst ? choose_chunk(h, inst, n_inst) : 1;
+    const int C = n_inst ? choose_chunk(h, inst, n_inst, ext_base ? ext_bytes : 0) : 1;
     int64_t n_sub = 0;
-    const size_t pool = batch_pool_bytes(inst, n_inst, C, h->tw, h->th, &n_sub);
-    rc = open_session(h, (int)std::max<int64_t>(n_sub, 1), pool);
+    const size_t pool = batch_pool_bytes(inst, n_inst, C, h->tw, h->th, h->opt.gap != 0, &n_sub);
+    rc = open_session(h, (int)std::max<int64_t>(n_sub, 1), pool, ext_base, ext_bytes);
     if (rc != PMF_OK) return rc;
     h->batch = true;
     h->chunk = C;
@@ -833,7 +1000,7 @@ int pmf_solve_batch(pmf_handle *h, const pmf_instance *inst, int32_t n_inst, int
     size_t moff = 0;
     const size_t mbytes = align_up(8 * meta.size()) + align_up(4 * subs.size());
     if (!h->pool.alloc(mbytes, &moff)) return PMF_ENOMEM;
-    char *mbase = h->arena + h->pool_base + moff;
+    char *mbase = h->base + h->pool_base + moff;
     int64_t *d_meta = (int64_t *)mbase;
     int32_t *d_sub_status = (int32_t *)(mbase + align_up(8 * meta.size()));
     if (hipMemcpyAsync(d_meta, meta.data(), 8 * meta.size(), hipMemcpyHostToDevice, h->stream) != hipSuccess)
@@ -842,14 +1009,14 @@ int pmf_solve_batch(pmf_handle *h, const pmf_instance *inst, int32_t n_inst, int
     if (rc != PMF_OK) return rc == PMF_EBUSY ? PMF_ENOMEM : rc;
     // The work list keeps finished instances (their tiles exit at once), so
     // one captured superstep graph serves the whole solve.
-    const int S = h->opt.timing ? 1 : h->opt.steps_per_sync;
+    const int S = h->opt.steps_per_sync;
     const int64_t max_rounds = h->opt.max_supersteps / S + 4;
     int64_t done = 0;
     std::vector<int> fin;
     for (int64_t round = 0; done < (int64_t)subs.size(); ++round) {
         if (round > max_rounds) return PMF_ETIMEOUT;
         fin.clear();
-        rc = run_steps(h, S, &fin);
+        rc = run_steps(h, S, &fin, 1 << 16);
         if (rc != PMF_OK) return rc;
         done += (int64_t)fin.size();
         h->wl_dirty = false;
@@ -859,8 +1026,54 @@ int pmf_solve_batch(pmf_handle *h, const pmf_instance *inst, int32_t n_inst, int
     return PMF_OK;
 }
 
+}  // namespace
+
+extern "C" {
+
+int pmf_solve_batch(pmf_handle *h, const pmf_instance *inst, int32_t n_inst, int64_t *flows_out,
+                    int32_t *status_out) {
+    if (!h) return PMF_EINVAL;
+    (void)finish_async(h);
+    return solve_batch(h, inst, n_inst, flows_out, status_out);
+}
+
+int pmf_solve_batch_async(pmf_handle *h, const pmf_instance *inst, int32_t n_inst, int64_t *flows_out,
+                          int32_t *status_out) {
+    if (!h) return PMF_EINVAL;
+    (void)finish_async(h);
+    if (n_inst < 0 || (n_inst > 0 && (!inst || !flows_out))) return PMF_EINVAL;
+    const int rc = pmf_check_instances(inst, n_inst, nullptr);
+    if (rc != PMF_OK) return rc;
+    h->async_inst.assign(inst, inst + n_inst);
+    h->async_done.store(0);
+    try {
+        h->worker = std::thread([h, n_inst, flows_out, status_out]() {
+            int r = hipSetDevice(h->device) == hipSuccess ? PMF_OK : PMF_EDEVICE;
+            if (r == PMF_OK) r = solve_batch(h, h->async_inst.data(), n_inst, flows_out, status_out);
+            h->async_rc = r;
+            h->async_done.store(1);
+        });
+    } catch (...) {
+        h->async_done.store(1);
+        return PMF_EDEVICE;
+    }
+    return PMF_OK;
+}
+
+int pmf_wait(pmf_handle *h) {
+    if (!h) return PMF_EINVAL;
+    return finish_async(h);
+}
+
+int pmf_query_done(pmf_handle *h, int32_t *done) {
+    if (!h || !done) return PMF_EINVAL;
+    *done = h->async_done.load();
+    return PMF_OK;
+}
+
 int pmf_extract_cut(pmf_handle *h, int32_t inst, int32_t lambda_idx, uint8_t *mask_out) {
     if (!h || !mask_out) return PMF_EINVAL;
+    (void)finish_async(h);
     if (!h->open) return PMF_ENOTSOLVED;
     int slot, k;
     const int rc = locate(h, inst, lambda_idx, &slot, &k);
@@ -868,13 +1081,14 @@ int pmf_extract_cut(pmf_handle *h, int32_t inst, int32_t lambda_idx, uint8_t *ma
     const Slot &s = h->slots[slot];
     if (!s.live || !s.finished || s.done_k <= k) return PMF_ENOTSOLVED;
     const size_t px = (size_t)s.W * s.H;
-    const char *src = h->arena + s.masks + (size_t)k * px;
+    const char *src = h->base + s.masks + (size_t)k * px;
     if (hipMemcpyAsync(mask_out, src, px, hipMemcpyDeviceToDevice, h->stream) != hipSuccess) return PMF_EDEVICE;
     return PMF_OK;
 }
 
 int pmf_extract_levels(pmf_handle *h, int32_t inst, uint8_t *levels_out) {
     if (!h || !levels_out) return PMF_EINVAL;
+    (void)finish_async(h);
     if (!h->open) return PMF_ENOTSOLVED;
     int first, last;
     if (h->batch) {
@@ -895,7 +1109,7 @@ int pmf_extract_levels(pmf_handle *h, int32_t inst, uint8_t *levels_out) {
     // every chunk adds the lambdas it holds (the sets are nested across chunks too)
     for (int sl = first; sl < last; ++sl) {
         const Slot &s = h->slots[sl];
-        const uint8_t *masks = (const uint8_t *)(h->arena + s.masks);
+        const uint8_t *masks = (const uint8_t *)(h->base + s.masks);
         if (launch_levels(masks, s.L, s.W * s.H, levels_out, sl > first, h->stream) != 0) return PMF_EDEVICE;
     }
     return PMF_OK;
@@ -903,6 +1117,7 @@ int pmf_extract_levels(pmf_handle *h, int32_t inst, uint8_t *levels_out) {
 
 int pmf_session_open(pmf_handle *h, int32_t max_slots, size_t pool_bytes) {
     if (!h || max_slots < 1) return PMF_EINVAL;
+    (void)finish_async(h);
     h->batch = false;
     if (pool_bytes == 0) {
         size_t avail = 0;
@@ -928,6 +1143,7 @@ int pmf_session_open(pmf_handle *h, int32_t max_slots, size_t pool_bytes) {
 int pmf_session_submit(pmf_handle *h, const pmf_instance *inst, int32_t n_inst, int64_t *flows_out,
                        int32_t *status_out, int32_t *ids_out) {
     if (!h) return PMF_EINVAL;
+    (void)finish_async(h);
     return submit(h, inst, n_inst, flows_out, status_out, ids_out);
 }
 
@@ -935,6 +1151,7 @@ int pmf_session_step(pmf_handle *h, int32_t supersteps, int32_t *done_ids, int32
     if (!h || supersteps < 1 || supersteps > (1 << 16) || max_ids < 0 || (max_ids > 0 && !done_ids))
         return PMF_EINVAL;
     if (n_done) *n_done = 0;
+    (void)finish_async(h);
     if (!h->open) return PMF_EINVAL;
     std::vector<int> fin;
     const int rc = run_steps(h, supersteps, &fin);
@@ -946,7 +1163,9 @@ int pmf_session_step(pmf_handle *h, int32_t supersteps, int32_t *done_ids, int32
 }
 
 int pmf_session_release(pmf_handle *h, int32_t id) {
-    if (!h || !h->open) return PMF_EINVAL;
+    if (!h) return PMF_EINVAL;
+    (void)finish_async(h);
+    if (!h->open) return PMF_EINVAL;
     if (id < 0 || id >= h->max_slots || !h->slots[id].live) return PMF_ERANGE;
     Slot &s = h->slots[id];
     if (!s.finished) {
@@ -967,6 +1186,7 @@ int pmf_session_release(pmf_handle *h, int32_t id) {
 
 int pmf_session_query(pmf_handle *h, pmf_session_info *out) {
     if (!h || !out) return PMF_EINVAL;
+    (void)finish_async(h);
     std::memset(out, 0, sizeof(*out));
     if (!h->open) return PMF_OK;
     out->free_bytes = (int64_t)h->pool.free_bytes();
@@ -981,6 +1201,7 @@ int pmf_session_query(pmf_handle *h, pmf_session_info *out) {
 
 int pmf_slot_stats(pmf_handle *h, int64_t *out, int32_t max_slots, int32_t *n_slots) {
     if (!h || max_slots < 0 || (max_slots > 0 && !out)) return PMF_EINVAL;
+    (void)finish_async(h);
     const int n = h->open ? h->max_slots : 0;
     if (n_slots) *n_slots = n;
     for (int i = 0; i < std::min(n, (int)max_slots); ++i) {
@@ -988,7 +1209,7 @@ int pmf_slot_stats(pmf_handle *h, int64_t *out, int32_t max_slots, int32_t *n_sl
         const Slot &s = h->slots[i];
         std::memset(o, 0, 8 * sizeof(int64_t));
         if (!s.live || !s.finished) continue;
-        const InstState &x = h->pinned_state[i];
+        const InstState &x = h->ext ? h->host_state[i] : h->pinned_state[i];
         o[0] = 1;
         o[1] = x.steps;
         o[2] = x.sweeps;
@@ -1003,12 +1224,14 @@ int pmf_slot_stats(pmf_handle *h, int64_t *out, int32_t max_slots, int32_t *n_sl
 
 int pmf_get_stats(pmf_handle *h, pmf_stats *out) {
     if (!h || !out) return PMF_EINVAL;
+    (void)finish_async(h);
     *out = h->stats;
     return PMF_OK;
 }
 
 int64_t pmf_get_trace(pmf_handle *h, int64_t *out, int64_t max_rows) {
     if (!h || max_rows < 0 || (max_rows > 0 && !out)) return -(int64_t)PMF_EINVAL;
+    (void)finish_async(h);
     const int64_t rows = (int64_t)h->trace.size() / PMF_TRACE_COLS;
     const int64_t n = std::min(rows, max_rows);
     if (n > 0) std::copy(h->trace.begin(), h->trace.begin() + n * PMF_TRACE_COLS, out);
@@ -1019,58 +1242,70 @@ int pmf_parametric(pmf_handle *h, const pmf_instance *inst, int32_t lam_lo, int3
                    int64_t *f_out, int32_t max_bp, int32_t *n_bp, int32_t *exit_out) {
     if (!h || !inst || !n_bp || max_bp < 0 || (max_bp > 0 && !bp_out) || lam_lo < 0 || lam_hi < lam_lo)
         return PMF_EINVAL;
+    (void)finish_async(h);
+    if (lam_hi == INT32_MAX) return PMF_EINVAL;  // lam_hi + 1 marks pixels that never leave
     *n_bp = 0;
     pmf_instance base = *inst;
     base.L = 1;
     base.lambdas = nullptr;
+    {
+        pmf_instance chk = base;  // the schedule is made here: only its pointer's presence is checked
+        chk.lambdas = &lam_lo;
+        if (check_instance(chk) != PMF_OK) return PMF_EINVAL;
+    }
     const int n = base.W * base.H;
-    // every solved lambda: its flow, |S_min| and slope sum w(S_min), and its
-    // mask (kept on the device for the exit map)
+    // every solved lambda: its flow, |S_min| and slope sum w(S_min)
     struct Point {
         int64_t F = 0, size = 0, w = 0;
-        const uint8_t *mask = nullptr;
     };
     std::map<int32_t, Point> pts;
-    std::vector<void *> owned;  // device allocations of this call
+    // the exit map is a running minimum over the solved lambdas: the smallest
+    // solved lambda whose set lacks the pixel (every change point is solved,
+    // and the set is constant between change points, so it is exact)
+    if (exit_out && launch_fill_i32(exit_out, n, lam_hi + 1, h->stream) != 0) return PMF_EDEVICE;
     auto release = [&]() {
         (void)hipStreamSynchronize(h->stream);
-        for (void *p : owned) (void)hipFree(p);
-        owned.clear();
+        h->reserve_tail = 0;
     };
-    auto dalloc = [&](size_t bytes) -> void * {
-        void *p = nullptr;
-        if (hipMalloc(&p, std::max<size_t>(bytes, 4)) != hipSuccess) {
-            (void)hipGetLastError();
-            return nullptr;
-        }
-        owned.push_back(p);
-        return p;
-    };
-    // solve the lambdas of `lams` (one instance each, one batched call)
+    // Solve the (ascending, distinct) lambdas of `lams` as the schedule of one
+    // instance: the batched call splits it into warm-started chunks solved in
+    // parallel.  The round's own device data (lambdas, flows, status, mask
+    // statistics, one mask) sit at the end of the handle's arena, which is
+    // first grown to hold them next to the largest layout the call can pick
+    // (every lambda a chunk of its own), so that the call never moves it.
     auto solve = [&](const std::vector<int32_t> &lams) -> int {
         const int m = (int)lams.size();
-        int32_t *dl = (int32_t *)dalloc(4 * (size_t)m);
-        int64_t *df = (int64_t *)dalloc(8 * (size_t)m);
-        int32_t *ds = (int32_t *)dalloc(4 * (size_t)m);
-        int64_t *dst = (int64_t *)dalloc(16 * (size_t)m);
-        uint8_t *dm = (uint8_t *)dalloc((size_t)m * n);
-        if (!dl || !df || !ds || !dst || !dm) return PMF_ENOMEM;
+        const size_t o_f = align_up(4 * (size_t)m), o_s = o_f + align_up(8 * (size_t)m), o_st = o_s + align_up(4),
+                     o_m = o_st + align_up(16 * (size_t)m), T = o_m + align_up((size_t)n);
+        pmf_instance I = base;
+        I.L = m;
+        int64_t subs = 0;
+        const size_t pool1 = batch_pool_bytes(&I, 1, 1, h->tw, h->th, h->opt.gap != 0, &subs);
+        const size_t need = control_bytes((int)subs, worklist_cap((int)subs, pool1)) + pool1;
+        h->reserve_tail = 0;
+        int rc = ensure_arena(h, need + T);
+        if (rc != PMF_OK) return rc;
+        h->reserve_tail = T;
+        char *tail = h->arena + h->arena_bytes - T;
+        int32_t *dl = (int32_t *)tail;
+        int64_t *df = (int64_t *)(tail + o_f);
+        int32_t *ds = (int32_t *)(tail + o_s);
+        int64_t *dst = (int64_t *)(tail + o_st);
+        uint8_t *dm = (uint8_t *)(tail + o_m);
         if (hipMemcpyAsync(dl, lams.data(), 4 * (size_t)m, hipMemcpyHostToDevice, h->stream) != hipSuccess ||
             hipMemsetAsync(dst, 0, 16 * (size_t)m, h->stream) != hipSuccess)
             return PMF_EDEVICE;
-        std::vector<pmf_instance> I(m, base);
-        for (int i = 0; i < m; ++i) I[i].lambdas = dl + i;
-        int rc = pmf_solve_batch(h, I.data(), m, df, ds);
+        I.lambdas = dl;
+        rc = pmf_solve_batch(h, &I, 1, df, ds);
         if (rc != PMF_OK) return rc;
-        std::vector<int32_t> st(m);
-        if (hipMemcpy(st.data(), ds, 4 * (size_t)m, hipMemcpyDeviceToHost) != hipSuccess) return PMF_EDEVICE;
-        for (int i = 0; i < m; ++i)
-            if (st[i] != PMF_OK) return st[i];
+        int32_t st = PMF_OK;
+        if (hipMemcpy(&st, ds, 4, hipMemcpyDeviceToHost) != hipSuccess) return PMF_EDEVICE;
+        if (st != PMF_OK) return st;
         for (int i = 0; i < m; ++i) {
-            rc = pmf_extract_cut(h, i, 0, dm + (size_t)i * n);
+            rc = pmf_extract_cut(h, 0, i, dm);
             if (rc != PMF_OK) return rc;
-            if (launch_mask_stats(dm + (size_t)i * n, n, base.snk_slope, base.seed, dst + 2 * i, h->stream) != 0)
-                return PMF_EDEVICE;
+            if (launch_mask_stats(dm, n, base.snk_slope, base.seed, dst + 2 * i, h->stream) != 0) return PMF_EDEVICE;
+            if (exit_out && launch_exit_min(dm, n, lams[i], exit_out, h->stream) != 0) return PMF_EDEVICE;
         }
         std::vector<int64_t> f(m), sw(2 * (size_t)m);
         if (hipMemcpyAsync(f.data(), df, 8 * (size_t)m, hipMemcpyDeviceToHost, h->stream) != hipSuccess ||
@@ -1082,7 +1317,6 @@ int pmf_parametric(pmf_handle *h, const pmf_instance *inst, int32_t lam_lo, int3
             q.F = f[i];
             q.size = sw[2 * i];
             q.w = sw[2 * i + 1];
-            q.mask = dm + (size_t)i * n;
         }
         return PMF_OK;
     };
@@ -1150,42 +1384,18 @@ int pmf_parametric(pmf_handle *h, const pmf_instance *inst, int32_t lam_lo, int3
         f_out[0] = pts[lam_lo].F;
         for (int i = 0; i < (int)changes.size() && i < max_bp; ++i) f_out[i + 1] = pts[changes[i]].F;
     }
-    if (exit_out) {
-        // masks in ascending lambda order, gathered into one buffer
-        const int m = (int)pts.size();
-        uint8_t *all = (uint8_t *)dalloc((size_t)m * n);
-        int32_t *dl = (int32_t *)dalloc(4 * (size_t)m);
-        if (!all || !dl) {
-            release();
-            return PMF_ENOMEM;
-        }
-        std::vector<int32_t> lams;
-        int i = 0;
-        for (const auto &kv : pts) {
-            lams.push_back(kv.first);
-            if (hipMemcpyAsync(all + (size_t)i * n, kv.second.mask, n, hipMemcpyDeviceToDevice, h->stream) !=
-                hipSuccess) {
-                release();
-                return PMF_EDEVICE;
-            }
-            ++i;
-        }
-        if (hipMemcpyAsync(dl, lams.data(), 4 * (size_t)m, hipMemcpyHostToDevice, h->stream) != hipSuccess ||
-            launch_exit_lambda(all, dl, m, n, lam_hi + 1, exit_out, h->stream) != 0) {
-            release();
-            return PMF_EDEVICE;
-        }
-    }
     release();
     return (int)changes.size() > max_bp ? PMF_ERANGE : PMF_OK;
 }
 
 int pmf_destroy(pmf_handle *h) {
     if (!h) return PMF_EINVAL;
+    (void)finish_async(h);
     (void)hipStreamSynchronize(h->stream);
     drop_graph(h);
     if (h->own_arena && h->arena) (void)hipFree(h->arena);
     if (h->pinned) (void)hipHostFree(h->pinned);
+    if (h->pinned_params) (void)hipHostFree(h->pinned_params);
     if (h->pinned_ring) (void)hipHostFree(h->pinned_ring);
     if (h->pinned_state) (void)hipHostFree(h->pinned_state);
     if (h->capture) (void)hipStreamDestroy(h->capture);
@@ -1193,6 +1403,8 @@ int pmf_destroy(pmf_handle *h) {
     if (h->ev1) (void)hipEventDestroy(h->ev1);
     for (hipEvent_t e : h->kev)
         if (e) (void)hipEventDestroy(e);
+    if (h->trace_lists) (void)hipFree(h->trace_lists);
+    if (h->kpx) (void)hipFree(h->kpx);
     delete h;
     return PMF_OK;
 }

@@ -11,6 +11,8 @@
 //                        tile) pair
 //   rmask  uint16 [n]    bit k: r_k > 0, bit 8: rt > 0, bit 9: e > 0
 //   masks  uint8 [L][n]  minimal source side for every lambda
+//   hist   int32 [ntiles * TW * TH]  (gap heuristic only) number of pixels
+//                        whose stored label is each value below the size
 // All pixel planes are row-major with pitch W, 256-byte aligned.
 #pragma once
 
@@ -74,6 +76,9 @@ struct alignas(16) InstDesc {
     uint32_t *tile_act;  // [ntiles] bit 0: active pixels, bit 1: inbox pending
     uint8_t *tile_chg;   // [2][ntiles] a label changed in the pass of that parity
     int32_t *tile_cnt;   // [ntiles] active pixels under the current labels
+    int32_t *hist;       // gap heuristic: pixels per label value (null when off)
+    int32_t hsize;       // entries of hist (ntiles * TW * TH); larger labels are not counted
+    int32_t pad2;
 };
 
 struct alignas(16) InstState {
@@ -96,6 +101,9 @@ struct alignas(16) InstState {
     int32_t listed;   // the last compaction listed a tile of this instance to sweep
     int64_t sum_raise;  // exchanged instances: source capacity added for the next lambda
     int64_t px_orient, px_init_x, px_cut_x;  // pixel visits: orientation count, exchanged init and cut
+    int32_t gap;      // gap heuristic: lowest label level found empty since the last relabel (kHInf: none)
+    int32_t hist1;    // gap heuristic: pixels labelled 1 by the first pass of the current relabel
+    int64_t gap_kills;  // pixels found above an empty level by the sweeps (statistics)
 };
 
 struct StepParams {
@@ -122,8 +130,14 @@ struct StepParams {
     int32_t tail_exchange_rounds;
     int32_t relabel_passes;     // cap on the passes of a relabel that leaves active pixels (0 = none)
     int32_t orientation;        // Orientation policy
+    int32_t gap;                // 1: gap heuristic (every descriptor then has a hist array)
     int64_t max_steps;
+    int32_t *trace_lists;       // timing mode: the control kernel copies the 4 list sizes here (may be null)
+    int64_t *kpx;               // timing mode: pixel visits of this launch's tile work by kind (may be null)
 };
+
+// Kinds of tile work (index into StepParams::kpx and pmf_stats::kernel_px).
+enum PxKind : int { kPxSweep = 0, kPxRelabel, kPxCut, kPxInit, kPxOrient, kPxInitX, kPxCutX, kPxKinds };
 
 // Enqueue one superstep (compaction, tile work and control kernels) over
 // every tile (defined in pmf_kernels.hip).  The sweeps and the relabel / cut
@@ -139,6 +153,21 @@ int launch_superstep(const StepParams &p, int tile_w, void *stream, void *const 
 // holds at once (0 if the runtime cannot tell).
 int resident_workgroups(int K, int tile_w);
 
+// Persistent supersteps (one cooperative launch of `grid` workgroups, a
+// multiple of 8 no larger than persist_workgroups(), reading the parameters
+// from a device copy p_dev): up to max_steps
+// supersteps, leaving early when no instance of the work list is running or
+// when a superstep listed more than exit_tiles tiles.  The counter block
+// after the list counters holds the barrier words: [16] arrivals, [17]
+// generation, [18] abort (a barrier wait gave up: the state is not usable),
+// [19] supersteps run.  Returns 0, or -1 if the launch was refused.
+// kset: 4 or 8 when every instance of the work list has that connectivity,
+// 12 for a mixed list.  Not for the gap heuristic.
+constexpr int kBarAbort = 18, kBarSteps = 19;
+int persist_workgroups(int tile_w, int kset);
+int launch_persist(const StepParams *p_dev, int tile_w, int kset, int grid, int max_steps, int exit_tiles,
+                   void *stream);
+
 // out[p] (+)= number of the L masks that hold pixel p (n pixels).
 int launch_levels(const uint8_t *masks, int L, int n, uint8_t *out, bool accumulate, void *stream);
 
@@ -151,9 +180,9 @@ int launch_levels(const uint8_t *masks, int L, int n, uint8_t *out, bool accumul
 int launch_mask_stats(const uint8_t *mask, int n, const int32_t *slope, const uint8_t *seed, int64_t *out,
                       void *stream);
 
-// out[p] = first lams[i] (ascending) whose mask i lacks pixel p, else `none`.
-int launch_exit_lambda(const uint8_t *masks, const int32_t *lams, int m, int n, int32_t none, int32_t *out,
-                       void *stream);
+// out[p] = min(out[p], lam) where mask[p] == 0 (n pixels); out[p] = v.
+int launch_exit_min(const uint8_t *mask, int n, int32_t lam, int32_t *out, void *stream);
+int launch_fill_i32(int32_t *out, int n, int32_t v, void *stream);
 
 int launch_finalize(const int32_t *sub_status, const int64_t *meta, int n_user, int64_t *flows,
                     int32_t *status_out, void *stream);

@@ -137,6 +137,13 @@ __device__ __forceinline__ void count_px(int64_t *ctr, long long v) {
     atomicAdd((unsigned long long *)ctr, (unsigned long long)v);
 }
 
+// Pixel visits of one tile pass: into the instance's counter and, in timing
+// mode, into the launch's counter of that kind of work.
+__device__ __forceinline__ void count_visit(const StepParams &P, int64_t *ctr, int kind, long long v) {
+    count_px(ctr, v);
+    if (P.kpx) count_px(&P.kpx[kind], v);
+}
+
 // Block-wide count of set flags by wave ballots: each wave adds the popcount
 // of its ballots once (returned to every thread).
 template <int N>
@@ -220,7 +227,7 @@ __device__ void orient_tile(const StepParams &P, const InstDesc &D, InstState *S
     if (tid == 0) {
         if (np) atomicAdd(&S->cnt_pos, np);
         if (nn) atomicAdd(&S->cnt_neg, nn);
-        count_px(&S->px_orient, tile_pixels<TW, TH>(W, H, x0, y0));
+        count_visit(P, &S->px_orient, kPxOrient, tile_pixels<TW, TH>(W, H, x0, y0));
     }
     (void)P;
 }
@@ -297,7 +304,8 @@ __device__ void init_tile(const StepParams &P, const InstDesc &D, InstState *S, 
     const long long tot = block_sum_i64(scs, s_sum);
     if (tid == 0) {
         if (tot) atomicAdd((unsigned long long *)&S->sum_cs, (unsigned long long)tot);
-        count_px(swap ? &S->px_init_x : &S->px_init, tile_pixels<TW, TH>(W, H, x0, y0));
+        count_visit(P, swap ? &S->px_init_x : &S->px_init, swap ? kPxInitX : kPxInit,
+                    tile_pixels<TW, TH>(W, H, x0, y0));
         gp(D.tile_act)[tl] = 0;
         gp(D.tile_cnt)[tl] = 0;
         gp(D.tile_chg)[tl] = 1;
@@ -326,7 +334,7 @@ __device__ void init_tile(const StepParams &P, const InstDesc &D, InstState *S, 
 // tile) lands in the halo cell's word of the reverse arc, i.e. exactly the
 // amount handed over; those words go to the neighbours' inboxes at the end.
 // ---------------------------------------------------------------------------
-template <int K, int TW, int TH>
+template <int K, int TW, int TH, bool GAP>
 __device__ void sweep_tile(const StepParams &P, const InstDesc &D, InstState *S, int tl,
                            int iters, int32_t *lds, int *s_red) {
     using G = Geo<TW, TH>;
@@ -363,6 +371,15 @@ __device__ void sweep_tile(const StepParams &P, const InstDesc &D, InstState *S,
         rt[j] = gp(D.rt)[p];
         h[j] = gp(D.h)[p];
     }
+    // Gap heuristic: no pixel is labelled `gap` (a level that emptied since
+    // the last global relabel), so no pixel labelled above it has a residual
+    // path to t while the labels are valid; such pixels stop being active
+    // until the next global relabel.  Labels of other tiles may be stale, so
+    // this can also stop a pixel that could still reach t: that only delays
+    // it (the exact relabel that certifies termination looks at every pixel).
+    const int gap = GAP ? __builtin_amdgcn_readfirstlane(
+                                __hip_atomic_load(&S->gap, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+                          : kHInf;
     static_assert(G::RING <= kThreads, "one halo cell per thread");
     int hx, hy;
     G::ring(min(tid, G::RING - 1), hx, hy);
@@ -383,7 +400,7 @@ __device__ void sweep_tile(const StepParams &P, const InstDesc &D, InstState *S,
         if (ibv[q]) ibv[q] = g_exch(&inbox[i], 0);
     }
     if (tid < G::RING) {
-        sh_h[hc] = hin ? hv : kHInf;
+        sh_h[hc] = hin && hv <= gap ? hv : kHInf;
 #pragma unroll
         for (int k = 0; k < K; ++k) sh_r[hc * K + k] = 0;  // hand-over words
     }
@@ -394,7 +411,7 @@ __device__ void sweep_tile(const StepParams &P, const InstDesc &D, InstState *S,
         sh_t[c] = valid[j] ? rt[j] : 0;
 #pragma unroll
         for (int k = 0; k < K; ++k) sh_r[c * K + k] = valid[j] ? r[j][k] : 0;
-        sh_h[c] = valid[j] ? h[j] : kHInf;
+        sh_h[c] = valid[j] && h[j] <= gap ? h[j] : kHInf;
     }
     __syncthreads();
 #pragma unroll
@@ -490,15 +507,31 @@ __device__ void sweep_tile(const StepParams &P, const InstDesc &D, InstState *S,
 
     // write back
     int active = 0;
+    bool killed[PPT];
 #pragma unroll
     for (int j = 0; j < PPT; ++j) {
+        killed[j] = false;
         if (!valid[j]) continue;
         const int ly = ly0 + j * RPI;
         const int p = (y0 + ly) * W + x0 + lx;
         const int c = (ly + 1) * HW + lx + 1;
+        const int h0 = h[j];
         const int e = sh_e[c];
         const int h = sh_h[c];
         active |= e > 0 && h < kHInf;
+        if (GAP) {
+            // the label histogram follows every stored label below the gap;
+            // the level a pixel leaves may empty: a gap below the current one
+            killed[j] = h0 > gap && h0 < kHInf;
+            if (h0 <= gap && h != h0) {
+                if (h0 < D.hsize) {
+                    const int was = __hip_atomic_fetch_add(&gp(D.hist)[h0], -1, __ATOMIC_RELAXED,
+                                                           __HIP_MEMORY_SCOPE_AGENT);
+                    if (was == 1) atomicMin(&S->gap, h0);
+                }
+                if (h < D.hsize) g_add(&gp(D.hist)[h], 1);
+            }
+        }
         const int rt = sh_t[c];
         int rm = (rt > 0 ? kRtBit : 0) | (e > 0 ? kEBit : 0);
 #pragma unroll
@@ -542,12 +575,14 @@ __device__ void sweep_tile(const StepParams &P, const InstDesc &D, InstState *S,
         if (ntx >= 0 && ntx < D.tiles_x && nty >= 0 && nty < D.tiles_y)
             g_or(&gp(D.tile_act)[nty * D.tiles_x + ntx], 2u);
     }
+    const int nkill = GAP ? block_count_ballot(killed, s_red) : 0;
     if (tid == 0) {
         if (tile_active)
             g_or(&gp(D.tile_act)[tl], 1u);
         else
             g_and(&gp(D.tile_act)[tl], ~1u);
-        count_px(&S->px_sweep, tile_pixels<TW, TH>(W, H, x0, y0));
+        count_visit(P, &S->px_sweep, kPxSweep, tile_pixels<TW, TH>(W, H, x0, y0));
+        if (nkill) count_px(&S->gap_kills, nkill);
     }
 }
 
@@ -569,7 +604,7 @@ __device__ __forceinline__ bool frontier_needs(const InstDesc &D, int tx, int ty
 // ---------------------------------------------------------------------------
 // kRelabel: one pass of the exact global relabel (distance to t).
 // ---------------------------------------------------------------------------
-template <int K, int TW, int TH>
+template <int K, int TW, int TH, bool GAP>
 __device__ void relabel_tile(const StepParams &P, const InstDesc &D, InstState *S, int tl,
                              int sub, int xrounds, int32_t *lds, int *s_red) {
     using G = Geo<TW, TH>;
@@ -729,15 +764,29 @@ __device__ void relabel_tile(const StepParams &P, const InstDesc &D, InstState *
     if (!__syncthreads_or(got)) break;
     }
     int changed = first ? 1 : 0;
-    bool act[PPT];
+    bool act[PPT], one[PPT];
 #pragma unroll
     for (int j = 0; j < PPT; ++j) {
         const int ly = ly0 + j * RPI;
         const int gx = x0 + lx, gy = y0 + ly;
         act[j] = (rm[j] & kEBit) && d[j] < kHInf;  // rm = 0 outside the image
+        one[j] = first && d[j] == 1;
         if (gx >= W || gy >= H) continue;
         if (first || d[j] != d0[j]) changed = 1;
         if (first || d[j] != dpub[j]) gp(D.h)[gy * W + gx] = d[j];
+        // gap heuristic: the label histogram follows every change after the
+        // first pass (which sets every label to 1 or H_INF and clears it)
+        if (GAP && !first && d[j] != d0[j]) {
+            if (d0[j] < D.hsize) g_add(&gp(D.hist)[d0[j]], -1);
+            if (d[j] < D.hsize) g_add(&gp(D.hist)[d[j]], 1);
+        }
+    }
+    if (GAP && first) {
+        // this tile's share of the histogram starts at zero; the count of
+        // label-1 pixels goes to hist[1] once every first-pass tile is done
+        for (int i = tid; i < TW * TH; i += kThreads) gp(D.hist)[(size_t)tl * (TW * TH) + i] = 0;
+        const int ones = block_count_ballot(one, s_red);
+        if (tid == 0 && ones) atomicAdd(&S->hist1, ones);
     }
     const int tchg = __syncthreads_or(changed);
     const int tcnt = block_count_ballot(act, s_red);
@@ -748,7 +797,7 @@ __device__ void relabel_tile(const StepParams &P, const InstDesc &D, InstState *
         if (delta) atomicAdd(&S->active, delta);
         if (tchg) atomicOr(&S->changed, 1);
         gp(D.tile_act)[tl] = tcnt > 0 ? 1u : 0u;
-        count_px(&S->px_relabel, tile_pixels<TW, TH>(W, H, x0, y0));
+        count_visit(P, &S->px_relabel, kPxRelabel, tile_pixels<TW, TH>(W, H, x0, y0));
     }
 }
 
@@ -826,7 +875,7 @@ __device__ void cut_tile_swapped(const StepParams &P, const InstDesc &D, InstSta
         gp(D.tile_chg)[tl] = 0;  // the cut is complete after this pass
         if (tse) atomicAdd((unsigned long long *)&S->sum_e, (unsigned long long)tse);
         if (tra) atomicAdd((unsigned long long *)&S->sum_raise, (unsigned long long)tra);
-        count_px(&S->px_cut_x, tile_pixels<TW, TH>(W, H, x0, y0));
+        count_visit(P, &S->px_cut_x, kPxCutX, tile_pixels<TW, TH>(W, H, x0, y0));
     }
     (void)P;
 }
@@ -984,7 +1033,7 @@ __device__ void cut_tile(const StepParams &P, const InstDesc &D, InstState *S, i
         gp(D.tile_chg)[(size_t)cur * D.ntiles + tl] = (uint8_t)(tchg ? 1 : 0);
         if (tchg) atomicOr(&S->changed, 1);
         if (tse) atomicAdd((unsigned long long *)&S->sum_e, (unsigned long long)tse);
-        count_px(&S->px_cut, tile_pixels<TW, TH>(W, H, x0, y0));
+        count_visit(P, &S->px_cut, kPxCut, tile_pixels<TW, TH>(W, H, x0, y0));
     }
     (void)s_red;
 }
@@ -993,9 +1042,8 @@ __device__ void cut_tile(const StepParams &P, const InstDesc &D, InstState *S, i
 // Phase machine of every instance of the work list (one thread each), run
 // after the tile work of every superstep.
 // ---------------------------------------------------------------------------
-__device__ void control(const StepParams &P) {
-    const int w = (int)(blockIdx.x * kThreads + threadIdx.x);
-    if (w >= P.nwl) return;
+// Returns whether the instance is still running afterwards.
+__device__ bool control_one(const StepParams &P, int w) {
     const int i = P.wl_slot[w];
     // The state and the descriptor fields used here are read in one batch:
     // this kernel runs alone after the tile kernels of the superstep, whose
@@ -1006,7 +1054,7 @@ __device__ void control(const StepParams &P) {
     int64_t *flows = Dp->flows;
     int32_t *status_out = Dp->status;
     int ph = S.phase;
-    if (ph == kIdle || ph == kDone) return;
+    if (ph == kIdle || ph == kDone) return false;
     S.steps += 1;
     bool done = false;
     int status = PMF_OK;
@@ -1028,6 +1076,9 @@ __device__ void control(const StepParams &P) {
             break;
         case kRelabel:
             S.passes += 1;
+            // gap heuristic: the first pass has cleared the histogram and
+            // counted the pixels it labelled 1
+            if (P.gap && S.sub == 0) gp(Dp->hist)[1] = S.hist1;
             if (S.sub > 0 && !S.changed) {
                 S.relabels += 1;
                 ph = S.active == 0 ? kCut : kSweep;
@@ -1081,6 +1132,12 @@ __device__ void control(const StepParams &P) {
             break;
     }
     S.changed = 0;
+    if (ph == kRelabel && S.sub == 0) {
+        // a relabel starts: its first pass rebuilds the label histogram, and
+        // no level is known to be empty until a sweep empties one
+        S.gap = kHInf;
+        S.hist1 = 0;
+    }
     if (!done && S.steps >= P.max_steps) {
         done = true;
         status = PMF_ETIMEOUT;
@@ -1097,6 +1154,7 @@ __device__ void control(const StepParams &P) {
     }
     S.phase = ph;
     P.st[i] = S;
+    return ph != kDone;
 }
 
 // Append `value` to `list` for every lane whose `want` is set: one atomic per
@@ -1122,8 +1180,8 @@ __device__ __forceinline__ void wave_append(bool want, int2 *list, int32_t *coun
 // is in range, its instance in the listed phase (phases change only in the
 // control kernel), a listed sweep tile has work, a listed pass tile needs
 // the pass.
-__global__ __launch_bounds__(kThreads) void k_compact(StepParams P) {
-    const int slot = __builtin_amdgcn_readfirstlane(P.wl_slot[blockIdx.x]);
+__device__ void compact_instance(const StepParams &P, int w) {
+    const int slot = __builtin_amdgcn_readfirstlane(P.wl_slot[w]);
     const InstState *S = &P.st[slot];
     const int phase = __builtin_amdgcn_readfirstlane(S->phase);
     if (phase != kSweep && phase != kInit && phase != kOrient && phase != kRelabel && phase != kCut) return;
@@ -1160,6 +1218,8 @@ __global__ __launch_bounds__(kThreads) void k_compact(StepParams P) {
     if (threadIdx.x == 0) P.st[slot].listed = any;
 }
 
+__global__ __launch_bounds__(kThreads) void k_compact(StepParams P) { compact_instance(P, (int)blockIdx.x); }
+
 // Item i of a list, the same for every thread of the workgroup (scalar registers).
 __device__ __forceinline__ int2 list_item(const StepParams &P, int which, int i) {
     const int2 en = reinterpret_cast<const int2 *>(P.lists)[(size_t)which * P.list_cap + i];
@@ -1172,11 +1232,8 @@ __device__ __forceinline__ int2 list_item(const StepParams &P, int which, int i)
 // run side by side.  Workgroup b takes items of its XCD's eighth of each list
 // (b & 7 picks the eighth: consecutive items are neighbouring tiles of one
 // image, which then share an L2), round robin over the XCD's workgroups.
-template <int K, int TW, int TH>
-__global__ __launch_bounds__(kThreads) void k_step(StepParams P, int ws, int wp) {
-    __shared__ int32_t lds[(3 + K) * (TW + 2) * (TH + 2)];  // sweep layout; passes use 3 planes
-    __shared__ int s_red[4];
-    __shared__ unsigned long long s_sum;
+template <int K, int TW, int TH, bool GAP>
+__device__ void tile_work(const StepParams &P, int ws, int wp, int32_t *lds, int *s_red, unsigned long long *s_sum) {
     const int ns = ws >= 0 ? P.list_count[ws] : 0;
     const int np = wp >= 0 ? P.list_count[wp] : 0;
     const int x = (int)(blockIdx.x & 7), stride = (int)(gridDim.x >> 3), first = (int)(blockIdx.x >> 3);
@@ -1194,7 +1251,7 @@ __global__ __launch_bounds__(kThreads) void k_step(StepParams P, int ws, int wp)
         if (i < s_n) {
             const int2 en = list_item(P, ws, s_lo + i);
             const InstDesc D = load_desc(P.desc, en.x);
-            sweep_tile<K, TW, TH>(P, D, &P.st[en.x], en.y, iters, lds, s_red);
+            sweep_tile<K, TW, TH, GAP>(P, D, &P.st[en.x], en.y, iters, lds, s_red);
         } else {
             const int2 en = list_item(P, wp, p_lo + i - s_n);
             InstState *S = &P.st[en.x];
@@ -1202,26 +1259,189 @@ __global__ __launch_bounds__(kThreads) void k_step(StepParams P, int ws, int wp)
             const InstDesc D = load_desc(P.desc, en.x);
             const int tl = en.y;
             if (phase == kInit)
-                init_tile<K, TW, TH>(P, D, S, tl, s_red, &s_sum);
+                init_tile<K, TW, TH>(P, D, S, tl, s_red, s_sum);
             else if (phase == kOrient)
                 orient_tile<K, TW, TH>(P, D, S, tl, s_red);
             else if (phase == kRelabel)
-                relabel_tile<K, TW, TH>(P, D, S, tl, sub, xrounds, lds, s_red);
+                relabel_tile<K, TW, TH, GAP>(P, D, S, tl, sub, xrounds, lds, s_red);
             else if (swap)
-                cut_tile_swapped<K, TW, TH>(P, D, S, tl, kk, &s_sum);
+                cut_tile_swapped<K, TW, TH>(P, D, S, tl, kk, s_sum);
             else
-                cut_tile<K, TW, TH>(P, D, S, tl, sub, kk, xrounds, lds, s_red, &s_sum);
+                cut_tile<K, TW, TH>(P, D, S, tl, sub, kk, xrounds, lds, s_red, s_sum);
         }
     }
 }
 
+// GAP: the gap heuristic's label histogram is kept (a variant of its own, so
+// that the default build carries none of its registers).
+template <int K, int TW, int TH, bool GAP>
+__global__ __launch_bounds__(kThreads) void k_step(StepParams P, int ws, int wp) {
+    __shared__ int32_t lds[(3 + K) * (TW + 2) * (TH + 2)];  // sweep layout; passes use 3 planes
+    __shared__ int s_red[4];
+    __shared__ unsigned long long s_sum;
+    tile_work<K, TW, TH, GAP>(P, ws, wp, lds, s_red, &s_sum);
+}
+
 __global__ __launch_bounds__(kThreads) void k_control(StepParams P) {
-    control(P);
+    const int w = (int)(blockIdx.x * kThreads + threadIdx.x);
+    if (w < P.nwl) (void)control_one(P, w);
     if (blockIdx.x == 0 && threadIdx.x < 4) {
+        if (P.trace_lists) P.trace_lists[threadIdx.x] = P.list_count[threadIdx.x];
         // keep this superstep's list sizes (read by the timing mode), then
         // clear them: the next superstep compacts afresh
         P.list_count[4 + threadIdx.x] = P.list_count[threadIdx.x];
         P.list_count[threadIdx.x] = 0;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Persistent supersteps.  When few tiles have work the superstep is latency
+// bound and its three launches cost more than their work; k_persist then runs
+// supersteps back to back inside one cooperative launch (every workgroup
+// resident): compaction, tile work of both connectivities and the phase
+// machine, separated by grid-wide barriers.  It leaves when every instance of
+// the work list is done, when a superstep listed more than `exit_tiles` tiles
+// (wide again: separate launches spread them better), after `max_steps`
+// supersteps, or when a barrier wait exceeds its time limit (then it raises
+// the abort word and every workgroup returns; the host reports an error).
+// Barrier words (int32, after the list counters): [0] arrivals, [1]
+// generation, [2] abort, [3] supersteps run by the last launch, [4..5] running
+// instances counted by the control phase of even / odd supersteps.
+// ---------------------------------------------------------------------------
+constexpr int kBarWords = 16;                    // offset of the barrier words in the counter block
+constexpr long long kBarrierTicks = 100000000;   // 1 s of the 100 MHz constant clock
+
+// The workgroup's writes are complete once its barrier has passed (a
+// workgroup barrier waits for the stores of every wave); one thread then
+// makes them visible device-wide (release fence), arrives, and waits for the
+// generation to change with relaxed loads (no cache invalidation while it
+// spins), then one acquire fence makes the other workgroups' writes visible
+// here.  Returns false (in every thread) when the wait was abandoned.
+__device__ bool grid_barrier(int32_t *bar, unsigned nblocks, int *s_ok) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int ok = 1;
+        uint32_t *arrive = reinterpret_cast<uint32_t *>(bar);
+        uint32_t *gen = reinterpret_cast<uint32_t *>(bar + 1);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        const uint32_t g = __hip_atomic_load(gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const uint32_t at = __hip_atomic_fetch_add(arrive, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1u;
+        if (at == nblocks) {
+            // every other workgroup has arrived (and released its writes)
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            __hip_atomic_store(arrive, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(gen, g + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            const long long t0 = wall_clock64();
+            while (__hip_atomic_load(gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == g) {
+                if (__hip_atomic_load(bar + 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+                    ok = 0;
+                    break;
+                }
+                if (wall_clock64() - t0 > kBarrierTicks) {
+                    __hip_atomic_store(bar + 2, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    ok = 0;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(1);
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        *s_ok = ok;
+    }
+    __syncthreads();
+    return *s_ok != 0;
+}
+
+// The superstep parameters of a persistent launch live in device memory (the
+// host copies them there before the launch) and are read with scalar loads.
+__device__ __forceinline__ StepParams load_params(const StepParams *src) {
+    static_assert(sizeof(StepParams) % 4 == 0, "parameters read in 4-byte words");
+    const __attribute__((address_space(4))) uint32_t *w =
+        (const __attribute__((address_space(4))) uint32_t *)src;
+    StepParams P;
+    uint32_t *dst = reinterpret_cast<uint32_t *>(&P);
+#pragma unroll
+    for (int i = 0; i < (int)(sizeof(StepParams) / 4); ++i) dst[i] = w[i];
+    return P;
+}
+
+// Persistent kernels come in three forms: for work lists of 4-connected
+// instances only (KSET 4), of 8-connected ones only (KSET 8), both inlined
+// into the kernel; and for mixed lists (KSET 12), whose phases are separate
+// (not inlined) functions so that each gets the registers it needs rather
+// than the sum of both connectivities.  The sweep and pass layouts use the
+// launch's dynamic LDS.
+extern __shared__ int32_t persist_lds[];
+
+template <int K, int TW, int TH>
+__device__ __attribute__((noinline)) void persist_work(const StepParams *Pg) {
+    __shared__ int s_red[4];
+    __shared__ unsigned long long s_sum;
+    const StepParams P = load_params(Pg);
+    tile_work<K, TW, TH, false>(P, K == 4 ? 0 : 1, K == 4 ? 2 : 3, persist_lds, s_red, &s_sum);
+}
+
+__device__ __attribute__((noinline)) void persist_compact(const StepParams *Pg) {
+    const StepParams P = load_params(Pg);
+    for (int w = (int)blockIdx.x; w < P.nwl; w += (int)gridDim.x) compact_instance(P, w);
+}
+
+// Phase machine of the instances of this workgroup's share; whether one of
+// them is still running.
+__device__ __forceinline__ int control_share(const StepParams &P) {
+    int run = 0;
+    for (int w = (int)(blockIdx.x * kThreads + threadIdx.x); w < P.nwl; w += (int)gridDim.x * kThreads)
+        run |= control_one(P, w) ? 1 : 0;
+    return run;
+}
+
+__device__ __attribute__((noinline)) int persist_control(const StepParams *Pg) {
+    const StepParams P = load_params(Pg);
+    return control_share(P);
+}
+
+template <int TW, int TH, int KSET>
+__global__ __launch_bounds__(kThreads) void k_persist(const StepParams *Pg, int max_steps, int exit_tiles) {
+    __shared__ int s_ok;
+    __shared__ int s_red[4];
+    __shared__ unsigned long long s_sum;
+    const StepParams P = load_params(Pg);
+    int32_t *bar = P.ring_count + kBarWords;
+    const unsigned G = gridDim.x;
+    for (int step = 0; step < max_steps; ++step) {
+        // compaction: the instances of the work list, round robin over the workgroups
+        if (KSET == 12) {
+            persist_compact(Pg);
+        } else {
+            for (int w = (int)blockIdx.x; w < P.nwl; w += (int)G) compact_instance(P, w);
+        }
+        if (!grid_barrier(bar, G, &s_ok)) return;
+        // tile work; the running count of the next superstep starts at zero
+        // (its readers, after the previous superstep, are all past the barrier)
+        if (blockIdx.x == 0 && threadIdx.x == 0) bar[4 + ((step + 1) & 1)] = 0;
+        if (KSET == 4) {
+            tile_work<4, TW, TH, false>(P, 0, 2, persist_lds, s_red, &s_sum);
+        } else if (KSET == 8) {
+            tile_work<8, TW, TH, false>(P, 1, 3, persist_lds, s_red, &s_sum);
+        } else {
+            persist_work<4, TW, TH>(Pg);
+            __syncthreads();
+            persist_work<8, TW, TH>(Pg);
+        }
+        if (!grid_barrier(bar, G, &s_ok)) return;
+        // phase machine of every instance; the list sizes are kept and cleared
+        const int run = KSET == 12 ? persist_control(Pg) : control_share(P);
+        if (__syncthreads_or(run) && threadIdx.x == 0) atomicAdd(&bar[4 + (step & 1)], 1);
+        if (blockIdx.x == 0 && threadIdx.x < 4) {
+            P.list_count[4 + threadIdx.x] = P.list_count[threadIdx.x];
+            P.list_count[threadIdx.x] = 0;
+        }
+        if (!grid_barrier(bar, G, &s_ok)) return;
+        if (blockIdx.x == 0 && threadIdx.x == 0) bar[3] = step + 1;
+        const int running = __hip_atomic_load(&bar[4 + (step & 1)], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const int listed = P.list_count[4] + P.list_count[5] + P.list_count[6] + P.list_count[7];
+        if (running == 0 || listed > exit_tiles) break;
     }
 }
 
@@ -1289,27 +1509,28 @@ int launch_mask_stats(const uint8_t *mask, int n, const int32_t *slope, const ui
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
-// out[p] = the first lambda of `lams` (ascending, m entries) whose mask does
-// not hold pixel p, or `none` if every mask holds it (masks: m row-major
-// planes of n bytes).  With nested masks this is the lambda at which p leaves
-// the minimal source set.
-__global__ __launch_bounds__(kThreads) void k_exit_lambda(const uint8_t *masks, const int32_t *lams, int m, int n,
-                                                          int32_t none, int32_t *out) {
+// out[p] = min(out[p], lam) for every pixel p that `mask` (n bytes) does not
+// hold.  Applied to the masks of several lambdas it leaves, per pixel, the
+// smallest of those lambdas whose minimal source set lacks the pixel.
+__global__ __launch_bounds__(kThreads) void k_exit_min(const uint8_t *mask, int n, int32_t lam, int32_t *out) {
     const int p = blockIdx.x * kThreads + threadIdx.x;
-    if (p >= n) return;
-    int32_t ex = none;
-    for (int i = 0; i < m; ++i)
-        if (!masks[(size_t)i * n + p]) {
-            ex = lams[i];
-            break;
-        }
-    out[p] = ex;
+    if (p < n && !mask[p] && lam < out[p]) out[p] = lam;
 }
 
-int launch_exit_lambda(const uint8_t *masks, const int32_t *lams, int m, int n, int32_t none, int32_t *out,
-                       void *stream) {
-    hipLaunchKernelGGL(k_exit_lambda, dim3((n + kThreads - 1) / kThreads), dim3(kThreads), 0, (hipStream_t)stream,
-                       masks, lams, m, n, none, out);
+__global__ __launch_bounds__(kThreads) void k_fill_i32(int32_t *out, int n, int32_t v) {
+    const int p = blockIdx.x * kThreads + threadIdx.x;
+    if (p < n) out[p] = v;
+}
+
+int launch_exit_min(const uint8_t *mask, int n, int32_t lam, int32_t *out, void *stream) {
+    hipLaunchKernelGGL(k_exit_min, dim3((n + kThreads - 1) / kThreads), dim3(kThreads), 0, (hipStream_t)stream,
+                       mask, n, lam, out);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int launch_fill_i32(int32_t *out, int n, int32_t v, void *stream) {
+    hipLaunchKernelGGL(k_fill_i32, dim3((n + kThreads - 1) / kThreads), dim3(kThreads), 0, (hipStream_t)stream,
+                       out, n, v);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
@@ -1327,6 +1548,17 @@ int launch_finalize(const int32_t *sub_status, const int64_t *meta, int n_user, 
 // (a workgroup with no item left exits at once).
 static int list_grid(int tiles) { return 8 * ((std::min(tiles, 4096) + 7) / 8); }
 
+// One tile-work launch of connectivity K over sweep list ws and pass list wp.
+template <int K, int TW, int TH>
+static void step_launch(const StepParams &p, hipStream_t s, int ws, int wp) {
+    const int tiles = K == 4 ? p.t4_count : p.t8_count;
+    if (!tiles) return;
+    if (p.gap)
+        hipLaunchKernelGGL((k_step<K, TW, TH, true>), dim3(list_grid(tiles)), dim3(kThreads), 0, s, p, ws, wp);
+    else
+        hipLaunchKernelGGL((k_step<K, TW, TH, false>), dim3(list_grid(tiles)), dim3(kThreads), 0, s, p, ws, wp);
+}
+
 template <int TW, int TH>
 static int launch_tw(const StepParams &p, hipStream_t s, void *const *ev, bool split) {
     const dim3 block(kThreads);
@@ -1336,15 +1568,15 @@ static int launch_tw(const StepParams &p, hipStream_t s, void *const *ev, bool s
     if (ev) (void)hipEventRecord((hipEvent_t)ev[0], s);
     if (split) {
         // sweeps and passes as separate launches (timed apart)
-        if (p.t4_count) hipLaunchKernelGGL((k_step<4, TW, TH>), dim3(list_grid(p.t4_count)), block, 0, s, p, 0, -1);
-        if (p.t8_count) hipLaunchKernelGGL((k_step<8, TW, TH>), dim3(list_grid(p.t8_count)), block, 0, s, p, 1, -1);
+        step_launch<4, TW, TH>(p, s, 0, -1);
+        step_launch<8, TW, TH>(p, s, 1, -1);
         if (ev) (void)hipEventRecord((hipEvent_t)ev[1], s);
-        if (p.t4_count) hipLaunchKernelGGL((k_step<4, TW, TH>), dim3(list_grid(p.t4_count)), block, 0, s, p, -1, 2);
-        if (p.t8_count) hipLaunchKernelGGL((k_step<8, TW, TH>), dim3(list_grid(p.t8_count)), block, 0, s, p, -1, 3);
+        step_launch<4, TW, TH>(p, s, -1, 2);
+        step_launch<8, TW, TH>(p, s, -1, 3);
         n = 2 * ((p.t4_count > 0) + (p.t8_count > 0));
     } else {
-        if (p.t4_count) hipLaunchKernelGGL((k_step<4, TW, TH>), dim3(list_grid(p.t4_count)), block, 0, s, p, 0, 2);
-        if (p.t8_count) hipLaunchKernelGGL((k_step<8, TW, TH>), dim3(list_grid(p.t8_count)), block, 0, s, p, 1, 3);
+        step_launch<4, TW, TH>(p, s, 0, 2);
+        step_launch<8, TW, TH>(p, s, 1, 3);
         n = (p.t4_count > 0) + (p.t8_count > 0);
         if (ev) (void)hipEventRecord((hipEvent_t)ev[1], s);
     }
@@ -1361,12 +1593,52 @@ int resident_workgroups(int K, int tile_w) {
         return 0;
     hipError_t e;
     if (tile_w == 64)
-        e = K == 8 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_step<8, 64, 16>, kThreads, 0)
-                   : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_step<4, 64, 16>, kThreads, 0);
+        e = K == 8 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_step<8, 64, 16, false>, kThreads, 0)
+                   : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_step<4, 64, 16, false>, kThreads, 0);
     else
-        e = K == 8 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_step<8, 32, 32>, kThreads, 0)
-                   : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_step<4, 32, 32>, kThreads, 0);
+        e = K == 8 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_step<8, 32, 32, false>, kThreads, 0)
+                   : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_step<4, 32, 32, false>, kThreads, 0);
     return e == hipSuccess ? per * cus : 0;
+}
+
+// Dynamic LDS of a persistent launch: the sweep layout of its connectivity
+// (the 8-connected one for mixed lists).
+static unsigned persist_lds_bytes(int tile_w, int kset) {
+    const int tw = tile_w == 64 ? 64 : 32, th = 1024 / tw, K = kset == 4 ? 4 : 8;
+    return (unsigned)((3 + K) * (tw + 2) * (th + 2) * 4);
+}
+
+template <int TW, int TH>
+static const void *persist_fn(int kset) {
+    return kset == 4 ? (const void *)k_persist<TW, TH, 4>
+                     : kset == 8 ? (const void *)k_persist<TW, TH, 8> : (const void *)k_persist<TW, TH, 12>;
+}
+
+int persist_workgroups(int tile_w, int kset) {
+    int dev = 0, cus = 0, per = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        return 0;
+    const void *fn = tile_w == 64 ? persist_fn<64, 16>(kset) : persist_fn<32, 32>(kset);
+    const hipError_t e =
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, fn, kThreads, persist_lds_bytes(tile_w, kset));
+    return e == hipSuccess ? per * cus : 0;
+}
+
+int launch_persist(const StepParams *p_dev, int tile_w, int kset, int grid, int max_steps, int exit_tiles,
+                   void *stream) {
+    if (grid < 8 || grid % 8 != 0 || max_steps < 1 || !p_dev) return -1;
+    if (kset != 4 && kset != 8 && kset != 12) return -1;
+    const StepParams *a = p_dev;
+    void *args[] = {(void *)&a, (void *)&max_steps, (void *)&exit_tiles};
+    const void *fn = tile_w == 64 ? persist_fn<64, 16>(kset) : persist_fn<32, 32>(kset);
+    const hipError_t e = hipLaunchCooperativeKernel(fn, dim3(grid), dim3(kThreads), args,
+                                                    persist_lds_bytes(tile_w, kset), (hipStream_t)stream);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return -1;
+    }
+    return 0;
 }
 
 int launch_superstep(const StepParams &p, int tile_w, void *stream, void *const *events, bool split) {

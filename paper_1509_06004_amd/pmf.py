@@ -53,7 +53,9 @@ class Options(ctypes.Structure):
         ("tail_exchange_rounds", ctypes.c_int32),
         ("relabel_passes", ctypes.c_int32),
         ("orientation", ctypes.c_int32),
-        ("reserved2", ctypes.c_int32),
+        ("gap", ctypes.c_int32),
+        ("persist_tiles", ctypes.c_int32),
+        ("persist_wgs", ctypes.c_int32),
     ]
 
 
@@ -104,6 +106,11 @@ class Stats(ctypes.Structure):
         ("px_orient", ctypes.c_int64),
         ("px_init_x", ctypes.c_int64),
         ("px_cut_x", ctypes.c_int64),
+        ("gap_kills", ctypes.c_int64),
+        ("persist_launches", ctypes.c_int64),
+        ("persist_supersteps", ctypes.c_int64),
+        ("persist_ns", ctypes.c_int64),
+        ("kernel_px", ctypes.c_int64 * 16),
     ]
 
 
@@ -124,6 +131,9 @@ def load_library() -> ctypes.CDLL:
         "pmf_create": (ctypes.c_int, [ctypes.POINTER(Options), P, P, ctypes.c_size_t,
                                       ctypes.POINTER(P)]),
         "pmf_solve_batch": (ctypes.c_int, [P, ctypes.POINTER(InstanceC), ctypes.c_int32, P, P]),
+        "pmf_solve_batch_async": (ctypes.c_int, [P, ctypes.POINTER(InstanceC), ctypes.c_int32, P, P]),
+        "pmf_wait": (ctypes.c_int, [P]),
+        "pmf_query_done": (ctypes.c_int, [P, ctypes.POINTER(ctypes.c_int32)]),
         "pmf_extract_cut": (ctypes.c_int, [P, ctypes.c_int32, ctypes.c_int32, P]),
         "pmf_destroy": (ctypes.c_int, [P]),
         "pmf_strerror": (ctypes.c_char_p, [ctypes.c_int]),
@@ -182,6 +192,24 @@ def pmf_solve_batch(handle, instances: Sequence[InstanceC], flows_ptr: int, stat
     arr = (InstanceC * len(instances))(*instances)
     return load_library().pmf_solve_batch(handle, arr, len(instances), ctypes.c_void_p(flows_ptr),
                                           ctypes.c_void_p(status_ptr))
+
+
+def pmf_solve_batch_async(handle, instances: Sequence[InstanceC], flows_ptr: int, status_ptr: int) -> int:
+    arr = (InstanceC * len(instances))(*instances)
+    return load_library().pmf_solve_batch_async(handle, arr, len(instances), ctypes.c_void_p(flows_ptr),
+                                                ctypes.c_void_p(status_ptr))
+
+
+def pmf_wait(handle) -> int:
+    return load_library().pmf_wait(handle)
+
+
+def pmf_query_done(handle) -> bool:
+    done = ctypes.c_int32(0)
+    rc = load_library().pmf_query_done(handle, ctypes.byref(done))
+    if rc != PMF_OK:
+        raise PmfError(rc, "pmf_query_done")
+    return bool(done.value)
 
 
 def pmf_extract_cut(handle, inst: int, lambda_idx: int, mask_ptr: int) -> int:
@@ -270,7 +298,11 @@ def pmf_get_stats(handle) -> Dict[str, int]:
     rc = load_library().pmf_get_stats(handle, ctypes.byref(s))
     if rc != PMF_OK:
         raise PmfError(rc, "pmf_get_stats")
-    return {f: int(getattr(s, f)) for f, _ in Stats._fields_}
+    out = {}
+    for f, _ in Stats._fields_:
+        v = getattr(s, f)
+        out[f] = [int(x) for x in v] if f == "kernel_px" else int(v)
+    return out
 
 
 def pmf_session_open(handle, max_slots: int, pool_bytes: int = 0) -> int:
@@ -382,6 +414,27 @@ class Solver:
             raise PmfError(rc, "pmf_solve_batch")
         self.last = list(dev_insts)
         return flows, status
+
+    def solve_async(self, dev_insts: Sequence[DeviceInstance]) -> Tuple[torch.Tensor, torch.Tensor]:
+        """Start a solve and return at once; the tensors are complete after wait()."""
+        total = sum(d.L for d in dev_insts)
+        dev = dev_insts[0].lambdas.device if dev_insts else torch.device("cuda")
+        flows = torch.empty(total, dtype=torch.int64, device=dev)
+        status = torch.empty(len(dev_insts), dtype=torch.int32, device=dev)
+        self._async_args = [d.c_struct() for d in dev_insts]
+        rc = pmf_solve_batch_async(self.handle, self._async_args, int(flows.data_ptr()), int(status.data_ptr()))
+        if rc != PMF_OK:
+            raise PmfError(rc, "pmf_solve_batch_async")
+        self.last = list(dev_insts)
+        return flows, status
+
+    def wait(self) -> None:
+        rc = pmf_wait(self.handle)
+        if rc != PMF_OK:
+            raise PmfError(rc, "pmf_solve_batch_async")
+
+    def done(self) -> bool:
+        return pmf_query_done(self.handle)
 
     def extract_cut(self, inst: int, lambda_idx: int) -> torch.Tensor:
         d = self.last[inst]

@@ -21,6 +21,7 @@ fake backend and run on the GPU with :class:`PmfBackend`.
 from __future__ import annotations
 
 import dataclasses
+import itertools
 import time
 from collections import deque
 from typing import Dict, List, Optional, Sequence
@@ -64,7 +65,16 @@ class Backend:
         """Bytes of the whole pool: a request needing more can never run."""
         raise NotImplementedError
 
-    def submit(self, insts) -> Optional[List[int]]:
+    def stage(self, insts):
+        """Start moving a request's inputs to the device (returns a token for
+        `ready` and `submit`; None when the backend has nothing to stage)."""
+        return None
+
+    def ready(self, staged) -> bool:
+        """Whether the staged inputs have arrived (never blocks)."""
+        return True
+
+    def submit(self, insts, staged=None) -> Optional[List[int]]:
         """Admit all instances (ids) or none (None)."""
         raise NotImplementedError
 
@@ -95,6 +105,7 @@ class PmfBackend(Backend):
         for k, v in options.items():
             setattr(opts, k, v)
         self.stream = torch.cuda.current_stream()
+        self.copy_stream = torch.cuda.Stream()
         self.handle = pmf.pmf_create(opts, int(self.stream.cuda_stream))
         rc = pmf.pmf_session_open(self.handle, max_slots, pool_bytes)
         if rc != pmf.PMF_OK:
@@ -130,10 +141,32 @@ class PmfBackend(Backend):
     def capacity(self) -> int:
         return self.pool_bytes
 
-    def submit(self, insts) -> Optional[List[int]]:
+    def stage(self, insts):
+        """Upload the request's inputs from pinned host memory on a copy stream
+        of their own, so that the transfer overlaps with the supersteps that
+        are running; the session's stream waits for it before the request's
+        first launch (by then it has long finished)."""
+        torch, pmf = self.torch, self.pmf
+        with torch.cuda.stream(self.copy_stream):
+            dev = pmf.to_device(insts, non_blocking=True)
+            ev = torch.cuda.Event()
+            ev.record(self.copy_stream)
+        for d in dev:  # the tensors are used on the session's stream from now on
+            for t in (d.nlink, d.cap_src, d.cap_snk0, d.snk_slope, d.seed, d.lambdas):
+                t.record_stream(self.stream)
+        return dev, ev
+
+    def ready(self, staged) -> bool:
+        return staged is None or staged[1].query()
+
+    def submit(self, insts, staged=None) -> Optional[List[int]]:
         """One id per request instance (the id of its first chunk)."""
         torch, pmf = self.torch, self.pmf
-        dev = pmf.to_device(insts)
+        if staged is not None:
+            dev, ev = staged
+            self.stream.wait_event(ev)
+        else:
+            dev = pmf.to_device(insts)
         subs, owner = [], []
         for j, d in enumerate(dev):
             for a, b in self._chunks(insts[j]):
@@ -261,8 +294,9 @@ class Server:
     """FIFO admission by free memory, continuous batching, latency accounting."""
 
     def __init__(self, backend: Backend, max_inflight_instances: int = 1 << 30, keep_results: bool = False,
-                 clock=time.perf_counter, sleep=time.sleep):
+                 clock=time.perf_counter, sleep=time.sleep, stage_ahead: int = 8):
         self.backend = backend
+        self.stage_ahead = stage_ahead  # queued requests whose inputs are moved to the device ahead of admission
         self.max_inflight = max_inflight_instances
         self.keep_results = keep_results
         self.clock = clock
@@ -293,19 +327,34 @@ class Server:
                 rec = RequestRecord(index=nxt, arrival=arrivals[nxt], n_inst=len(insts),
                                     solves=sum(i.L for i in insts))
                 records.append(rec)
-                pending.append((rec, insts))
+                pending.append([rec, insts, None])
                 nxt += 1
+            # inputs of the first queued requests start moving to the device
+            # at once (bounded), overlapping with the work in flight
+            for item in itertools.islice(pending, self.stage_ahead):
+                if item[2] is None and item[0].failed is None:
+                    try:
+                        item[2] = ("staged", be.stage(item[1]))
+                    except Exception as exc:  # a failed upload fails that request only
+                        item[0].failed = repr(exc)
             max_queue = max(max_queue, len(pending))
             # admission: whole requests, FIFO, while memory, slots and the bound allow
             while pending and (n_inflight == 0 or n_inflight + pending[0][0].n_inst <= self.max_inflight):
-                rec, insts = pending[0]
+                rec, insts, staged = pending[0]
+                if rec.failed is not None:
+                    pending.popleft()
+                    rec.finished = self.clock() - t0
+                    continue
                 if be.bytes_needed(insts) > be.capacity():
                     pending.popleft()
                     rec.failed = "request larger than the whole pool"
                     rec.finished = self.clock() - t0
                     continue
+                token = staged[1] if staged is not None else None
+                if staged is not None and not be.ready(token):
+                    break  # FIFO: wait for its upload
                 try:
-                    ids = be.submit(insts)
+                    ids = be.submit(insts) if token is None else be.submit(insts, token)
                 except Exception as exc:  # a failed request must not stop the others
                     pending.popleft()
                     rec.failed = repr(exc)
@@ -328,6 +377,8 @@ class Server:
                     break
                 if not pending and nxt < len(arrivals):
                     self.sleep(max(0.0, min(arrivals[nxt] - now, 0.002)))
+                elif pending:
+                    self.sleep(0.0002)  # the head request's inputs are still on their way
                 continue
             try:
                 done = be.step()

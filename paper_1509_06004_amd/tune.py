@@ -4,8 +4,9 @@ The knobs change speed, never results: tile shape, push/relabel iterations per
 tile visit, sweeps between global relabels, the bound on relaxation rounds per
 tile visit, halo exchange rounds per pass, the settings of short (latency
 bound) supersteps, the orientation (s-t swap) rule, packing order (FIFO or
-largest-first) and the lambda chunk (how the schedule of each instance is cut
-into concurrently solved pieces).  The
+largest-first), the lambda chunk (how the schedule of each instance is cut
+into concurrently solved pieces), the gap heuristic, and when and how wide
+the persistent (cooperative) superstep launch runs.  The
 tuner times solves of a calibration set on the device by coordinate descent
 from the defaults and keeps the fastest point.  Every point's flows and masks
 must equal those of the starting point bit for bit; a point that differs is
@@ -26,7 +27,8 @@ from typing import Dict, List, Optional, Sequence
 from . import pmf
 
 KNOBS = ("tile_w", "inner_iters", "sweeps_per_relabel", "local_bfs_iters", "exchange_rounds", "tail_tiles",
-         "tail_inner_iters", "tail_exchange_rounds", "relabel_passes", "orientation", "order", "lambda_chunk")
+         "tail_inner_iters", "tail_exchange_rounds", "relabel_passes", "orientation", "order", "lambda_chunk",
+         "gap", "persist_tiles", "persist_wgs")
 SPACE = {
     "tile_w": [32, 64],
     "inner_iters": [4, 8, 12, 16, 32],
@@ -40,8 +42,13 @@ SPACE = {
     "orientation": [0, 1, 2, 3],
     "order": [0, 1],
     "lambda_chunk": [0, 1, 2, 4],
+    "gap": [0, 1],
+    "persist_tiles": [0, 256, 1024, 4096],
+    "persist_wgs": [0, 512, 1024],
 }
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "pmf_tune.json")
+# the cache committed with the package (written by ``bench.py --tune`` on the device)
+PACKAGE_CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tune_cache.json")
 
 
 def workload_key(insts: Sequence, device_name: str) -> str:

@@ -1,0 +1,98 @@
+"""GPU checks of the boundary's extra calls, through the C ABI: the
+asynchronous solve (same results as the blocking one, the caller's thread is
+free meanwhile), and all-breakpoints runs inside the handle's own memory
+(a caller workspace, a memory budget)."""
+
+import sys
+import time
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1509_06004_amd import workload as W
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def pmf():
+    import torch
+    from paper_1509_06004_amd import pmf as P
+    assert torch.cuda.is_available()
+    P.load_library()
+    return P
+
+
+def test_async_solve_matches_blocking(pmf):
+    import torch
+    insts = W.config1() + W.config2(K=4, seeds=3, L=6)
+    dev = pmf.to_device(insts)
+    ref = pmf.Solver()
+    f0, s0 = ref.solve(dev)
+    torch.cuda.synchronize()
+    m0 = [[ref.extract_cut(i, k).cpu() for k in range(inst.L)] for i, inst in enumerate(insts)]
+    a = pmf.Solver()
+    for rep in range(2):
+        t0 = time.perf_counter()
+        f1, s1 = a.solve_async(dev)
+        t_ret = time.perf_counter() - t0
+        polls = 0
+        while not a.done():
+            polls += 1
+            time.sleep(0.0005)
+        a.wait()
+        t_all = time.perf_counter() - t0
+        torch.cuda.synchronize()
+        say("async solve", rep, "returned after %.2f ms, done after %.2f ms, %d polls" % (t_ret * 1e3, t_all * 1e3, polls))
+        assert torch.equal(f0, f1) and torch.equal(s0, s1)
+        for i, inst in enumerate(insts):
+            for k in range(inst.L):
+                assert torch.equal(m0[i][k], a.extract_cut(i, k).cpu()), (i, k)
+    assert int(s1.cpu().max()) == 0
+    for k in (0, 9, 19):
+        f, m = O.fifo_pr(insts[0], int(insts[0].lambdas[k]))
+        assert int(f1[k].cpu()) == f
+    # a call on the handle while a solve is outstanding waits for it
+    f2, _ = a.solve_async(dev)
+    st = a.stats()
+    assert st["supersteps"] > 0
+    assert torch.equal(f0, f2)
+    a.close()
+    ref.close()
+
+
+def test_parametric_in_workspace_and_budget(pmf):
+    """All breakpoints inside a caller workspace give the same answer as with
+    library memory; a memory budget too small is reported, not exceeded."""
+    import torch
+    inst = W.config0()[0]
+    dev = pmf.to_device([inst])[0]
+    s = pmf.Solver()
+    bp0, f0, ex0 = pmf.pmf_parametric(s.handle, dev, 0, 250)
+    torch.cuda.synchronize()
+    s.close()
+    ws = torch.empty(256 << 20, dtype=torch.uint8, device="cuda")
+    w = pmf.Solver(workspace=ws)
+    bp1, f1, ex1 = pmf.pmf_parametric(w.handle, dev, 0, 250)
+    torch.cuda.synchronize()
+    assert list(bp0) == list(bp1) and list(f0) == list(f1)
+    assert torch.equal(ex0, ex1)
+    assert w.stats()["device_bytes"] <= ws.numel()
+    w.close()
+    small = pmf.Solver(mem_budget=1 << 16)
+    with pytest.raises(pmf.PmfError) as e:
+        pmf.pmf_parametric(small.handle, dev, 0, 250)
+    assert e.value.code == pmf.PMF_ENOMEM
+    small.close()
+    # and the breakpoints themselves against the oracle at every integer lambda
+    lams = list(range(0, 251))
+    sols = O.solve_many([(inst, lam) for lam in lams])
+    ms = np.stack([np.asarray(m, dtype=bool).reshape(inst.H, inst.W) for _, m in sols])
+    exp_bp = [lams[i] for i in range(1, len(lams)) if (ms[i] != ms[i - 1]).any()]
+    assert list(bp1) == exp_bp

@@ -142,6 +142,63 @@ def test_warm_chains_as_given_repeated(pmf, K):
         check_against_oracle(insts, flows, status, masks)
 
 
+@pytest.mark.parametrize("orientation", [0, 2])
+def test_gap_heuristic(pmf, orientation):
+    """The gap heuristic (a label histogram per instance; pixels above an
+    emptied level stop until the next global relabel) leaves every flow and
+    minimal source set equal to the oracle's, on warm chains over grids of
+    many tiles with long sweep periods (so that levels empty between
+    relabels), and it does stop pixels on them."""
+    rng = np.random.default_rng(900 + orientation)
+    insts = []
+    for i in range(6):
+        K = 4 if i % 2 else 8
+        img = W.voronoi_image(int(rng.integers(70, 160)), int(rng.integers(60, 120)), 10, rng)
+        nl = W.nlinks(img, K)
+        H, Wd = img.shape
+        insts.append(W.seed_instance(img, nl, K, int(rng.integers(5, Wd - 5)), int(rng.integers(5, H - 5)), 5,
+                                     W.loguniform_lambdas(rng, 6, 2000.0), image=i))
+    kills = 0
+    for opts in (dict(), dict(sweeps_per_relabel=64, inner_iters=4), dict(lambda_chunk=1)):
+        say("gap heuristic orientation", orientation, opts)
+        flows, status, masks, st = solve(pmf, insts, gap=1, orientation=orientation,
+                                         **dict(dict(lambda_chunk=100), **opts))
+        say("gap kills", st["gap_kills"])
+        kills += st["gap_kills"]
+        check_against_oracle(insts, flows, status, masks)
+    assert kills > 0
+
+
+@pytest.mark.parametrize("K,orientation,wgs", [(4, 2, 0), (8, 0, 16), (4, 0, 0)])
+def test_persistent_supersteps(pmf, K, orientation, wgs):
+    """Supersteps run back to back inside one cooperative launch (grid-wide
+    barriers between compaction, tile work and the phase machine) once the
+    lists are short: every flow and minimal source set equals the oracle's,
+    in three repeated solves of warm chains on grids of many tiles and on a
+    batch of tiny grids, and the persistent launch does run."""
+    rng = np.random.default_rng(500 + K + orientation)
+    insts = []
+    for i in range(4):
+        img = W.voronoi_image(int(rng.integers(70, 150)), int(rng.integers(60, 120)), 8, rng)
+        nl = W.nlinks(img, K)
+        H, Wd = img.shape
+        insts.append(W.seed_instance(img, nl, K, int(rng.integers(5, Wd - 5)), int(rng.integers(5, H - 5)), 5,
+                                     W.loguniform_lambdas(rng, 6, 2000.0), image=i))
+    for i in range(40):
+        Wd, Hd = int(rng.integers(1, 10)), int(rng.integers(1, 10))
+        cmax = int(rng.choice([1, 3, 20, 500]))
+        insts.append(W.tiny_random(rng, Wd, Hd, 4 if i % 2 else 8, cmax=cmax, L=int(rng.integers(1, 5)),
+                                   p_seed=float(rng.uniform(0, 0.3)), lam_max=3 * cmax))
+    for rep in range(3):
+        say("persistent K", K, "orientation", orientation, "wgs", wgs, "solve", rep)
+        flows, status, masks, st = solve(pmf, insts, persist_tiles=1 << 20, persist_wgs=wgs, steps_per_sync=4,
+                                         orientation=orientation, lambda_chunk=100 if rep < 2 else 2)
+        say("persistent launches", st["persist_launches"], "supersteps", st["persist_supersteps"], "of",
+            st["supersteps"])
+        assert st["persist_launches"] > 0 and st["persist_supersteps"] > 0
+        check_against_oracle(insts, flows, status, masks)
+
+
 def test_config0(pmf):
     insts = W.config0()
     say("config0 64x64")
@@ -188,7 +245,11 @@ def test_options_do_not_change_results(pmf):
                  dict(tail_tiles=1 << 30, tail_inner_iters=200, tail_exchange_rounds=64),
                  dict(relabel_passes=1), dict(relabel_passes=2, exchange_rounds=1, local_bfs_iters=3),
                  dict(orientation=1), dict(orientation=2), dict(orientation=3),
-                 dict(orientation=3, lambda_chunk=100), dict(orientation=2, lambda_chunk=2)]:
+                 dict(orientation=3, lambda_chunk=100), dict(orientation=2, lambda_chunk=2),
+                 dict(gap=1), dict(gap=1, orientation=0, lambda_chunk=100),
+                 dict(gap=1, inner_iters=64, sweeps_per_relabel=32, relabel_passes=2),
+                 dict(persist_tiles=1 << 30), dict(persist_tiles=1 << 30, persist_wgs=8, steps_per_sync=3),
+                 dict(persist_tiles=40, gap=1, lambda_chunk=1)]:
         say("options", opts)
         flows, status, masks, _ = solve(pmf, insts, **opts)
         assert (status == 0).all()

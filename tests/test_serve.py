@@ -249,3 +249,44 @@ def test_overload_throughput_counts_backlog_finished_in_window():
     # and requests from the warmup backlog are among them
     assert rep.solves > 0 and rep.solves % 2 == 0
     assert rep.solves > 2 * rep.completed
+
+
+class StagingBackend(OracleBackend):
+    """Uploads take a number of polls to arrive: admission must wait for them
+    without blocking, in FIFO order, and requests still come out exact."""
+
+    def __init__(self, *a, polls=3, **k):
+        super().__init__(*a, **k)
+        self.polls = polls
+        self.staged = 0
+        self.not_ready = 0
+
+    def stage(self, insts):
+        self.staged += 1
+        return {"left": self.polls, "insts": insts}
+
+    def ready(self, token):
+        token["left"] -= 1
+        if token["left"] > 0:
+            self.not_ready += 1
+            return False
+        return True
+
+    def submit(self, insts, staged=None):
+        assert staged is not None and staged["left"] <= 0 and staged["insts"] is insts
+        return super().submit(insts)
+
+
+def test_staged_uploads_gate_admission_in_order():
+    rng = np.random.default_rng(77)
+    reqs = [[W.tiny_random(rng, 5, 4, 4, cmax=9, L=2, p_seed=0.1, lam_max=20)] for _ in range(6)]
+    be = StagingBackend(1 << 30, per_step=1, polls=3)
+    sim = SimClock()
+    srv = Server(be, keep_results=True, clock=sim.clock, sleep=sim.sleep, stage_ahead=2)
+    rep = srv.run([0.0] * len(reqs), lambda i: reqs[i], duration_s=100.0, drain=True)
+    assert rep.completed == len(reqs) and be.staged == len(reqs) and be.not_ready > 0
+    assert be.admit_order == sorted(be.admit_order)
+    for rec in rep.records:
+        inst = reqs[rec.index][0]
+        flows, _ = O.solve_chain(inst)
+        assert list(rec.results[0].flows) == list(flows)
