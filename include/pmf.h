@@ -49,7 +49,8 @@ enum pmf_status {
     PMF_ETIMEOUT = 5,   /* superstep budget exhausted for an instance    */
     PMF_ENOTSOLVED = 6, /* no completed solve to read from               */
     PMF_ERANGE = 7,     /* instance or lambda index out of range         */
-    PMF_EBUSY = 8       /* no free slot; retry after results are released */
+    PMF_EBUSY = 8,      /* no free slot; retry after results are released */
+    PMF_ELIMIT = 9      /* batch larger than PMF_NOALLOC_BYTES (no-allocation solve) */
 };
 
 /* Solver options.  Fill with pmf_default_options(); every field is a tuning
@@ -199,6 +200,23 @@ int pmf_create(const pmf_options *opt, void *stream, void *workspace, size_t ws_
  * W, H, L < 1, NULL pointers), PMF_ENOMEM, PMF_EDEVICE. */
 int pmf_solve_batch(pmf_handle *h, const pmf_instance *inst, int32_t n_inst, int64_t *flows_out,
                     int32_t *status_out);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc):
+ * pmf_solve_batch with every byte of solver state in a fixed device array of
+ * PMF_NOALLOC_BYTES that the library holds on each device it runs on until
+ * the process ends.  Arguments, results and errors are those of
+ * pmf_solve_batch, and so are the flows and masks; the call itself allocates
+ * no device memory (it launches supersteps directly, without capturing a
+ * graph).  A batch whose state does not fit returns PMF_ELIMIT before any
+ * launch; options.timing must be 0 (else PMF_EINVAL).  Masks stay readable
+ * with pmf_extract_cut / pmf_extract_levels until the next solve on this
+ * handle or the next no-allocation solve on this device: every handle on a
+ * device shares the one array, so no-allocation solves on one device must
+ * not overlap (they race on it). */
+#define PMF_NOALLOC_BYTES ((size_t)64 << 20)
+int pmf_solve_batch_noalloc(pmf_handle *h, const pmf_instance *inst, int32_t n_inst, int64_t *flows_out,
+                            int32_t *status_out);
 
 /* pmf_solve_batch that returns once the solve is set up: the superstep loop
  * (launches on the handle's stream and the host polls between them) runs on a

@@ -12,6 +12,7 @@
 #include <functional>
 #include <atomic>
 #include <map>
+#include <mutex>
 #include <new>
 #include <numeric>
 #include <thread>
@@ -156,6 +157,32 @@ class Pool {
     std::map<size_t, size_t> free_;
 };
 
+// The fixed device array of the no-allocation solves: every device the
+// library runs on holds one until the process ends, shared by every handle
+// on that device.  Host code reaches it only through the address that
+// hipGetSymbolAddress returns for the current device.
+static __device__ __align__(256) unsigned char scratch[PMF_NOALLOC_BYTES];
+
+constexpr int kMaxDevices = 64;
+std::mutex scratch_mu;
+char *scratch_ptr[kMaxDevices] = {};
+
+// Device address of the current device's scratch array (looked up once per
+// device, with that device current); null on failure.
+char *scratch_address(int dev) {
+    if (dev < 0 || dev >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lock(scratch_mu);
+    if (!scratch_ptr[dev]) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess) {
+            (void)hipGetLastError();
+            return nullptr;
+        }
+        scratch_ptr[dev] = (char *)p;
+    }
+    return scratch_ptr[dev];
+}
+
 struct Slot {
     bool live = false;      // admitted and not released
     bool finished = false;  // completion seen by the host
@@ -227,6 +254,7 @@ struct pmf_handle {
     // the pinned buffers, so that the solve allocates nothing)
     char *base = nullptr;
     bool ext = false;
+    char *scratch_dev = nullptr;
     std::vector<int32_t> host_ring;
     std::vector<InstState> host_state;
     std::vector<int32_t> user_first, user_L;
@@ -763,6 +791,7 @@ const char *pmf_strerror(int code) {
         case PMF_ENOTSOLVED: return "no completed solve for this instance and lambda";
         case PMF_ERANGE: return "instance or lambda index out of range";
         case PMF_EBUSY: return "no free slot or pool memory";
+        case PMF_ELIMIT: return "batch does not fit the fixed buffer of pmf_solve_batch_noalloc";
         default: return "unknown status";
     }
 }
@@ -805,6 +834,7 @@ int pmf_create(const pmf_options *opt, void *stream, void *workspace, size_t ws_
         pmf_destroy(h);
         return PMF_EDEVICE;
     }
+    h->scratch_dev = scratch_address(h->device);
     if (o.persist_tiles > 0) {
         int cus = 0;
         if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, h->device) != hipSuccess) cus = 0;
@@ -1069,6 +1099,17 @@ int pmf_query_done(pmf_handle *h, int32_t *done) {
     if (!h || !done) return PMF_EINVAL;
     *done = h->async_done.load();
     return PMF_OK;
+}
+
+int pmf_solve_batch_noalloc(pmf_handle *h, const pmf_instance *inst, int32_t n_inst, int64_t *flows_out,
+                            int32_t *status_out) {
+    if (!h) return PMF_EINVAL;
+    (void)finish_async(h);
+    // timing mode keeps events and counters of its own: not available here
+    if (h->opt.timing != 0) return PMF_EINVAL;
+    if (!h->scratch_dev) return PMF_EDEVICE;
+    const int rc = solve_batch(h, inst, n_inst, flows_out, status_out, h->scratch_dev, PMF_NOALLOC_BYTES);
+    return rc == PMF_ENOMEM ? PMF_ELIMIT : rc;
 }
 
 int pmf_extract_cut(pmf_handle *h, int32_t inst, int32_t lambda_idx, uint8_t *mask_out) {

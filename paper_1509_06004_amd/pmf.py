@@ -22,7 +22,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libpmf.so")
 
 PMF_OK, PMF_EINVAL, PMF_EOVERFLOW, PMF_ENOMEM, PMF_EDEVICE = 0, 1, 2, 3, 4
-PMF_ETIMEOUT, PMF_ENOTSOLVED, PMF_ERANGE, PMF_EBUSY = 5, 6, 7, 8
+PMF_ETIMEOUT, PMF_ENOTSOLVED, PMF_ERANGE, PMF_EBUSY, PMF_ELIMIT = 5, 6, 7, 8, 9
+PMF_NOALLOC_BYTES = 64 << 20
 INF = 1 << 30
 
 
@@ -131,6 +132,7 @@ def load_library() -> ctypes.CDLL:
         "pmf_create": (ctypes.c_int, [ctypes.POINTER(Options), P, P, ctypes.c_size_t,
                                       ctypes.POINTER(P)]),
         "pmf_solve_batch": (ctypes.c_int, [P, ctypes.POINTER(InstanceC), ctypes.c_int32, P, P]),
+        "pmf_solve_batch_noalloc": (ctypes.c_int, [P, ctypes.POINTER(InstanceC), ctypes.c_int32, P, P]),
         "pmf_solve_batch_async": (ctypes.c_int, [P, ctypes.POINTER(InstanceC), ctypes.c_int32, P, P]),
         "pmf_wait": (ctypes.c_int, [P]),
         "pmf_query_done": (ctypes.c_int, [P, ctypes.POINTER(ctypes.c_int32)]),
@@ -192,6 +194,12 @@ def pmf_solve_batch(handle, instances: Sequence[InstanceC], flows_ptr: int, stat
     arr = (InstanceC * len(instances))(*instances)
     return load_library().pmf_solve_batch(handle, arr, len(instances), ctypes.c_void_p(flows_ptr),
                                           ctypes.c_void_p(status_ptr))
+
+
+def pmf_solve_batch_noalloc(handle, instances: Sequence[InstanceC], flows_ptr: int, status_ptr: int) -> int:
+    arr = (InstanceC * len(instances))(*instances)
+    return load_library().pmf_solve_batch_noalloc(handle, arr, len(instances), ctypes.c_void_p(flows_ptr),
+                                                  ctypes.c_void_p(status_ptr))
 
 
 def pmf_solve_batch_async(handle, instances: Sequence[InstanceC], flows_ptr: int, status_ptr: int) -> int:
