@@ -222,9 +222,9 @@ struct pmf_handle {
     int graph_S = 0;
     pmf_stats stats;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;  // bracket every launch group (device time)
-    // timing mode: four events per superstep of a host round (after the
-    // compaction, the sweeps, the passes and the control kernel) and a device
-    // buffer for the list sizes of each of those supersteps
+    // timing mode: six events per superstep of a host round (start and end
+    // of the tile-work or sweep kernels, of the pass kernels, of the control
+    // kernel) and a device buffer for the list sizes of each of those supersteps
     std::vector<hipEvent_t> kev;
     int32_t *trace_lists = nullptr;
     int trace_cap = 0;
@@ -536,7 +536,7 @@ int ensure_timing(pmf_handle *h, int steps) {
         }
         if (hipMemsetAsync(h->kpx, 0, 16 * sizeof(int64_t), h->stream) != hipSuccess) return PMF_EDEVICE;
     }
-    while ((int)h->kev.size() < 4 * steps) {
+    while ((int)h->kev.size() < 6 * steps) {
         hipEvent_t e = nullptr;
         if (hipEventCreate(&e) != hipSuccess) return PMF_EDEVICE;
         h->kev.push_back(e);
@@ -565,11 +565,11 @@ int read_kernel_events(pmf_handle *h, int steps) {
         return PMF_EDEVICE;
     const bool split = h->opt.timing == 2;
     for (int i = 0; i < steps; ++i) {
-        hipEvent_t *ev = h->kev.data() + 4 * i;
+        hipEvent_t *ev = h->kev.data() + 6 * i;
         float a = 0.f, b = 0.f, c = 0.f;
         if (hipEventElapsedTime(&a, ev[0], ev[1]) != hipSuccess) a = 0.f;
-        if (hipEventElapsedTime(&b, ev[1], ev[2]) != hipSuccess) b = 0.f;
-        if (hipEventElapsedTime(&c, ev[2], ev[3]) != hipSuccess) c = 0.f;
+        if (split && hipEventElapsedTime(&b, ev[2], ev[3]) != hipSuccess) b = 0.f;
+        if (hipEventElapsedTime(&c, ev[4], ev[5]) != hipSuccess) c = 0.f;
         const int64_t na = (int64_t)(a * 1e6), nb = (int64_t)(b * 1e6), nc = (int64_t)(c * 1e6);
         const int64_t sw = split ? na : 0, ps = split ? nb : 0, work = na + nb;
         h->stats.work_ns += work;
@@ -647,7 +647,7 @@ int run_steps(pmf_handle *h, int steps, std::vector<int> *finished, int persist_
                     Pi.trace_lists = h->trace_lists + 4 * i;
                     Pi.kpx = h->kpx;
                 }
-                const int ns = launch_superstep(Pi, h->tw, s, timing ? (void *const *)(h->kev.data() + 4 * i) : nullptr,
+                const int ns = launch_superstep(Pi, h->tw, s, timing ? (void *const *)(h->kev.data() + 6 * i) : nullptr,
                                                 h->opt.timing == 2);
                 if (ns < 0) return PMF_EDEVICE;
                 h->stats.work_launches += ns;

@@ -141,11 +141,12 @@ enum PxKind : int { kPxSweep = 0, kPxRelabel, kPxCut, kPxInit, kPxOrient, kPxIni
 
 // Enqueue one superstep (compaction, tile work and control kernels) over
 // every tile (defined in pmf_kernels.hip).  The sweeps and the relabel / cut
-// / init passes of a connectivity share one launch.  With `events` (4
-// hipEvent_t), events 0..3 are recorded before the tile-work launches, after
-// them (with `split`: after the sweeps, the sweeps and passes then being
-// separate launches), after the passes and after the control kernel.  Returns the number of tile-work kernels launched, or -1 on
-// a launch error.
+// / init passes of a connectivity share one launch.  With `events` (6
+// hipEvent_t) the launches record their kernels' own start and end: events
+// 0 / 1 the tile work (with `split`: the sweeps, the sweeps and passes then
+// being separate launches), 2 / 3 the passes (split only), 4 / 5 the control
+// kernel.  Returns the number of tile-work kernels launched, or -1 on a
+// launch error.
 int launch_superstep(const StepParams &p, int tile_w, void *stream, void *const *events = nullptr,
                      bool split = false);
 

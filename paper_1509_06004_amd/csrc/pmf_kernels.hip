@@ -34,6 +34,7 @@
 // Correctness never depends on labels being valid between global relabels:
 // the bookkeeping is exact integer arithmetic and termination is certified by
 // an exact relabel on a quiescent state.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -618,6 +619,7 @@ __device__ void relabel_tile(const StepParams &P, const InstDesc &D, InstState *
     int32_t *sh_d = lds;              // [HALO] labels
     int32_t *sh_in = lds + G::HALO;   // first pass: inflow folded into each tile cell
     int32_t *sh_ib = lds + 2 * G::HALO;  // first pass: arcs whose residual the inflow raised
+    int32_t *sh_rm = lds + 3 * G::HALO;  // residual bits of each tile cell (relaxation rounds)
     // Every global load is issued before any is used (cells outside the
     // image read a clamped in-image address and take the defaults): the
     // pixels' residual masks (and labels after the first pass), one halo cell
@@ -688,6 +690,7 @@ __device__ void relabel_tile(const StepParams &P, const InstDesc &D, InstState *
         d[j] = !valid[j] ? kHInf : first ? ((rm[j] & kRtBit) ? 1 : kHInf) : d[j];
         d0[j] = d[j];
         sh_d[(ly0 + j * RPI + 1) * HW + lx + 1] = d[j];
+        sh_rm[(ly0 + j * RPI + 1) * HW + lx + 1] = (int32_t)rm[j];
     }
     if (tid < G::RING)
         sh_d[hy * HW + hx] = !hin ? kHInf : first ? ((hv & kRtBit) ? 1 : kHInf) : hv;
@@ -707,37 +710,76 @@ __device__ void relabel_tile(const StepParams &P, const InstDesc &D, InstState *
     // rounds.  Labels only decrease and every value read is an upper bound of
     // the true distance, so rounds need no barrier between them; a window in
     // which no thread changed a label proves the local fixed point.
+    // The rounds work on horizontal strips: thread t owns the 4 consecutive
+    // cells (4 (t mod TW/4) .. + 3, t div (TW/4)) of the tile, so the
+    // neighbours inside its strip are registers and a round reads only the
+    // strip's left and right cells and the rows above and below it from LDS
+    // (10 reads at K = 4, 14 at K = 8, against 4K for four scattered cells).
+    // The residual bits of the strip come from the LDS copy made below.
+    constexpr int SPR = TW / 4;  // strips per row
+    const int sy = tid / SPR, sx = 4 * (tid % SPR);
+    const int sc = (sy + 1) * HW + sx + 1;  // LDS cell of the strip's first pixel
+    uint32_t srm[4];
+    int sd[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        srm[j] = (uint32_t)sh_rm[sc + j];
+        sd[j] = sh_d[sc + j];
+    }
     int ch = 0;
     for (int it = 0; it < P.local_bfs_iters; ++it) {
-        int v[PPT][K];
+        // neighbours: up row (sx - 1 .. sx + 4), down row, left and right cells
+        int up[6], dn[6];
+        const int lf = sh_d[sc - 1], rg = sh_d[sc + 4];
 #pragma unroll
-        for (int j = 0; j < PPT; ++j) {
-            const int c = (ly0 + j * RPI + 1) * HW + lx + 1;
-#pragma unroll
-            for (int k = 0; k < K; ++k) v[j][k] = sh_d[c + DYk(k) * HW + DXk(k)];
+        for (int i = 0; i < 6; ++i) {
+            if (K == 4 && (i == 0 || i == 5)) {
+                up[i] = dn[i] = kHInf;  // corners: diagonal arcs only
+                continue;
+            }
+            up[i] = sh_d[sc - HW - 1 + i];
+            dn[i] = sh_d[sc + HW - 1 + i];
         }
         // branch-free: every label is rewritten (only its owner writes it) as
         // min(d, 1 + min over residual arcs of the neighbour's label), taken
         // as 1 + min(d - 1, neighbour label or H_INF - 1 where the arc is
         // saturated): one select per arc; a result never exceeds H_INF
+        int nd[4];
 #pragma unroll
-        for (int j = 0; j < PPT; ++j) {
-            int mn = d[j] - 1;
+        for (int j = 0; j < 4; ++j) {
+            // the neighbour in direction k of strip cell j (old values: Jacobi)
+            int nb[8];
+            nb[0] = j < 3 ? sd[j + 1] : rg;  // (+1, 0)
+            nb[1] = j > 0 ? sd[j - 1] : lf;  // (-1, 0)
+            nb[2] = dn[j + 1];               // (0, +1)
+            nb[3] = up[j + 1];               // (0, -1)
+            nb[4] = dn[j + 2];               // (+1, +1)
+            nb[5] = up[j];                   // (-1, -1)
+            nb[6] = dn[j];                   // (-1, +1)
+            nb[7] = up[j + 2];               // (+1, -1)
+            int mn = sd[j] - 1;
 #pragma unroll
             for (int k = 0; k < K; ++k) {
-                const int vk = ((rm[j] >> k) & 1u) ? v[j][k] : kHInf - 1;
+                const int vk = ((srm[j] >> k) & 1u) ? nb[k] : kHInf - 1;
                 mn = vk < mn ? vk : mn;
             }
-            const int nd = mn + 1;
-            ch |= nd < d[j];
-            d[j] = nd;
-            sh_d[(ly0 + j * RPI + 1) * HW + lx + 1] = nd;
+            nd[j] = mn + 1;
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            ch |= nd[j] < sd[j];
+            sd[j] = nd[j];
+            sh_d[sc + j] = nd[j];
         }
         if ((it & 3) == 3 || it + 1 == P.local_bfs_iters) {
             if (!__syncthreads_or(ch)) break;
             ch = 0;
         }
     }
+    __syncthreads();
+    // back to the load layout
+#pragma unroll
+    for (int j = 0; j < PPT; ++j) d[j] = sh_d[(ly0 + j * RPI + 1) * HW + lx + 1];
     if (round + 1 == rounds) break;
     // publish, then take the neighbours' newer labels
 #pragma unroll
@@ -1276,7 +1318,7 @@ __device__ void tile_work(const StepParams &P, int ws, int wp, int32_t *lds, int
 // that the default build carries none of its registers).
 template <int K, int TW, int TH, bool GAP>
 __global__ __launch_bounds__(kThreads) void k_step(StepParams P, int ws, int wp) {
-    __shared__ int32_t lds[(3 + K) * (TW + 2) * (TH + 2)];  // sweep layout; passes use 3 planes
+    __shared__ int32_t lds[(3 + K) * (TW + 2) * (TH + 2)];  // sweep layout; passes use 4 planes
     __shared__ int s_red[4];
     __shared__ unsigned long long s_sum;
     tile_work<K, TW, TH, GAP>(P, ws, wp, lds, s_red, &s_sum);
@@ -1548,41 +1590,62 @@ int launch_finalize(const int32_t *sub_status, const int64_t *meta, int n_user, 
 // (a workgroup with no item left exits at once).
 static int list_grid(int tiles) { return 8 * ((std::min(tiles, 4096) + 7) / 8); }
 
-// One tile-work launch of connectivity K over sweep list ws and pass list wp.
+// One tile-work launch of connectivity K over sweep list ws and pass list wp
+// (no launch when the work list has no tile of that connectivity).  With
+// start / stop events the launch records the kernel's own start and end
+// (hipExtLaunchKernel), so timing excludes the dispatch gaps around it.
 template <int K, int TW, int TH>
-static void step_launch(const StepParams &p, hipStream_t s, int ws, int wp) {
+static bool step_launch(const StepParams &p, hipStream_t s, int ws, int wp, hipEvent_t start = nullptr,
+                        hipEvent_t stop = nullptr) {
     const int tiles = K == 4 ? p.t4_count : p.t8_count;
-    if (!tiles) return;
-    if (p.gap)
-        hipLaunchKernelGGL((k_step<K, TW, TH, true>), dim3(list_grid(tiles)), dim3(kThreads), 0, s, p, ws, wp);
-    else
-        hipLaunchKernelGGL((k_step<K, TW, TH, false>), dim3(list_grid(tiles)), dim3(kThreads), 0, s, p, ws, wp);
+    if (!tiles) return false;
+    const dim3 g(list_grid(tiles)), b(kThreads);
+    const bool timed = start || stop;  // plain launches otherwise (they are also captured into graphs)
+    if (p.gap) {
+        if (timed)
+            hipExtLaunchKernelGGL((k_step<K, TW, TH, true>), g, b, 0, s, start, stop, 0, p, ws, wp);
+        else
+            hipLaunchKernelGGL((k_step<K, TW, TH, true>), g, b, 0, s, p, ws, wp);
+    } else {
+        if (timed)
+            hipExtLaunchKernelGGL((k_step<K, TW, TH, false>), g, b, 0, s, start, stop, 0, p, ws, wp);
+        else
+            hipLaunchKernelGGL((k_step<K, TW, TH, false>), g, b, 0, s, p, ws, wp);
+    }
+    return true;
+}
+
+// The tile-work launches of one kind (both connectivities): the first records
+// `start`, the last `stop`.
+template <int TW, int TH>
+static int step_pair(const StepParams &p, hipStream_t s, int ws4, int wp4, int ws8, int wp8, hipEvent_t start,
+                     hipEvent_t stop) {
+    const bool a = p.t4_count > 0, b = p.t8_count > 0;
+    int n = 0;
+    if (a) n += step_launch<4, TW, TH>(p, s, ws4, wp4, start, b ? nullptr : stop);
+    if (b) n += step_launch<8, TW, TH>(p, s, ws8, wp8, a ? nullptr : start, stop);
+    return n;
 }
 
 template <int TW, int TH>
 static int launch_tw(const StepParams &p, hipStream_t s, void *const *ev, bool split) {
     const dim3 block(kThreads);
-    int n = 0;
     if (p.ntiles == 0) return 0;
+    hipEvent_t *e = (hipEvent_t *)ev;
     hipLaunchKernelGGL(k_compact, dim3(p.nwl), block, 0, s, p);
-    if (ev) (void)hipEventRecord((hipEvent_t)ev[0], s);
+    int n;
     if (split) {
         // sweeps and passes as separate launches (timed apart)
-        step_launch<4, TW, TH>(p, s, 0, -1);
-        step_launch<8, TW, TH>(p, s, 1, -1);
-        if (ev) (void)hipEventRecord((hipEvent_t)ev[1], s);
-        step_launch<4, TW, TH>(p, s, -1, 2);
-        step_launch<8, TW, TH>(p, s, -1, 3);
-        n = 2 * ((p.t4_count > 0) + (p.t8_count > 0));
+        n = step_pair<TW, TH>(p, s, 0, -1, 1, -1, e ? e[0] : nullptr, e ? e[1] : nullptr);
+        n += step_pair<TW, TH>(p, s, -1, 2, -1, 3, e ? e[2] : nullptr, e ? e[3] : nullptr);
     } else {
-        step_launch<4, TW, TH>(p, s, 0, 2);
-        step_launch<8, TW, TH>(p, s, 1, 3);
-        n = (p.t4_count > 0) + (p.t8_count > 0);
-        if (ev) (void)hipEventRecord((hipEvent_t)ev[1], s);
+        n = step_pair<TW, TH>(p, s, 0, 2, 1, 3, e ? e[0] : nullptr, e ? e[1] : nullptr);
     }
-    if (ev) (void)hipEventRecord((hipEvent_t)ev[2], s);
-    hipLaunchKernelGGL(k_control, dim3((p.nwl + kThreads - 1) / kThreads), block, 0, s, p);
-    if (ev) (void)hipEventRecord((hipEvent_t)ev[3], s);
+    const dim3 cg((p.nwl + kThreads - 1) / kThreads);
+    if (e)
+        hipExtLaunchKernelGGL(k_control, cg, block, 0, s, e[4], e[5], 0, p);
+    else
+        hipLaunchKernelGGL(k_control, cg, block, 0, s, p);
     return n;
 }
 
