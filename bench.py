@@ -132,7 +132,7 @@ def verify_all(insts, flows, masks, results):
     return bad
 
 
-def roofline(dev, overrides: dict, K: int, pmf, torch) -> dict:
+def roofline(dev, overrides: dict, K: int, pmf, torch, split: bool = True) -> dict:
     """Timing-mode solve: HIP events around every tile-work launch (and every
     persistent launch) on the solver's stream, no host round trip between the
     supersteps of a poll, pixel visits counted per launch kind."""
@@ -146,7 +146,8 @@ def roofline(dev, overrides: dict, K: int, pmf, torch) -> dict:
     bi = impl_bytes_per_px(K)
     kpx = st["kernel_px"]
     kernels = {}
-    step_name = "k_step<%d, %d, %d, %s>" % (K, tw, 1024 // tw, "true" if overrides.get("gap") else "false")
+    # timing mode launches the tile-work kernel under the symbol k_step<..., true> (same code)
+    step_name = "k_step<%d, %d, %d, %s, true>" % (K, tw, 1024 // tw, "true" if overrides.get("gap") else "false")
     if st["work_launches"]:
         n = st["work_launches"]
         byt = kind_bytes(kpx[:7], b)
@@ -167,11 +168,31 @@ def roofline(dev, overrides: dict, K: int, pmf, torch) -> dict:
     dom = max(kernels, key=lambda k: kernels[k]["total_ms"])
     d = kernels[dom]
     achieved = d["alg_bytes_per_launch"] / (d["avg_launch_us"] * 1e-6) / 1e9
-    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": dom,
-            "avg_launch_us": d["avg_launch_us"], "alg_bytes_per_launch": d["alg_bytes_per_launch"],
-            "launches": d["launches"], "bytes_per_px": b, "impl_bytes_per_px": bi, "kernels": kernels,
-            "supersteps": st["supersteps"], "device_ms": round(st["device_ns"] / 1e6, 3)}
+    out = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": dom,
+           "avg_launch_us": d["avg_launch_us"], "alg_bytes_per_launch": d["alg_bytes_per_launch"],
+           "launches": d["launches"], "bytes_per_px": b, "impl_bytes_per_px": bi, "kernels": kernels,
+           "supersteps": st["supersteps"], "device_ms": round(st["device_ns"] / 1e6, 3)}
+    if not split:
+        return out
+    # timing mode 2: sweeps and passes as separate launches, each kind timed
+    # apart (its own kernel start and end), for the sweep-only bandwidth
+    sp = pmf.Solver(timing=2, **dict(overrides, persist_tiles=0))
+    sp.solve(dev)
+    torch.cuda.synchronize()
+    ss = sp.stats()
+    sp.close()
+    spx = ss["kernel_px"][:7]
+    sweep_b = spx[0] * b["sweep"]
+    pass_b = kind_bytes(spx, b) - sweep_b
+    tot = max(ss["sweep_ns"] + ss["pass_ns"] + ss["control_ns"], 1)
+    out["split"] = {"sweep_GBs": round(sweep_b / max(ss["sweep_ns"], 1), 1),
+                    "sweep_frac": round(sweep_b / max(ss["sweep_ns"], 1) / HBM_PEAK_GBS, 4),
+                    "pass_GBs": round(pass_b / max(ss["pass_ns"], 1), 1),
+                    "sweep_ms": round(ss["sweep_ns"] / 1e6, 3), "pass_ms": round(ss["pass_ns"] / 1e6, 3),
+                    "control_ms": round(ss["control_ns"] / 1e6, 3),
+                    "sweep_share": round(ss["sweep_ns"] / tot, 3), "pass_share": round(ss["pass_ns"] / tot, 3)}
+    return out
 
 
 def attach_profile(roof: dict, path: str) -> None:
@@ -281,6 +302,18 @@ def run_serving(qps: float, seconds: float, warmup: float, templates: int, infli
     return out
 
 
+def leg_options(insts, log, cli: dict) -> dict:
+    """Options for a leg of the bench: the tuner cache's entry for that
+    workload class on this device if there is one, else library defaults;
+    command-line overrides on top."""
+    _, opts, _ = tuned_options(insts, log)
+    out = dict(opts or {})
+    out.update(cli)
+    if "tile_w" in out:
+        out["tile_h"] = 1024 // out["tile_w"]
+    return out
+
+
 def tuned_options(insts, log) -> tuple:
     """Knob values of the committed tuner cache for this workload class and
     device, if present."""
@@ -314,6 +347,9 @@ def main():
     ap.add_argument("--no-roofline", action="store_true")
     ap.add_argument("--no-breakpoints", action="store_true")
     ap.add_argument("--no-copy", action="store_true")
+    ap.add_argument("--no-split", action="store_true",
+                    help="skip the split-timing solve (for profiled runs: the timed tile-work symbol then "
+                         "covers exactly the launches of the fused timing solve)")
     ap.add_argument("--serve-qps", type=float, action="append", default=[],
                     help="serving rates (default 50, 200, 800)")
     ap.add_argument("--serve-seconds", type=float, default=60.0)
@@ -355,7 +391,7 @@ def main():
         key = T.workload_key(insts, torch.cuda.get_device_name(0))
         cache = T.load_cache(T.PACKAGE_CACHE)
         cache[key] = {"options": res["options"], "seconds": res["seconds"], "trials": len(res["trials"]),
-                      "tuned_on": "500x375 4-connected, 25 seeds x 20 lambdas"}
+                      "confirmed": res["confirmed"], "tuned_on": "500x375 4-connected, 25 seeds x 20 lambdas"}
         T.save_cache(cache, T.PACKAGE_CACHE)
         tuned = {"source": "tuned in this run", "key": key, "options": res["options"],
                  "tune_seconds": round(time.perf_counter() - t0, 1), "trials": len(res["trials"])}
@@ -366,11 +402,17 @@ def main():
             overrides = opts
             from paper_1509_06004_amd import tune as T
             tuned = {"source": os.path.relpath(T.PACKAGE_CACHE, ROOT), "key": key, "options": opts}
+    cli = {}
     for kv in args.opt:
         k, v = kv.split("=", 1)
-        overrides[k] = int(v)
+        cli[k] = int(v)
+    overrides.update(cli)
     if "tile_w" in overrides:
         overrides["tile_h"] = 1024 // overrides["tile_w"]
+
+    def other(leg_insts):
+        # the other legs use options tuned for their own workload class (or the defaults)
+        return cli if args.defaults else leg_options(leg_insts, log, cli)
 
     solver = pmf.Solver(**overrides)
     torch.cuda.synchronize()
@@ -423,7 +465,7 @@ def main():
         log("with transfers: %s" % out["with_transfers"])
 
     if not args.no_roofline:
-        roof = roofline(dev, overrides, 4, pmf, torch)
+        roof = roofline(dev, overrides, 4, pmf, torch, split=not args.no_split)
         attach_profile(roof, os.path.join(ROOT, "profiles", "k_step_500x375_4conn.txt"))
         if not args.no_copy:
             roof["copy"] = copy_bandwidth(torch)
@@ -433,7 +475,9 @@ def main():
     # plain: one instance (one seed's 20-lambda warm chain) per call, same
     # kernels, same GPU, same run
     if not args.no_plain:
-        psolver = pmf.Solver(**dict(overrides, lambda_chunk=max(i.L for i in insts)))
+        # library defaults (knobs tuned for the packed batch, e.g. the
+        # persistent launch, can slow a lone chain down)
+        psolver = pmf.Solver(lambda_chunk=max(i.L for i in insts))
         psolver.solve([dev[0]])
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -447,7 +491,8 @@ def main():
         plain = n_solves / pt
         psolver.close()
         out["plain"] = {"value": round(plain, 2), "unit": "solves/s",
-                        "form": "one instance (one seed's 20-lambda warm chain) per pmf_solve_batch call",
+                        "form": "one instance (one seed's 20-lambda warm chain) per pmf_solve_batch call, "
+                                "library default options",
                         "chain_latency_ms": {"p50": round(float(np.percentile(plain_lat, 50)) * 1e3, 2),
                                              "p99": round(float(np.percentile(plain_lat, 99)) * 1e3, 2)}}
         out["batched_over_plain"] = round(value / plain, 2)
@@ -456,20 +501,23 @@ def main():
     if not args.no_8conn:
         insts8 = workload.config2(K=8)
         dev8 = pmf.to_device(insts8)
-        solver.solve(dev8)
+        o8 = other(insts8)
+        solver8 = pmf.Solver(**o8)
+        solver8.solve(dev8)
         torch.cuda.synchronize()
         t8 = []
         for _ in range(3):
             t0 = time.perf_counter()
-            solver.solve(dev8)
+            solver8.solve(dev8)
             torch.cuda.synchronize()
             t8.append(time.perf_counter() - t0)
-        st8 = solver.stats()
+        st8 = solver8.stats()
+        solver8.close()
         c8 = {"value": round(n_solves * len(t8) / sum(t8), 2), "unit": "solves/s",
-              "workload": "same, 8-connected (diagonals / sqrt 2)",
+              "workload": "same, 8-connected (diagonals / sqrt 2)", "options": o8 or "library defaults",
               "alg_GB_per_step": round(stat_bytes(st8, bytes_per_px(8)) / 1e9, 3)}
         if not args.no_roofline:
-            r8 = roofline(dev8, overrides, 8, pmf, torch)
+            r8 = roofline(dev8, o8, 8, pmf, torch, split=False)
             c8["roofline"] = {k: r8[k] for k in ("kernel", "achieved", "frac", "avg_launch_us",
                                                  "alg_bytes_per_launch", "launches")}
         out["config_8conn"] = c8
@@ -482,7 +530,8 @@ def main():
         gen = time.perf_counter() - t0
         dev3 = pmf.to_device(insts3)
         n3 = sum(i.L for i in insts3)
-        s3 = pmf.Solver(**overrides)
+        o3 = other(insts3)
+        s3 = pmf.Solver(**o3)
         s3.solve(dev3)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -497,6 +546,7 @@ def main():
         s3.close()
         out["config3"] = {"value": round(n3 / t3, 2), "unit": "solves/s", "solves": n3, "instances": len(insts3),
                           "ms": round(t3 * 1e3, 2), "all_ok": ok3, "generate_s": round(gen, 1),
+                          "options": o3 or "library defaults",
                           "alg_GB": round(alg3 / 1e9, 3),
                           "alg_GBs_over_device_time": round(alg3 / max(stats3["device_ns"], 1), 1),
                           "workload": "256 images 64..640 x 64..480, K 4 or 8, 8..48 regions, 1..16 seeds "
@@ -507,7 +557,7 @@ def main():
     if not args.no_breakpoints:
         # the second workload on the same kernels: every lambda in 1..2000 at
         # which the minimal source set of one seed's instance changes
-        bsolver = pmf.Solver(**overrides)
+        bsolver = pmf.Solver(**cli)
         binst = pmf.to_device([insts[0]])[0]
         pmf.pmf_parametric(bsolver.handle, binst, 1, 2000)
         torch.cuda.synchronize()
@@ -523,7 +573,7 @@ def main():
 
     if not args.no_serve:
         rates = args.serve_qps or [50.0, 200.0, 800.0]
-        persist = {k: overrides[k] for k in ("persist_tiles", "persist_wgs", "gap") if k in overrides}
+        persist = {k: cli[k] for k in ("persist_tiles", "persist_wgs", "gap") if k in cli}
         out["serving"] = [run_serving(q, args.serve_seconds, args.serve_warmup, args.serve_templates,
                                       args.serve_inflight, log, args.serve_chunk, persist) for q in rates]
         sv = out["serving"][0]

@@ -216,6 +216,7 @@ struct pmf_handle {
     std::vector<int> free_slots;  // stack, lowest id on top
     int32_t ring_seen = 0;
     bool wl_dirty = true;
+    int64_t wl_finished = 0;  // finished instances still in the work list
     int64_t epoch_steps = 0;  // steps run since the work list last changed
     StepParams P;
     hipGraphExec_t graph = nullptr;
@@ -424,6 +425,7 @@ int rebuild_worklist(pmf_handle *h) {
     }
     drop_graph(h);
     h->wl_dirty = false;
+    h->wl_finished = 0;
     h->epoch_steps = 0;
     return PMF_OK;
 }
@@ -750,8 +752,12 @@ int run_steps(pmf_handle *h, int steps, std::vector<int> *finished, int persist_
         h->stats.bfs_passes += x.passes;
         if (finished) finished->push_back(id);
     }
-    // finished instances leave the work list at the next step
-    h->wl_dirty = true;
+    // Finished instances stay in the work list (their compaction and control
+    // return at once), so a completion alone neither rebuilds the list nor
+    // drops the captured graph; the list is rebuilt once they are half of it
+    // (and whenever instances are admitted or cancelled).
+    h->wl_finished += (int64_t)got.size();
+    if (2 * h->wl_finished > (int64_t)P.nwl) h->wl_dirty = true;
     return PMF_OK;
 }
 

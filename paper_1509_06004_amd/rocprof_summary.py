@@ -65,7 +65,7 @@ def main():
     ap.add_argument("--stats")
     ap.add_argument("--fetch")
     ap.add_argument("--write")
-    ap.add_argument("--kernel", default="void pmf::k_step<4, 32, 32, false>")
+    ap.add_argument("--kernel", default="void pmf::k_step<4, 32, 32, false, true>")
     ap.add_argument("--calib-bytes", type=int, default=1 << 30)
     ap.add_argument("--command", action="append", default=[], help="command line that produced a database")
     ap.add_argument("--out", required=True)

@@ -101,11 +101,17 @@ def _same(a, b) -> bool:
     return bool((fa == fb).all()) and all(bool((x == y).all()) for x, y in zip(la, lb)) and bool((sa == sb).all())
 
 
-def tune(dev_insts: Sequence["pmf.DeviceInstance"], start: Optional[Dict[str, int]] = None, repeats: int = 2,
-         space: Optional[Dict[str, List[int]]] = None, log=None) -> Dict[str, object]:
+def tune(dev_insts: Sequence["pmf.DeviceInstance"], start: Optional[Dict[str, int]] = None, repeats: int = 3,
+         space: Optional[Dict[str, List[int]]] = None, log=None, margin: float = 0.03,
+         confirm: int = 4) -> Dict[str, object]:
     """Coordinate descent over the knobs on `dev_insts` (device instances).
+    A candidate replaces the current point only when it is faster by more
+    than `margin` (timings of a solve vary by a few percent from run to run);
+    at the end the chosen point and the starting point are timed `confirm`
+    more times, interleaved, and the starting point is kept unless the chosen
+    one has the lower median.
     Returns {"options": best knob values, "seconds": its time, "trials": [...],
-    "rejected": [points whose results differed]}."""
+    "rejected": [points whose results differed], "confirmed": {...}}."""
     space = dict(SPACE if space is None else space)
     d = pmf.pmf_default_options()
     cur = {k: int(getattr(d, k)) for k in KNOBS}
@@ -129,9 +135,23 @@ def tune(dev_insts: Sequence["pmf.DeviceInstance"], start: Optional[Dict[str, in
                 continue
             if log:
                 log("tune %s=%s: %.1f ms" % (knob, v, t * 1e3))
-            if t < t_best:
+            if t < t_best * (1.0 - margin):
                 t_best, cur = t, cand
-    return {"options": cur, "seconds": t_best, "trials": trials, "rejected": rejected}
+    first = trials[0]
+    start_pt = {k: first[k] for k in KNOBS}
+    confirmed = None
+    if cur != start_pt and confirm > 0:
+        ta, tb = [], []
+        for _ in range(confirm):
+            ta.append(_run(dev_insts, start_pt, 1)[0])
+            tb.append(_run(dev_insts, cur, 1)[0])
+        ma, mb = sorted(ta)[len(ta) // 2], sorted(tb)[len(tb) // 2]
+        confirmed = {"start_ms": round(ma * 1e3, 2), "chosen_ms": round(mb * 1e3, 2)}
+        if log:
+            log("tune confirm: start %.1f ms, chosen %.1f ms (medians of %d)" % (ma * 1e3, mb * 1e3, confirm))
+        if mb >= ma:
+            cur, t_best = start_pt, ma
+    return {"options": cur, "seconds": t_best, "trials": trials, "rejected": rejected, "confirmed": confirmed}
 
 
 def load_cache(path: str = DEFAULT_CACHE) -> Dict[str, dict]:
