@@ -107,6 +107,10 @@ typedef struct pmf_options {
                                 /*   host polls (0 = never; not with gap = 1)       */
     int32_t persist_wgs;        /* workgroups of that launch (0 = one per compute   */
                                 /*   unit; at most what the device holds at once)   */
+    int32_t tail_sweep_exchanges; /* short supersteps: a sweep visit hands its      */
+                                /*   cross-tile pushes to the neighbour tiles and   */
+                                /*   takes theirs this many times during the visit  */
+                                /*   (0 = only at its end)                          */
 } pmf_options;
 
 /* One (image, seed) problem and its lambda schedule.  All pointers are device

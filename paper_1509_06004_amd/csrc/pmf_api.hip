@@ -45,6 +45,7 @@ bool valid_options(const pmf_options &o) {
     if (o.orientation < kOrientAsGiven || o.orientation > kOrientExchange) return false;
     if (o.gap != 0 && o.gap != 1) return false;
     if (o.persist_tiles < 0 || o.persist_wgs < 0) return false;
+    if (o.tail_sweep_exchanges < 0 || o.tail_sweep_exchanges > 64) return false;
     if (o.tail_tiles > 0 && (o.tail_inner_iters < 1 || o.tail_inner_iters > 4096 ||
                              o.tail_exchange_rounds < 1 || o.tail_exchange_rounds > 64))
         return false;
@@ -365,6 +366,7 @@ int open_session(pmf_handle *h, int slots, size_t pool_bytes, char *ext_base = n
     P.tail_tiles = h->opt.tail_tiles;
     P.tail_inner_iters = h->opt.tail_inner_iters;
     P.tail_exchange_rounds = h->opt.tail_exchange_rounds;
+    P.tail_sweep_exchanges = h->opt.tail_sweep_exchanges;
     P.relabel_passes = h->opt.relabel_passes;
     P.orientation = h->opt.orientation;
     P.gap = h->opt.gap;

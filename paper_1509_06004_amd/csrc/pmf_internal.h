@@ -128,6 +128,7 @@ struct StepParams {
     int32_t tail_tiles;         // lists shorter than this use the two settings below
     int32_t tail_inner_iters;
     int32_t tail_exchange_rounds;
+    int32_t tail_sweep_exchanges;  // short supersteps: mid-visit flow exchanges of a sweep visit
     int32_t relabel_passes;     // cap on the passes of a relabel that leaves active pixels (0 = none)
     int32_t orientation;        // Orientation policy
     int32_t gap;                // 1: gap heuristic (every descriptor then has a hist array)

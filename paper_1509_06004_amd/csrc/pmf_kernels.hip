@@ -82,10 +82,6 @@ __device__ __forceinline__ void st_agent(GLOBAL T *p, T v) {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 template <typename T>
-__device__ __forceinline__ T g_exch(GLOBAL T *p, T v) {
-    return __hip_atomic_exchange(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-template <typename T>
 __device__ __forceinline__ void g_add(GLOBAL T *p, T v) {
     (void)__hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
@@ -337,7 +333,7 @@ __device__ void init_tile(const StepParams &P, const InstDesc &D, InstState *S, 
 // ---------------------------------------------------------------------------
 template <int K, int TW, int TH, bool GAP>
 __device__ void sweep_tile(const StepParams &P, const InstDesc &D, InstState *S, int tl,
-                           int iters, int32_t *lds, int *s_red) {
+                           int iters, int xsw, int32_t *lds, int *s_red) {
     using G = Geo<TW, TH>;
     constexpr int PPT = G::PPT, RPI = G::RPI, HW = G::HW, HH = G::HH, HALO = G::HALO;
     const int tid = threadIdx.x, lx = tid % TW, ly0 = tid / TW;
@@ -393,12 +389,15 @@ __device__ void sweep_tile(const StepParams &P, const InstDesc &D, InstState *S,
     int ibv[NBP];
 #pragma unroll
     for (int q = 0; q < NBP; ++q) ibv[q] = ld_agent(&inbox[min(tid + q * kThreads, B::E - 1)]);
-    // only nonzero words are taken (neighbour tiles may be adding to them)
+    // take exactly what was read: neighbour tiles only ever add to these
+    // words (this tile is the only one that takes from them), so subtracting
+    // the amount read leaves whatever arrived meanwhile for the next visit,
+    // and the subtraction needs no reply
 #pragma unroll
     for (int q = 0; q < NBP; ++q) {
         const int i = tid + q * kThreads;
         ibv[q] = i < B::E ? ibv[q] : 0;
-        if (ibv[q]) ibv[q] = g_exch(&inbox[i], 0);
+        if (ibv[q]) g_add(&inbox[i], -ibv[q]);
     }
     if (tid < G::RING) {
         sh_h[hc] = hin && hv <= gap ? hv : kHInf;
@@ -426,6 +425,62 @@ __device__ void sweep_tile(const StepParams &P, const InstDesc &D, InstState *S,
         }
     }
     __syncthreads();
+
+    // Hand pushes into halo cells to the neighbour tiles' inboxes (the word k
+    // of halo cell q with q + d_k inside the tile holds what q received) and
+    // clear those words; the neighbour tiles are marked for the wake-up below.
+    auto flush_halo = [&]() {
+        for (int i = tid; i < G::RING; i += kThreads) {
+            int hx, hy;
+            G::ring(i, hx, hy);
+            const int c = hy * HW + hx;
+            const int gx = x0 + hx - 1, gy = y0 + hy - 1;
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                const int ix = hx + DXk(k), iy = hy + DYk(k);
+                if (ix < 1 || ix > TW || iy < 1 || iy > TH) continue;
+                const int v = sh_r[c * K + k];
+                if (v > 0 && gx >= 0 && gx < W && gy >= 0 && gy < H) {
+                    // the receiving pixel, in the neighbour tile's coordinates
+                    const int dtx = hx == 0 ? 0 : (hx == HW - 1 ? 2 : 1);
+                    const int dty = hy == 0 ? 0 : (hy == HH - 1 ? 2 : 1);
+                    const int bx = dtx == 0 ? TW - 1 : dtx == 2 ? 0 : hx - 1;
+                    const int by = dty == 0 ? TH - 1 : dty == 2 ? 0 : hy - 1;
+                    const int nt = (ty + dty - 1) * D.tiles_x + tx + dtx - 1;
+                    g_add(&gp(D.inbox)[(size_t)nt * B::E + B::index(bx, by, k)], v);
+                    sh_r[c * K + k] = 0;
+                    s_nb[dty * 3 + dtx] = 1;
+                }
+            }
+        }
+    };
+    // Mid-visit exchange (short supersteps): flow handed to neighbour tiles
+    // that are being swept in the same launch reaches them while they still
+    // run, and what they handed here is taken now, so flow can cross several
+    // tiles in one superstep.  Taking follows the rule of the visit's start
+    // (subtract exactly what was read).
+    auto exchange = [&]() {
+        __syncthreads();  // every push of the iterations so far is in LDS
+        flush_halo();
+        int iv[NBP];
+#pragma unroll
+        for (int q = 0; q < NBP; ++q) iv[q] = ld_agent(&inbox[min(tid + q * kThreads, B::E - 1)]);
+#pragma unroll
+        for (int q = 0; q < NBP; ++q) {
+            const int i = tid + q * kThreads;
+            const int v = i < B::E ? iv[q] : 0;
+            if (v) {
+                g_add(&inbox[i], -v);
+                int bx, by, k;
+                B::pair(i, bx, by, k);
+                const int c = (by + 1) * HW + bx + 1;
+                atomicAdd(&sh_e[c], v);
+                atomicAdd(&sh_r[c * K + k], v);
+            }
+        }
+        __syncthreads();
+    };
+    const int xperiod = xsw > 0 ? max(1, iters / (xsw + 1)) : iters + 1;
 
     // Iterations.  Every pixel belongs to one wave (the PPT pixels of each of
     // its lanes).  Per iteration a wave lists its active pixels (e > 0,
@@ -503,6 +558,7 @@ __device__ void sweep_tile(const StepParams &P, const InstDesc &D, InstState *S,
         if ((it & 1) == 1 || it + 1 == iters) {
             if (!__syncthreads_or(na > 0)) break;
         }
+        if ((it + 1) % xperiod == 0 && it + 1 < iters) exchange();
     }
     __syncthreads();
 
@@ -546,30 +602,7 @@ __device__ void sweep_tile(const StepParams &P, const InstDesc &D, InstState *S,
         gp(D.h)[p] = h;
         gp(D.rmask)[p] = (uint16_t)rm;
     }
-    // hand pushes into halo cells to the neighbour tiles' inboxes: the word
-    // k of halo cell q with q + d_k inside the tile holds what q received
-    for (int i = tid; i < G::RING; i += kThreads) {
-        int hx, hy;
-        G::ring(i, hx, hy);
-        const int c = hy * HW + hx;
-        const int gx = x0 + hx - 1, gy = y0 + hy - 1;
-#pragma unroll
-        for (int k = 0; k < K; ++k) {
-            const int ix = hx + DXk(k), iy = hy + DYk(k);
-            if (ix < 1 || ix > TW || iy < 1 || iy > TH) continue;
-            const int v = sh_r[c * K + k];
-            if (v > 0 && gx >= 0 && gx < W && gy >= 0 && gy < H) {
-                // the receiving pixel, in the neighbour tile's coordinates
-                const int dtx = hx == 0 ? 0 : (hx == HW - 1 ? 2 : 1);
-                const int dty = hy == 0 ? 0 : (hy == HH - 1 ? 2 : 1);
-                const int bx = dtx == 0 ? TW - 1 : dtx == 2 ? 0 : hx - 1;
-                const int by = dty == 0 ? TH - 1 : dty == 2 ? 0 : hy - 1;
-                const int nt = (ty + dty - 1) * D.tiles_x + tx + dtx - 1;
-                g_add(&gp(D.inbox)[(size_t)nt * B::E + B::index(bx, by, k)], v);
-                s_nb[dty * 3 + dtx] = 1;
-            }
-        }
-    }
+    flush_halo();
     const int tile_active = __syncthreads_or(active);
     if (tid < 9 && tid != 4 && s_nb[tid]) {
         const int ntx = tx + (tid % 3) - 1, nty = ty + (tid / 3) - 1;
@@ -640,6 +673,9 @@ __device__ void relabel_tile(const StepParams &P, const InstDesc &D, InstState *
     const bool hin = x0 + hx - 1 >= 0 && x0 + hx - 1 < W && y0 + hy - 1 >= 0 && y0 + hy - 1 < H;
     const int hq = min(max(y0 + hy - 1, 0), H - 1) * W + min(max(x0 + hx - 1, 0), W - 1);
     const int hv = first ? (int)gp(D.rmask)[hq] : gp(D.h)[hq];
+    // the tile's active count under the previous labels, read now so that
+    // the end of the visit does not wait for it
+    const int cnt_prev = (!first && tid == 0) ? gp(D.tile_cnt)[tl] : 0;
     if (first) {
         // fold flow that neighbour tiles pushed into the border pixels (no
         // sweep of this instance runs in the same launch, so nobody else
@@ -743,11 +779,12 @@ __device__ void relabel_tile(const StepParams &P, const InstDesc &D, InstState *
         // branch-free: every label is rewritten (only its owner writes it) as
         // min(d, 1 + min over residual arcs of the neighbour's label), taken
         // as 1 + min(d - 1, neighbour label or H_INF - 1 where the arc is
-        // saturated): one select per arc; a result never exceeds H_INF
-        int nd[4];
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            // the neighbour in direction k of strip cell j (old values: Jacobi)
+        // saturated): one select per arc; a result never exceeds H_INF.
+        // The strip's cells are taken in order, left to right in even rounds
+        // and right to left in odd ones, each seeing the label its strip
+        // neighbour got earlier in the same round, so a distance crosses
+        // the whole strip in one round in the direction of the pass.
+        auto relax = [&](int j) {
             int nb[8];
             nb[0] = j < 3 ? sd[j + 1] : rg;  // (+1, 0)
             nb[1] = j > 0 ? sd[j - 1] : lf;  // (-1, 0)
@@ -763,14 +800,13 @@ __device__ void relabel_tile(const StepParams &P, const InstDesc &D, InstState *
                 const int vk = ((srm[j] >> k) & 1u) ? nb[k] : kHInf - 1;
                 mn = vk < mn ? vk : mn;
             }
-            nd[j] = mn + 1;
-        }
+            ch |= mn + 1 < sd[j];
+            sd[j] = mn + 1;
+        };
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            ch |= nd[j] < sd[j];
-            sd[j] = nd[j];
-            sh_d[sc + j] = nd[j];
-        }
+        for (int j = 0; j < 4; ++j) relax(j);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) sh_d[sc + j] = sd[j];
         if ((it & 3) == 3 || it + 1 == P.local_bfs_iters) {
             if (!__syncthreads_or(ch)) break;
             ch = 0;
@@ -834,7 +870,7 @@ __device__ void relabel_tile(const StepParams &P, const InstDesc &D, InstState *
     const int tcnt = block_count_ballot(act, s_red);
     if (tid == 0) {
         gp(D.tile_chg)[(size_t)cur * D.ntiles + tl] = (uint8_t)(tchg ? 1 : 0);
-        const int delta = first ? tcnt : tcnt - gp(D.tile_cnt)[tl];
+        const int delta = first ? tcnt : tcnt - cnt_prev;
         gp(D.tile_cnt)[tl] = tcnt;
         if (delta) atomicAdd(&S->active, delta);
         if (tchg) atomicOr(&S->changed, 1);
@@ -1284,8 +1320,9 @@ __device__ void tile_work(const StepParams &P, int ws, int wp, int32_t *lds, int
     const int p_lo = x * ep, p_n = max(0, min(np, p_lo + ep) - p_lo);
     // a short superstep (few tiles in a kind of list) is latency bound: its
     // visits may run longer at no cost in width
-    const int iters =
-        P.list_count[0] + P.list_count[1] < P.tail_tiles ? P.tail_inner_iters : P.inner_iters;
+    const bool short_sweeps = P.list_count[0] + P.list_count[1] < P.tail_tiles;
+    const int iters = short_sweeps ? P.tail_inner_iters : P.inner_iters;
+    const int xsw = short_sweeps ? P.tail_sweep_exchanges : 0;
     const int xrounds =
         P.list_count[2] + P.list_count[3] < P.tail_tiles ? P.tail_exchange_rounds : P.exchange_rounds;
     for (int i = first; i < s_n + p_n; i += stride) {
@@ -1293,7 +1330,7 @@ __device__ void tile_work(const StepParams &P, int ws, int wp, int32_t *lds, int
         if (i < s_n) {
             const int2 en = list_item(P, ws, s_lo + i);
             const InstDesc D = load_desc(P.desc, en.x);
-            sweep_tile<K, TW, TH, GAP>(P, D, &P.st[en.x], en.y, iters, lds, s_red);
+            sweep_tile<K, TW, TH, GAP>(P, D, &P.st[en.x], en.y, iters, xsw, lds, s_red);
         } else {
             const int2 en = list_item(P, wp, p_lo + i - s_n);
             InstState *S = &P.st[en.x];

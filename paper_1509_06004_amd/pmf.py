@@ -57,6 +57,7 @@ class Options(ctypes.Structure):
         ("gap", ctypes.c_int32),
         ("persist_tiles", ctypes.c_int32),
         ("persist_wgs", ctypes.c_int32),
+        ("tail_sweep_exchanges", ctypes.c_int32),
     ]
 
 

@@ -123,6 +123,26 @@ def test_orientation_edge_cases(pmf, orientation, chunk):
     check_against_oracle(tiny, flows, status, masks)
 
 
+@pytest.mark.parametrize("K,xsw", [(4, 4), (8, 2)])
+def test_sweep_exchanges_repeated(pmf, K, xsw):
+    """Sweep visits that hand flow to running neighbour tiles and take theirs
+    during the visit (every superstep counted as short): warm chains on grids
+    of many tiles, both orientations, three solves, oracle-exact."""
+    rng = np.random.default_rng(800 + K)
+    insts = []
+    for i in range(4):
+        img = W.voronoi_image(int(rng.integers(70, 140)), int(rng.integers(60, 110)), 8, rng)
+        nl = W.nlinks(img, K)
+        H, Wd = img.shape
+        insts.append(W.seed_instance(img, nl, K, int(rng.integers(5, Wd - 5)), int(rng.integers(5, H - 5)), 5,
+                                     W.loguniform_lambdas(rng, 6, 2000.0), image=i))
+    for rep in range(3):
+        say("sweep exchanges K", K, "xsw", xsw, "solve", rep)
+        flows, status, masks, _ = solve(pmf, insts, tail_tiles=1 << 30, tail_sweep_exchanges=xsw,
+                                        orientation=2 if rep else 0, lambda_chunk=100 if rep < 2 else 2)
+        check_against_oracle(insts, flows, status, masks)
+
+
 @pytest.mark.parametrize("K", [4, 8])
 def test_warm_chains_as_given_repeated(pmf, K):
     """Whole warm chains solved as given (never exchanged), on grids of many
@@ -249,7 +269,9 @@ def test_options_do_not_change_results(pmf):
                  dict(gap=1), dict(gap=1, orientation=0, lambda_chunk=100),
                  dict(gap=1, inner_iters=64, sweeps_per_relabel=32, relabel_passes=2),
                  dict(persist_tiles=1 << 30), dict(persist_tiles=1 << 30, persist_wgs=8, steps_per_sync=3),
-                 dict(persist_tiles=40, gap=1, lambda_chunk=1)]:
+                 dict(persist_tiles=40, gap=1, lambda_chunk=1),
+                 dict(tail_sweep_exchanges=3), dict(tail_tiles=1 << 30, tail_sweep_exchanges=5, tail_inner_iters=24),
+                 dict(tail_tiles=1 << 30, tail_sweep_exchanges=64, tail_inner_iters=8, orientation=0)]:
         say("options", opts)
         flows, status, masks, _ = solve(pmf, insts, **opts)
         assert (status == 0).all()
