@@ -134,11 +134,16 @@ __device__ __forceinline__ void count_px(int64_t *ctr, long long v) {
     atomicAdd((unsigned long long *)ctr, (unsigned long long)v);
 }
 
-// Pixel visits of one tile pass: into the instance's counter and, in timing
-// mode, into the launch's counter of that kind of work.
+// Timing mode: pixel visits of the workgroup's items by kind, added to the
+// launch's counters once per workgroup at the end of its tile work (an
+// atomic on one device-wide word from every visit would serialise them).
+__shared__ unsigned long long s_kpx[kPxKinds];
+
+// Pixel visits of one tile pass (thread 0): into the instance's counter and,
+// in timing mode, into the workgroup's count of that kind of work.
 __device__ __forceinline__ void count_visit(const StepParams &P, int64_t *ctr, int kind, long long v) {
     count_px(ctr, v);
-    if (P.kpx) count_px(&P.kpx[kind], v);
+    if (P.kpx) s_kpx[kind] += (unsigned long long)v;
 }
 
 // Block-wide count of set flags by wave ballots: each wave adds the popcount
@@ -1325,6 +1330,7 @@ __device__ void tile_work(const StepParams &P, int ws, int wp, int32_t *lds, int
     const int xsw = short_sweeps ? P.tail_sweep_exchanges : 0;
     const int xrounds =
         P.list_count[2] + P.list_count[3] < P.tail_tiles ? P.tail_exchange_rounds : P.exchange_rounds;
+    if (P.kpx && threadIdx.x < kPxKinds) s_kpx[threadIdx.x] = 0ull;  // ordered by the loop's first barrier
     for (int i = first; i < s_n + p_n; i += stride) {
         __syncthreads();  // the previous item's LDS is no longer in use
         if (i < s_n) {
@@ -1348,6 +1354,11 @@ __device__ void tile_work(const StepParams &P, int ws, int wp, int32_t *lds, int
             else
                 cut_tile<K, TW, TH>(P, D, S, tl, sub, kk, xrounds, lds, s_red, s_sum);
         }
+    }
+    if (P.kpx) {
+        __syncthreads();
+        if (threadIdx.x < kPxKinds && s_kpx[threadIdx.x])
+            count_px(&P.kpx[threadIdx.x], (long long)s_kpx[threadIdx.x]);
     }
 }
 
