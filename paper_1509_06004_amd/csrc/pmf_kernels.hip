@@ -20,8 +20,9 @@
 //   - kRelabel: exact distances to t by tile-parallel Bellman-Ford relaxation
 //     (tile-local relaxation to a fixed point, repeated over the tiles whose
 //     neighbourhood changed).  A pass in which no label changes proves the
-//     distances exact; pixels that cannot reach t get H_INF (this subsumes the
-//     gap heuristic: every vertex above an empty level is unreachable).  If no
+//     distances exact; pixels that cannot reach t get H_INF (at that instant
+//     every vertex above an empty level is among them; between relabels the
+//     optional gap heuristic finds levels that the sweeps empty).  If no
 //     pixel with excess can still reach t, the preflow is maximum;
 //   - kCut: the minimal source side is the set of pixels reachable in the
 //     residual graph from the pixels still holding excess (all source arcs
