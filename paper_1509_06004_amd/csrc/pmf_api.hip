@@ -477,6 +477,7 @@ int submit(pmf_handle *h, const pmf_instance *inst, int n, int64_t *flows_out, i
         D.L = I.L;
         D.slot_id = id;
         D.check_prev = check_prev ? check_prev[i] : 0;
+        D.tile_w = h->tw;
         D.lambdas = I.lambdas;
         D.nlink = I.nlink;
         D.cap_src = I.cap_src;

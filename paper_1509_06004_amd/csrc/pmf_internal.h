@@ -57,7 +57,7 @@ struct alignas(16) InstDesc {
     int32_t tiles_x, tiles_y, ntiles, tile0;
     int32_t L, slot_id;
     int32_t check_prev;  // lambdas[-1] belongs to the same schedule: check it too
-    int32_t pad1;
+    int32_t tile_w;      // tile width in pixels (tiles hold 1024 pixels)
     const int32_t *lambdas;
     const int32_t *nlink;
     const int32_t *cap_src;
@@ -134,7 +134,7 @@ struct StepParams {
     int32_t gap;                // 1: gap heuristic (every descriptor then has a hist array)
     int64_t max_steps;
     int32_t *trace_lists;       // timing mode: the control kernel copies the 4 list sizes here (may be null)
-    int64_t *kpx;               // timing mode: pixel visits of this launch's tile work by kind (may be null)
+    int64_t *kpx;               // timing mode: pixel visits of the listed tiles by kind (may be null)
 };
 
 // Kinds of tile work (index into StepParams::kpx and pmf_stats::kernel_px).

@@ -123,28 +123,15 @@ struct Geo {
     }
 };
 
-// Pixels of tile (tx, ty) that lie inside the W x H image.
-template <int TW, int TH>
-__device__ __forceinline__ long long tile_pixels(int W, int H, int x0, int y0) {
-    const int w = W - x0 < TW ? W - x0 : TW;
-    const int h = H - y0 < TH ? H - y0 : TH;
-    return (long long)w * h;
+// Pixels of the tw x th tile at (x0, y0) that lie inside the W x H image.
+__device__ __forceinline__ int tile_pixels(int W, int H, int tw, int th, int x0, int y0) {
+    const int w = W - x0 < tw ? W - x0 : tw;
+    const int h = H - y0 < th ? H - y0 : th;
+    return w * h;
 }
 
 __device__ __forceinline__ void count_px(int64_t *ctr, long long v) {
     atomicAdd((unsigned long long *)ctr, (unsigned long long)v);
-}
-
-// Timing mode: pixel visits of the workgroup's items by kind, added to the
-// launch's counters once per workgroup at the end of its tile work (an
-// atomic on one device-wide word from every visit would serialise them).
-__shared__ unsigned long long s_kpx[kPxKinds];
-
-// Pixel visits of one tile pass (thread 0): into the instance's counter and,
-// in timing mode, into the workgroup's count of that kind of work.
-__device__ __forceinline__ void count_visit(const StepParams &P, int64_t *ctr, int kind, long long v) {
-    count_px(ctr, v);
-    if (P.kpx) s_kpx[kind] += (unsigned long long)v;
 }
 
 // Block-wide count of set flags by wave ballots: each wave adds the popcount
@@ -230,7 +217,6 @@ __device__ void orient_tile(const StepParams &P, const InstDesc &D, InstState *S
     if (tid == 0) {
         if (np) atomicAdd(&S->cnt_pos, np);
         if (nn) atomicAdd(&S->cnt_neg, nn);
-        count_visit(P, &S->px_orient, kPxOrient, tile_pixels<TW, TH>(W, H, x0, y0));
     }
     (void)P;
 }
@@ -307,8 +293,6 @@ __device__ void init_tile(const StepParams &P, const InstDesc &D, InstState *S, 
     const long long tot = block_sum_i64(scs, s_sum);
     if (tid == 0) {
         if (tot) atomicAdd((unsigned long long *)&S->sum_cs, (unsigned long long)tot);
-        count_visit(P, swap ? &S->px_init_x : &S->px_init, swap ? kPxInitX : kPxInit,
-                    tile_pixels<TW, TH>(W, H, x0, y0));
         gp(D.tile_act)[tl] = 0;
         gp(D.tile_cnt)[tl] = 0;
         gp(D.tile_chg)[tl] = 1;
@@ -621,7 +605,6 @@ __device__ void sweep_tile(const StepParams &P, const InstDesc &D, InstState *S,
             g_or(&gp(D.tile_act)[tl], 1u);
         else
             g_and(&gp(D.tile_act)[tl], ~1u);
-        count_visit(P, &S->px_sweep, kPxSweep, tile_pixels<TW, TH>(W, H, x0, y0));
         if (nkill) count_px(&S->gap_kills, nkill);
     }
 }
@@ -881,7 +864,6 @@ __device__ void relabel_tile(const StepParams &P, const InstDesc &D, InstState *
         if (delta) atomicAdd(&S->active, delta);
         if (tchg) atomicOr(&S->changed, 1);
         gp(D.tile_act)[tl] = tcnt > 0 ? 1u : 0u;
-        count_visit(P, &S->px_relabel, kPxRelabel, tile_pixels<TW, TH>(W, H, x0, y0));
     }
 }
 
@@ -959,7 +941,6 @@ __device__ void cut_tile_swapped(const StepParams &P, const InstDesc &D, InstSta
         gp(D.tile_chg)[tl] = 0;  // the cut is complete after this pass
         if (tse) atomicAdd((unsigned long long *)&S->sum_e, (unsigned long long)tse);
         if (tra) atomicAdd((unsigned long long *)&S->sum_raise, (unsigned long long)tra);
-        count_visit(P, &S->px_cut_x, kPxCutX, tile_pixels<TW, TH>(W, H, x0, y0));
     }
     (void)P;
 }
@@ -1117,7 +1098,6 @@ __device__ void cut_tile(const StepParams &P, const InstDesc &D, InstState *S, i
         gp(D.tile_chg)[(size_t)cur * D.ntiles + tl] = (uint8_t)(tchg ? 1 : 0);
         if (tchg) atomicOr(&S->changed, 1);
         if (tse) atomicAdd((unsigned long long *)&S->sum_e, (unsigned long long)tse);
-        count_visit(P, &S->px_cut, kPxCut, tile_pixels<TW, TH>(W, H, x0, y0));
     }
     (void)s_red;
 }
@@ -1263,8 +1243,11 @@ __device__ __forceinline__ void wave_append(bool want, int2 *list, int32_t *coun
 // a processed tile would.  The tile kernels rely on these tests: a listed tile
 // is in range, its instance in the listed phase (phases change only in the
 // control kernel), a listed sweep tile has work, a listed pass tile needs
-// the pass.
+// the pass.  Every listed tile is visited exactly once by the tile work that
+// follows, so the pixel-visit statistics of that work are counted here, by
+// the instance's own workgroup, rather than by every visit.
 __device__ void compact_instance(const StepParams &P, int w) {
+    __shared__ unsigned long long s_cpx;
     const int slot = __builtin_amdgcn_readfirstlane(P.wl_slot[w]);
     const InstState *S = &P.st[slot];
     const int phase = __builtin_amdgcn_readfirstlane(S->phase);
@@ -1277,6 +1260,10 @@ __device__ void compact_instance(const StepParams &P, int w) {
     int2 *pl = lists + (is8 ? 3 : 2) * (size_t)P.list_cap;
     int32_t *sc = P.list_count + (is8 ? 1 : 0), *pc = P.list_count + (is8 ? 3 : 2);
     int nsw = 0;
+    const int tw = D.tile_w, th = (kThreads * 4) / tw;
+    int npx = 0;  // pixels of the tiles this thread listed
+    if (threadIdx.x == 0) s_cpx = 0ull;
+    __syncthreads();
     for (int t0 = 0; t0 < D.ntiles; t0 += kThreads) {
         const int tl = t0 + (int)threadIdx.x;
         bool sw = false, bf = false;
@@ -1295,11 +1282,34 @@ __device__ void compact_instance(const StepParams &P, int w) {
         wave_append(sw, sl, sc, en);
         wave_append(bf, pl, pc, en);
         nsw |= sw;
+        if (sw || bf) npx += tile_pixels(D.W, D.H, tw, th, (tl % D.tiles_x) * tw, (tl / D.tiles_x) * th);
     }
+    if (npx) atomicAdd(&s_cpx, (unsigned long long)npx);
     // a sweeping instance with no tile to sweep is at rest: the control
     // kernel then starts its relabel at once
     const int any = __syncthreads_or(nsw);
-    if (threadIdx.x == 0) P.st[slot].listed = any;
+    if (threadIdx.x == 0) {
+        InstState *Sw = &P.st[slot];
+        Sw->listed = any;
+        const long long v = (long long)s_cpx;
+        if (v) {
+            const int swap = Sw->swap;
+            const int kind = phase == kSweep ? kPxSweep
+                             : phase == kRelabel ? kPxRelabel
+                             : phase == kOrient ? kPxOrient
+                             : phase == kInit ? (swap ? kPxInitX : kPxInit)
+                                              : (swap ? kPxCutX : kPxCut);
+            int64_t *ctr = kind == kPxSweep     ? &Sw->px_sweep
+                           : kind == kPxRelabel ? &Sw->px_relabel
+                           : kind == kPxOrient  ? &Sw->px_orient
+                           : kind == kPxInit    ? &Sw->px_init
+                           : kind == kPxInitX   ? &Sw->px_init_x
+                           : kind == kPxCut     ? &Sw->px_cut
+                                                : &Sw->px_cut_x;
+            *ctr += v;  // no other kernel runs meanwhile, and only this workgroup writes the instance's counters
+            if (P.kpx) count_px(&P.kpx[kind], v);
+        }
+    }
 }
 
 __global__ __launch_bounds__(kThreads) void k_compact(StepParams P) { compact_instance(P, (int)blockIdx.x); }
@@ -1331,7 +1341,6 @@ __device__ void tile_work(const StepParams &P, int ws, int wp, int32_t *lds, int
     const int xsw = short_sweeps ? P.tail_sweep_exchanges : 0;
     const int xrounds =
         P.list_count[2] + P.list_count[3] < P.tail_tiles ? P.tail_exchange_rounds : P.exchange_rounds;
-    if (P.kpx && threadIdx.x < kPxKinds) s_kpx[threadIdx.x] = 0ull;  // ordered by the loop's first barrier
     for (int i = first; i < s_n + p_n; i += stride) {
         __syncthreads();  // the previous item's LDS is no longer in use
         if (i < s_n) {
@@ -1355,11 +1364,6 @@ __device__ void tile_work(const StepParams &P, int ws, int wp, int32_t *lds, int
             else
                 cut_tile<K, TW, TH>(P, D, S, tl, sub, kk, xrounds, lds, s_red, s_sum);
         }
-    }
-    if (P.kpx) {
-        __syncthreads();
-        if (threadIdx.x < kPxKinds && s_kpx[threadIdx.x])
-            count_px(&P.kpx[threadIdx.x], (long long)s_kpx[threadIdx.x]);
     }
 }
 

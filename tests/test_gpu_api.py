@@ -96,3 +96,30 @@ def test_parametric_in_workspace_and_budget(pmf):
     ms = np.stack([np.asarray(m, dtype=bool).reshape(inst.H, inst.W) for _, m in sols])
     exp_bp = [lams[i] for i in range(1, len(lams)) if (ms[i] != ms[i - 1]).any()]
     assert list(bp1) == exp_bp
+
+
+def test_pixel_visit_statistics(pmf):
+    """Visit statistics: with an orientation count every instance (chunk) is
+    counted and initialised exactly once, so both totals are its pixels; the
+    per-kind counts of timing mode equal the instances' own counters."""
+    import torch
+    insts = W.config1() + W.config2(K=4, seeds=2, L=5) + W.config2(K=8, seeds=1, L=4)
+    dev = pmf.to_device(insts)
+    chunk = 2
+    px = sum(inst.W * inst.H * ((inst.L + chunk - 1) // chunk) for inst in insts)
+    px_all_lambdas = sum(inst.W * inst.H * inst.L for inst in insts)
+    for timing in (0, 1):
+        s = pmf.Solver(lambda_chunk=chunk, orientation=2, timing=timing)
+        s.solve(dev)
+        torch.cuda.synchronize()
+        st = s.stats()
+        say("timing", timing, {k: st[k] for k in ("px_orient", "px_init", "px_init_x", "px_sweep", "px_relabel", "px_cut")})
+        assert st["px_orient"] == px
+        assert st["px_init"] + st["px_init_x"] == px
+        # every lambda's cut starts with a pass over all of the instance's tiles
+        assert st["px_relabel"] > 0 and st["px_cut"] + st["px_cut_x"] >= px_all_lambdas
+        if timing:
+            kp = st["kernel_px"]
+            own = [st["px_sweep"], st["px_relabel"], st["px_cut"], st["px_init"], st["px_orient"],
+                   st["px_init_x"], st["px_cut_x"]]
+            assert [int(kp[i]) + int(kp[8 + i]) for i in range(7)] == own
