@@ -149,6 +149,31 @@ __device__ __forceinline__ int block_count_ballot(const bool (&flag)[N], int *s_
     return s_red[0];
 }
 
+// Block-wide OR of `any` and count of the set `cnt` flags behind a single
+// barrier: lane 0 of each wave leaves its wave's ballots in slots[2w] and
+// slots[2w + 1] (8 ints), and every thread sums the four.  A previous use of
+// the same slots must be separated from this one by a barrier.
+template <int N>
+__device__ __forceinline__ int2 block_vote(bool any, const bool (&cnt)[N], int *slots) {
+    int c = 0;
+#pragma unroll
+    for (int j = 0; j < N; ++j) c += __popcll(__ballot(cnt[j]));
+    const int a = __ballot(any) != 0ull ? 1 : 0;
+    const int w = (int)(threadIdx.x >> 6);
+    if ((threadIdx.x & 63) == 0) {
+        slots[2 * w] = a;
+        slots[2 * w + 1] = c;
+    }
+    __syncthreads();
+    int2 r = make_int2(0, 0);
+#pragma unroll
+    for (int i = 0; i < kThreads / 64; ++i) {
+        r.x |= slots[2 * i];
+        r.y += slots[2 * i + 1];
+    }
+    return r;
+}
+
 __device__ __forceinline__ long long block_sum_i64(long long v, unsigned long long *s_sum) {
     __syncthreads();
     if (threadIdx.x == 0) *s_sum = 0ull;
@@ -593,13 +618,15 @@ __device__ void sweep_tile(const StepParams &P, const InstDesc &D, InstState *S,
         gp(D.rmask)[p] = (uint16_t)rm;
     }
     flush_halo();
-    const int tile_active = __syncthreads_or(active);
+    // one barrier: the wake-up marks of flush_halo are complete, and the
+    // tile's activity (and gap-stopped pixels) are counted
+    const int2 vote = block_vote(active != 0, killed, s_red + 8);
+    const int tile_active = vote.x, nkill = GAP ? vote.y : 0;
     if (tid < 9 && tid != 4 && s_nb[tid]) {
         const int ntx = tx + (tid % 3) - 1, nty = ty + (tid / 3) - 1;
         if (ntx >= 0 && ntx < D.tiles_x && nty >= 0 && nty < D.tiles_y)
             g_or(&gp(D.tile_act)[nty * D.tiles_x + ntx], 2u);
     }
-    const int nkill = GAP ? block_count_ballot(killed, s_red) : 0;
     if (tid == 0) {
         if (tile_active)
             g_or(&gp(D.tile_act)[tl], 1u);
@@ -855,8 +882,8 @@ __device__ void relabel_tile(const StepParams &P, const InstDesc &D, InstState *
         const int ones = block_count_ballot(one, s_red);
         if (tid == 0 && ones) atomicAdd(&S->hist1, ones);
     }
-    const int tchg = __syncthreads_or(changed);
-    const int tcnt = block_count_ballot(act, s_red);
+    const int2 vote = block_vote(changed != 0, act, s_red + 8);
+    const int tchg = vote.x, tcnt = vote.y;
     if (tid == 0) {
         gp(D.tile_chg)[(size_t)cur * D.ntiles + tl] = (uint8_t)(tchg ? 1 : 0);
         const int delta = first ? tcnt : tcnt - cnt_prev;
@@ -1374,7 +1401,7 @@ __device__ void tile_work(const StepParams &P, int ws, int wp, int32_t *lds, int
 template <int K, int TW, int TH, bool GAP, bool TIMED = false>
 __global__ __launch_bounds__(kThreads) void k_step(StepParams P, int ws, int wp) {
     __shared__ int32_t lds[(3 + K) * (TW + 2) * (TH + 2)];  // sweep layout; passes use 4 planes
-    __shared__ int s_red[4];
+    __shared__ int s_red[16];  // [0]: block_count_ballot, [8..15]: block_vote
     __shared__ unsigned long long s_sum;
     tile_work<K, TW, TH, GAP>(P, ws, wp, lds, s_red, &s_sum);
 }
@@ -1473,7 +1500,7 @@ extern __shared__ int32_t persist_lds[];
 
 template <int K, int TW, int TH>
 __device__ __attribute__((noinline)) void persist_work(const StepParams *Pg) {
-    __shared__ int s_red[4];
+    __shared__ int s_red[16];  // [0]: block_count_ballot, [8..15]: block_vote
     __shared__ unsigned long long s_sum;
     const StepParams P = load_params(Pg);
     tile_work<K, TW, TH, false>(P, K == 4 ? 0 : 1, K == 4 ? 2 : 3, persist_lds, s_red, &s_sum);
@@ -1501,7 +1528,7 @@ __device__ __attribute__((noinline)) int persist_control(const StepParams *Pg) {
 template <int TW, int TH, int KSET>
 __global__ __launch_bounds__(kThreads) void k_persist(const StepParams *Pg, int max_steps, int exit_tiles) {
     __shared__ int s_ok;
-    __shared__ int s_red[4];
+    __shared__ int s_red[16];  // [0]: block_count_ballot, [8..15]: block_vote
     __shared__ unsigned long long s_sum;
     const StepParams P = load_params(Pg);
     int32_t *bar = P.ring_count + kBarWords;
