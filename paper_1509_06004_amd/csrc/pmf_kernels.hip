@@ -174,6 +174,21 @@ __device__ __forceinline__ int2 block_vote(bool any, const bool (&cnt)[N], int *
     return r;
 }
 
+// Block-wide OR behind a single barrier (the runtime's block OR takes three):
+// lane 0 of each wave writes its wave's ballot to `bank` (4 ints).  Calls
+// that follow one another without another barrier in between must alternate
+// between two banks: a bank is rewritten only after the barrier of the call
+// in between, which every wave reaches after reading it.
+__device__ __forceinline__ bool block_any(bool v, int *bank) {
+    const int a = __ballot(v) != 0ull ? 1 : 0;
+    if ((threadIdx.x & 63) == 0) bank[threadIdx.x >> 6] = a;
+    __syncthreads();
+    int r = 0;
+#pragma unroll
+    for (int i = 0; i < kThreads / 64; ++i) r |= bank[i];
+    return r != 0;
+}
+
 __device__ __forceinline__ long long block_sum_i64(long long v, unsigned long long *s_sum) {
     __syncthreads();
     if (threadIdx.x == 0) *s_sum = 0ull;
@@ -571,7 +586,7 @@ __device__ void sweep_tile(const StepParams &P, const InstDesc &D, InstState *S,
         // progress check every 2 iterations: an iteration in which no wave
         // listed a pixel changed nothing, so the tile is at rest
         if ((it & 1) == 1 || it + 1 == iters) {
-            if (!__syncthreads_or(na > 0)) break;
+            if (!block_any(na > 0, s_red + 16 + 4 * ((it >> 1) & 1))) break;
         }
         if ((it + 1) % xperiod == 0 && it + 1 < iters) exchange();
     }
@@ -824,7 +839,7 @@ __device__ void relabel_tile(const StepParams &P, const InstDesc &D, InstState *
 #pragma unroll
         for (int j = 0; j < 4; ++j) sh_d[sc + j] = sd[j];
         if ((it & 3) == 3 || it + 1 == P.local_bfs_iters) {
-            if (!__syncthreads_or(ch)) break;
+            if (!block_any(ch != 0, s_red + 16 + 4 * ((it >> 2) & 1))) break;
             ch = 0;
         }
     }
@@ -855,7 +870,7 @@ __device__ void relabel_tile(const StepParams &P, const InstDesc &D, InstState *
             got = 1;
         }
     }
-    if (!__syncthreads_or(got)) break;
+    if (!block_any(got != 0, s_red + 24)) break;
     }
     int changed = first ? 1 : 0;
     bool act[PPT], one[PPT];
@@ -1398,10 +1413,12 @@ __device__ void tile_work(const StepParams &P, int ws, int wp, int32_t *lds, int
 // that the default build carries none of its registers).  TIMED: the same
 // code under a name of its own for the launches of timing mode, so that a
 // profiler's kernel trace reports exactly the launches that mode times.
+// The 4-connected kernel is held to 128 VGPRs: four waves per SIMD, which its
+// LDS also allows (four workgroups per CU).
 template <int K, int TW, int TH, bool GAP, bool TIMED = false>
-__global__ __launch_bounds__(kThreads) void k_step(StepParams P, int ws, int wp) {
+__global__ __launch_bounds__(kThreads, K == 4 ? 4 : 1) void k_step(StepParams P, int ws, int wp) {
     __shared__ int32_t lds[(3 + K) * (TW + 2) * (TH + 2)];  // sweep layout; passes use 4 planes
-    __shared__ int s_red[16];  // [0]: block_count_ballot, [8..15]: block_vote
+    __shared__ int s_red[32];  // [0]: block_count_ballot, [8..15]: block_vote, [16..27]: block_any
     __shared__ unsigned long long s_sum;
     tile_work<K, TW, TH, GAP>(P, ws, wp, lds, s_red, &s_sum);
 }
@@ -1500,7 +1517,7 @@ extern __shared__ int32_t persist_lds[];
 
 template <int K, int TW, int TH>
 __device__ __attribute__((noinline)) void persist_work(const StepParams *Pg) {
-    __shared__ int s_red[16];  // [0]: block_count_ballot, [8..15]: block_vote
+    __shared__ int s_red[32];  // [0]: block_count_ballot, [8..15]: block_vote, [16..27]: block_any
     __shared__ unsigned long long s_sum;
     const StepParams P = load_params(Pg);
     tile_work<K, TW, TH, false>(P, K == 4 ? 0 : 1, K == 4 ? 2 : 3, persist_lds, s_red, &s_sum);
@@ -1528,7 +1545,7 @@ __device__ __attribute__((noinline)) int persist_control(const StepParams *Pg) {
 template <int TW, int TH, int KSET>
 __global__ __launch_bounds__(kThreads) void k_persist(const StepParams *Pg, int max_steps, int exit_tiles) {
     __shared__ int s_ok;
-    __shared__ int s_red[16];  // [0]: block_count_ballot, [8..15]: block_vote
+    __shared__ int s_red[32];  // [0]: block_count_ballot, [8..15]: block_vote, [16..27]: block_any
     __shared__ unsigned long long s_sum;
     const StepParams P = load_params(Pg);
     int32_t *bar = P.ring_count + kBarWords;
