@@ -1289,7 +1289,7 @@ __device__ __forceinline__ void wave_append(bool want, int2 *list, int32_t *coun
 // follows, so the pixel-visit statistics of that work are counted here, by
 // the instance's own workgroup, rather than by every visit.
 __device__ void compact_instance(const StepParams &P, int w) {
-    __shared__ unsigned long long s_cpx;
+    __shared__ int s_vote[8];
     const int slot = __builtin_amdgcn_readfirstlane(P.wl_slot[w]);
     const InstState *S = &P.st[slot];
     const int phase = __builtin_amdgcn_readfirstlane(S->phase);
@@ -1304,8 +1304,7 @@ __device__ void compact_instance(const StepParams &P, int w) {
     int nsw = 0;
     const int tw = D.tile_w, th = (kThreads * 4) / tw;
     int npx = 0;  // pixels of the tiles this thread listed
-    if (threadIdx.x == 0) s_cpx = 0ull;
-    __syncthreads();
+    __syncthreads();  // a previous call's vote has been read (persistent launches compact several instances)
     for (int t0 = 0; t0 < D.ntiles; t0 += kThreads) {
         const int tl = t0 + (int)threadIdx.x;
         bool sw = false, bf = false;
@@ -1326,14 +1325,28 @@ __device__ void compact_instance(const StepParams &P, int w) {
         nsw |= sw;
         if (sw || bf) npx += tile_pixels(D.W, D.H, tw, th, (tl % D.tiles_x) * tw, (tl / D.tiles_x) * th);
     }
-    if (npx) atomicAdd(&s_cpx, (unsigned long long)npx);
-    // a sweeping instance with no tile to sweep is at rest: the control
-    // kernel then starts its relabel at once
-    const int any = __syncthreads_or(nsw);
+    // one barrier: whether a tile was listed to sweep (a sweeping instance
+    // with no tile to sweep is at rest: the control kernel then starts its
+    // relabel at once) and the listed pixels (at most 2^31 per instance)
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) npx += __shfl_xor(npx, off);
+    const int wv = (int)(threadIdx.x >> 6);
+    const bool wany = __ballot(nsw != 0) != 0ull;
+    if ((threadIdx.x & 63) == 0) {
+        s_vote[2 * wv] = wany ? 1 : 0;
+        s_vote[2 * wv + 1] = npx;
+    }
+    __syncthreads();
     if (threadIdx.x == 0) {
+        int any = 0;
+        long long v = 0;
+#pragma unroll
+        for (int i = 0; i < kThreads / 64; ++i) {
+            any |= s_vote[2 * i];
+            v += s_vote[2 * i + 1];
+        }
         InstState *Sw = &P.st[slot];
         Sw->listed = any;
-        const long long v = (long long)s_cpx;
         if (v) {
             const int swap = Sw->swap;
             const int kind = phase == kSweep ? kPxSweep
