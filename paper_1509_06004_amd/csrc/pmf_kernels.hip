@@ -923,7 +923,7 @@ __device__ void relabel_tile(const StepParams &P, const InstDesc &D, InstState *
 // ---------------------------------------------------------------------------
 template <int K, int TW, int TH>
 __device__ void cut_tile_swapped(const StepParams &P, const InstDesc &D, InstState *S, int tl, int kk,
-                                 unsigned long long *s_sum) {
+                                 int *s_red, unsigned long long *s_sum) {
     using G = Geo<TW, TH>;
     constexpr int PPT = G::PPT, RPI = G::RPI;
     const int tid = threadIdx.x, lx = tid % TW, ly0 = tid / TW;
@@ -977,7 +977,7 @@ __device__ void cut_tile_swapped(const StepParams &P, const InstDesc &D, InstSta
     // relabel there): the tiles with a pixel made active by the raise are the
     // sweep's work (every other tile has none: the relabel that ended this
     // lambda left no active pixel).
-    const int tact = __syncthreads_or(act);
+    const int tact = block_any(act != 0, s_red + 28) ? 1 : 0;
     if (tid == 0) {
         if (tact) g_or(&gp(D.tile_act)[tl], 1u);
         gp(D.tile_chg)[tl] = 0;  // the cut is complete after this pass
@@ -1095,7 +1095,7 @@ __device__ void cut_tile(const StepParams &P, const InstDesc &D, InstState *S, i
             sh_w[(ly0 + j * RPI + 1) * HW + lx + 1] = rmv[j] | (nm << 15);
         }
         if ((it & 3) == 3 || it + 1 == P.local_bfs_iters) {
-            if (!__syncthreads_or(ch)) break;
+            if (!block_any(ch != 0, s_red + 16 + 4 * ((it >> 2) & 1))) break;
             ch = 0;
         }
     }
@@ -1122,7 +1122,7 @@ __device__ void cut_tile(const StepParams &P, const InstDesc &D, InstState *S, i
             got = 1;
         }
     }
-    if (!__syncthreads_or(got)) break;
+    if (!block_any(got != 0, s_red + 24)) break;
     }
     int changed = first ? 1 : 0;
 #pragma unroll
@@ -1133,7 +1133,7 @@ __device__ void cut_tile(const StepParams &P, const InstDesc &D, InstState *S, i
         if (first || m[j] != m0[j]) changed = 1;
         if (first || m[j] != mpub[j]) mask[gy * W + gx] = (uint8_t)m[j];
     }
-    const int tchg = __syncthreads_or(changed);
+    const int tchg = block_any(changed != 0, s_red + 28) ? 1 : 0;
     long long tse = 0;
     if (first) tse = block_sum_i64(se, s_sum);
     if (tid == 0) {
@@ -1141,7 +1141,6 @@ __device__ void cut_tile(const StepParams &P, const InstDesc &D, InstState *S, i
         if (tchg) atomicOr(&S->changed, 1);
         if (tse) atomicAdd((unsigned long long *)&S->sum_e, (unsigned long long)tse);
     }
-    (void)s_red;
 }
 
 // ---------------------------------------------------------------------------
@@ -1415,7 +1414,7 @@ __device__ void tile_work(const StepParams &P, int ws, int wp, int32_t *lds, int
             else if (phase == kRelabel)
                 relabel_tile<K, TW, TH, GAP>(P, D, S, tl, sub, xrounds, lds, s_red);
             else if (swap)
-                cut_tile_swapped<K, TW, TH>(P, D, S, tl, kk, s_sum);
+                cut_tile_swapped<K, TW, TH>(P, D, S, tl, kk, s_red, s_sum);
             else
                 cut_tile<K, TW, TH>(P, D, S, tl, sub, kk, xrounds, lds, s_red, s_sum);
         }
@@ -1431,7 +1430,7 @@ __device__ void tile_work(const StepParams &P, int ws, int wp, int32_t *lds, int
 template <int K, int TW, int TH, bool GAP, bool TIMED = false>
 __global__ __launch_bounds__(kThreads, K == 4 ? 4 : 1) void k_step(StepParams P, int ws, int wp) {
     __shared__ int32_t lds[(3 + K) * (TW + 2) * (TH + 2)];  // sweep layout; passes use 4 planes
-    __shared__ int s_red[32];  // [0]: block_count_ballot, [8..15]: block_vote, [16..27]: block_any
+    __shared__ int s_red[32];  // [0]: block_count_ballot, [8..15]: block_vote, [16..31]: block_any
     __shared__ unsigned long long s_sum;
     tile_work<K, TW, TH, GAP>(P, ws, wp, lds, s_red, &s_sum);
 }
@@ -1530,7 +1529,7 @@ extern __shared__ int32_t persist_lds[];
 
 template <int K, int TW, int TH>
 __device__ __attribute__((noinline)) void persist_work(const StepParams *Pg) {
-    __shared__ int s_red[32];  // [0]: block_count_ballot, [8..15]: block_vote, [16..27]: block_any
+    __shared__ int s_red[32];  // [0]: block_count_ballot, [8..15]: block_vote, [16..31]: block_any
     __shared__ unsigned long long s_sum;
     const StepParams P = load_params(Pg);
     tile_work<K, TW, TH, false>(P, K == 4 ? 0 : 1, K == 4 ? 2 : 3, persist_lds, s_red, &s_sum);
@@ -1558,7 +1557,7 @@ __device__ __attribute__((noinline)) int persist_control(const StepParams *Pg) {
 template <int TW, int TH, int KSET>
 __global__ __launch_bounds__(kThreads) void k_persist(const StepParams *Pg, int max_steps, int exit_tiles) {
     __shared__ int s_ok;
-    __shared__ int s_red[32];  // [0]: block_count_ballot, [8..15]: block_vote, [16..27]: block_any
+    __shared__ int s_red[32];  // [0]: block_count_ballot, [8..15]: block_vote, [16..31]: block_any
     __shared__ unsigned long long s_sum;
     const StepParams P = load_params(Pg);
     int32_t *bar = P.ring_count + kBarWords;
