@@ -376,7 +376,7 @@ __device__ void sweep_tile(const StepParams &P, const InstDesc &D, InstState *S,
     int32_t *sh_t = lds + 2 * HALO;  // [HALO] sink residuals (tile cells only)
     int32_t *sh_r = lds + 3 * HALO;  // [HALO][K] residuals; halo cells: pushes handed over
     __shared__ int s_nb[9];
-    __shared__ uint16_t s_slot[kThreads * PPT];  // per wave: its active pixels' cells
+    __shared__ uint16_t s_slot[kThreads * PPT + kThreads];  // per wave: its active pixels' cells; then one spare word per thread
 
     if (tid < 9) s_nb[tid] = 0;
     if (tid == 0) g_and(&gp(D.tile_act)[tl], ~2u);  // about to drain the inbox
@@ -522,7 +522,6 @@ __device__ void sweep_tile(const StepParams &P, const InstDesc &D, InstState *S,
     // by its own wave.
     const int lane = tid & 63;
     uint16_t *slot = s_slot + (tid >> 6) * (PPT * 64);
-    const unsigned long long below = (1ull << lane) - 1ull;
     for (int it = 0; it < iters; ++it) {
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         int ev[PPT], hv[PPT];
@@ -538,7 +537,12 @@ __device__ void sweep_tile(const StepParams &P, const InstDesc &D, InstState *S,
             const int c = (ly0 + j * RPI + 1) * HW + lx + 1;
             const bool a = (ev[j] > 0) & (hv[j] < kHInf);
             const unsigned long long m = __ballot(a);
-            if (a) slot[na + __popcll(m & below)] = (uint16_t)c;
+            // listed lanes below this one (hardware prefix count), and no
+            // branch: every lane writes, the unlisted ones to a word of their own
+            const int below_n =
+                (int)__builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
+            const int at = a ? (tid >> 6) * (PPT * 64) + na + below_n : kThreads * PPT + tid;
+            s_slot[at] = (uint16_t)c;
             na += __popcll(m);
         }
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
