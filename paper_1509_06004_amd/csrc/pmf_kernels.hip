@@ -656,16 +656,27 @@ __device__ void sweep_tile(const StepParams &P, const InstDesc &D, InstState *S,
 }
 
 // Whether this tile or one of its neighbours changed a label in the previous pass.
+// The nine flags are read unconditionally (a neighbour outside the image
+// reads the clamped, in-image position and is ignored), so that the loads
+// are in flight together.
 __device__ __forceinline__ bool frontier_needs(const InstDesc &D, int tx, int ty, int prev) {
     GLOBAL const uint8_t *chg = gp(D.tile_chg) + (size_t)prev * D.ntiles;
+    uint8_t f[9];
+#pragma unroll
+    for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
+        for (int dx = -1; dx <= 1; ++dx) {
+            const int ntx = min(max(tx + dx, 0), D.tiles_x - 1), nty = min(max(ty + dy, 0), D.tiles_y - 1);
+            f[(dy + 1) * 3 + dx + 1] = chg[nty * D.tiles_x + ntx];
+        }
     bool need = false;
 #pragma unroll
     for (int dy = -1; dy <= 1; ++dy)
 #pragma unroll
         for (int dx = -1; dx <= 1; ++dx) {
             const int ntx = tx + dx, nty = ty + dy;
-            if (ntx >= 0 && ntx < D.tiles_x && nty >= 0 && nty < D.tiles_y)
-                need |= chg[nty * D.tiles_x + ntx] != 0;
+            const bool in = ntx >= 0 && ntx < D.tiles_x && nty >= 0 && nty < D.tiles_y;
+            need |= in && f[(dy + 1) * 3 + dx + 1] != 0;
         }
     return need;
 }
