@@ -205,9 +205,22 @@ __device__ __forceinline__ long long block_sum_i64(long long v, unsigned long lo
 // Values are clamped to [0, INF]; err collects invalid values (bit 0) and
 // sink capacities that would exceed INF at the last lambda (bit 1).
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void terminal_caps(const InstDesc &D, int p, long long lam, long long lamL,
-                                              long long &cs, long long &ct, int &err) {
-    const int sd = D.seed ? (int)gp(D.seed)[p] : 0;
+// The raw inputs are read first, for every pixel (a seed's capacities are
+// read and ignored), so that a visit's loads are all in flight together.
+struct TermIn {
+    int sd, cs, c0, sl;
+};
+__device__ __forceinline__ TermIn load_term(const InstDesc &D, int p) {
+    TermIn t;
+    t.sd = D.seed ? (int)gp(D.seed)[p] : 0;
+    t.cs = gp(D.cap_src)[p];
+    t.c0 = gp(D.cap_snk0)[p];
+    t.sl = D.slope ? gp(D.slope)[p] : 1;
+    return t;
+}
+__device__ __forceinline__ void terminal_caps(const TermIn &t, long long lam, long long lamL, long long &cs,
+                                              long long &ct, int &err) {
+    const int sd = t.sd;
     if (sd == 1) {
         cs = kInf;
         ct = 0;
@@ -215,9 +228,9 @@ __device__ __forceinline__ void terminal_caps(const InstDesc &D, int p, long lon
         cs = 0;
         ct = kInf;
     } else {
-        const long long c0 = gp(D.cap_snk0)[p];
-        const long long sl = D.slope ? gp(D.slope)[p] : 1;
-        cs = gp(D.cap_src)[p];
+        const long long c0 = t.c0;
+        const long long sl = t.sl;
+        cs = t.cs;
         if (sd != 0) err |= 1;
         if (cs < 0 || cs > kInf || c0 < 0 || sl < 0) err |= 1;
         if (c0 + sl * lamL > kInf) err |= 2;
@@ -242,13 +255,19 @@ __device__ void orient_tile(const StepParams &P, const InstDesc &D, InstState *S
     const long long lam0 = gp(D.lambdas)[0];
     int err = 0;
     bool pos[G::PPT], neg[G::PPT];
+    TermIn tin[G::PPT];
+#pragma unroll
+    for (int j = 0; j < G::PPT; ++j) {  // pixels outside the image read a clamped position
+        const int gx = x0 + lx, gy = y0 + ly0 + j * G::RPI;
+        tin[j] = load_term(D, min(gy, H - 1) * W + min(gx, W - 1));
+    }
 #pragma unroll
     for (int j = 0; j < G::PPT; ++j) {
         const int gx = x0 + lx, gy = y0 + ly0 + j * G::RPI;
         pos[j] = neg[j] = false;
         if (gx >= W || gy >= H) continue;
         long long cs, ct;
-        terminal_caps(D, gy * W + gx, lam0, lam0, cs, ct, err);
+        terminal_caps(tin[j], lam0, lam0, cs, ct, err);
         pos[j] = cs > ct;
         neg[j] = cs < ct;
     }
@@ -283,14 +302,37 @@ __device__ void init_tile(const StepParams &P, const InstDesc &D, InstState *S, 
     const int32_t nlmax = ((1 << 30) - 1) / K;
     int err = 0;
     long long scs = 0;
+    // The pixels in two halves; each half's loads are all issued before any
+    // is used (pixels and neighbours outside the image read clamped
+    // positions): terminal inputs, n-links and, for an exchanged instance,
+    // the reverse n-links.
+    constexpr int HP = G::PPT / 2;
 #pragma unroll
-    for (int j = 0; j < G::PPT; ++j) {
+    for (int half = 0; half < 2; ++half) {
+    TermIn tin[HP];
+    int nl[HP][K], rv[HP][K];
+#pragma unroll
+    for (int jj = 0; jj < HP; ++jj) {
+        const int j = half * HP + jj;
+        const int gx = min(x0 + lx, W - 1), gy = min(y0 + ly0 + j * G::RPI, H - 1);
+        const int p = gy * W + gx;
+        tin[jj] = load_term(D, p);
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            nl[jj][k] = gp(D.nlink)[(size_t)k * n + p];
+            const int qx = min(max(gx + DXk(k), 0), W - 1), qy = min(max(gy + DYk(k), 0), H - 1);
+            rv[jj][k] = swap ? gp(D.nlink)[(size_t)(k ^ 1) * n + qy * W + qx] : 0;
+        }
+    }
+#pragma unroll
+    for (int jj = 0; jj < HP; ++jj) {
+        const int j = half * HP + jj;
         const int ly = ly0 + j * G::RPI;
         const int gx = x0 + lx, gy = y0 + ly;
         if (gx >= W || gy >= H) continue;
         const int p = gy * W + gx;
         long long cs, ct;
-        terminal_caps(D, p, lam0, lamL, cs, ct, err);
+        terminal_caps(tin[jj], lam0, lamL, cs, ct, err);
         if (swap) {
             const long long t = cs;
             cs = ct;
@@ -305,10 +347,10 @@ __device__ void init_tile(const StepParams &P, const InstDesc &D, InstState *S, 
         for (int k = 0; k < K; ++k) {
             const int qx = gx + DXk(k), qy = gy + DYk(k);
             const bool on = qx >= 0 && qx < W && qy >= 0 && qy < H;
-            int c = gp(D.nlink)[(size_t)k * n + p];  // validated here, once per arc
+            int c = nl[jj][k];  // validated here, once per arc
             if (c < 0 || (!on && c != 0)) err |= 1;
             if (c > nlmax) err |= 2;
-            if (swap) c = on ? gp(D.nlink)[(size_t)(k ^ 1) * n + qy * W + qx] : 0;
+            if (swap) c = on ? rv[jj][k] : 0;
             if (!on || c < 0) c = 0;
             if (c > nlmax) c = nlmax;
             gp(D.r)[(size_t)k * n + p] = c;
@@ -318,6 +360,7 @@ __device__ void init_tile(const StepParams &P, const InstDesc &D, InstState *S, 
         gp(D.rt)[p] = rt;
         gp(D.h)[p] = rt > 0 ? 1 : kHInf;
         gp(D.rmask)[p] = (uint16_t)rm;
+    }
     }
     for (int i = tid; i < Border<K, TW, TH>::E; i += kThreads)
         gp(D.inbox)[(size_t)tl * Border<K, TW, TH>::E + i] = 0;
