@@ -222,6 +222,8 @@ struct pmf_handle {
     StepParams P;
     hipGraphExec_t graph = nullptr;
     int graph_S = 0;
+    StepParams graph_P;  // the parameters the graph was captured with (a new work list of the same
+                         // shape and place, e.g. the next batch of the same sizes, replays it as it is)
     pmf_stats stats;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;  // bracket every launch group (device time)
     // timing mode: six events per superstep of a host round (start and end
@@ -308,8 +310,7 @@ int ensure_arena(pmf_handle *h, size_t need) {
 // polling are then ordinary host memory).
 int open_session(pmf_handle *h, int slots, size_t pool_bytes, char *ext_base = nullptr, size_t ext_bytes = 0) {
     if (slots < 1) return PMF_EINVAL;
-    drop_graph(h);
-    h->open = false;
+    h->open = false;  // a captured graph stays: it is replayed only while the parameters match
     (void)hipStreamSynchronize(h->stream);
     const size_t wl = worklist_cap(slots, pool_bytes);
     const size_t ctl = control_bytes(slots, wl);
@@ -425,7 +426,6 @@ int rebuild_worklist(pmf_handle *h) {
         // pageable source: the copy must finish before the vector goes
         if (hipStreamSynchronize(h->stream) != hipSuccess) return PMF_EDEVICE;
     }
-    drop_graph(h);
     h->wl_dirty = false;
     h->wl_finished = 0;
     h->epoch_steps = 0;
@@ -518,13 +518,18 @@ int submit(pmf_handle *h, const pmf_instance *inst, int n, int64_t *flows_out, i
         s.masks = h->pool_base + offs[i] + B.masks;
         if (ids_out) ids_out[i] = id;
     }
-    // descriptors and states go to their slots (ids need not be contiguous)
-    for (int i = 0; i < n; ++i) {
-        if (hipMemcpyAsync(h->P.desc + ids[i], &desc[i], sizeof(InstDesc), hipMemcpyHostToDevice, h->stream) !=
-                hipSuccess ||
-            hipMemcpyAsync(h->P.st + ids[i], &st[i], sizeof(InstState), hipMemcpyHostToDevice, h->stream) !=
+    // descriptors and states go to their slots, one copy per run of
+    // consecutive ids (ids need not be contiguous; a fresh batch is one run)
+    for (int i = 0; i < n;) {
+        int j = i + 1;
+        while (j < n && ids[j] == ids[j - 1] + 1) ++j;
+        const size_t cnt = (size_t)(j - i);
+        if (hipMemcpyAsync(h->P.desc + ids[i], &desc[i], sizeof(InstDesc) * cnt, hipMemcpyHostToDevice,
+                           h->stream) != hipSuccess ||
+            hipMemcpyAsync(h->P.st + ids[i], &st[i], sizeof(InstState) * cnt, hipMemcpyHostToDevice, h->stream) !=
                 hipSuccess)
             return PMF_EDEVICE;
+        i = j;
     }
     if (hipStreamSynchronize(h->stream) != hipSuccess) return PMF_EDEVICE;
     if (n) h->wl_dirty = true;
@@ -624,9 +629,11 @@ int run_steps(pmf_handle *h, int steps, std::vector<int> *finished, int persist_
         }
     }
     if (P.ntiles > 0 && !persisted) {
-        // replay a captured graph once the work list has been used once
-        const bool use_graph = h->opt.use_graph && !timing && !h->ext && h->epoch_steps > 0;
-        if (use_graph && (!h->graph || h->graph_S != steps)) {
+        // replay a captured graph: a batch's work list from its first superstep
+        // (it stays the same for the whole solve), a session's once it has been
+        // used once; the graph is captured again when the parameters changed
+        const bool use_graph = h->opt.use_graph && !timing && !h->ext && (h->batch || h->epoch_steps > 0);
+        if (use_graph && (!h->graph || h->graph_S != steps || std::memcmp(&h->graph_P, &P, sizeof(P)) != 0)) {
             drop_graph(h);
             hipGraph_t g = nullptr;
             bool ok = hipStreamBeginCapture(h->capture, hipStreamCaptureModeThreadLocal) == hipSuccess;
@@ -640,6 +647,7 @@ int run_steps(pmf_handle *h, int steps, std::vector<int> *finished, int persist_
                 return PMF_EDEVICE;
             }
             h->graph_S = steps;
+            h->graph_P = P;
         }
         if (hipEventRecord(h->ev0, s) != hipSuccess) return PMF_EDEVICE;
         if (use_graph) {

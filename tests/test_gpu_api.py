@@ -123,3 +123,28 @@ def test_pixel_visit_statistics(pmf):
             own = [st["px_sweep"], st["px_relabel"], st["px_cut"], st["px_init"], st["px_orient"],
                    st["px_init_x"], st["px_cut_x"]]
             assert [int(kp[i]) + int(kp[8 + i]) for i in range(7)] == own
+
+
+def test_same_shape_batches_on_one_handle(pmf):
+    """Consecutive batches of the same shape on one handle (the captured
+    superstep graph is replayed for the second, with new descriptors and
+    states): each batch equals the oracle, element by element."""
+    import torch
+    s = pmf.Solver()
+    for seed in (11, 12):
+        rng = np.random.default_rng(seed)
+        insts = [W.tiny_random(rng, 70, 50, K, cmax=40, L=4, lam_max=40) for K in (4, 4, 8)]
+        dev = pmf.to_device(insts)
+        flows, status = s.solve(dev)
+        torch.cuda.synchronize()
+        assert int(status.cpu().max()) == 0
+        f = flows.cpu().numpy()
+        off = 0
+        for i, inst in enumerate(insts):
+            for k in range(inst.L):
+                fo, mo = O.fifo_pr(inst, int(inst.lambdas[k]))
+                assert int(f[off + k]) == fo, (seed, i, k)
+                got = s.extract_cut(i, k).cpu().numpy().astype(bool)
+                assert np.array_equal(got, np.asarray(mo, dtype=bool).reshape(inst.H, inst.W)), (seed, i, k)
+            off += inst.L
+        say("batch", seed, "equals the oracle; supersteps", s.stats()["supersteps"])
