@@ -1350,8 +1350,9 @@ __device__ void compact_instance(const StepParams &P, int w) {
     const int slot = __builtin_amdgcn_readfirstlane(P.wl_slot[w]);
     const InstState *S = &P.st[slot];
     const int phase = __builtin_amdgcn_readfirstlane(S->phase);
-    if (phase != kSweep && phase != kInit && phase != kOrient && phase != kRelabel && phase != kCut) return;
     const int sub = __builtin_amdgcn_readfirstlane(S->sub);
+    const int swap = __builtin_amdgcn_readfirstlane(S->swap);  // read with the phase: the kind of the visits
+    if (phase != kSweep && phase != kInit && phase != kOrient && phase != kRelabel && phase != kCut) return;
     const InstDesc D = load_desc(P.desc, slot);
     const bool is8 = D.K == 8;
     int2 *lists = reinterpret_cast<int2 *>(P.lists);
@@ -1405,7 +1406,6 @@ __device__ void compact_instance(const StepParams &P, int w) {
         InstState *Sw = &P.st[slot];
         Sw->listed = any;
         if (v) {
-            const int swap = Sw->swap;
             const int kind = phase == kSweep ? kPxSweep
                              : phase == kRelabel ? kPxRelabel
                              : phase == kOrient ? kPxOrient
@@ -1418,7 +1418,7 @@ __device__ void compact_instance(const StepParams &P, int w) {
                            : kind == kPxInitX   ? &Sw->px_init_x
                            : kind == kPxCut     ? &Sw->px_cut
                                                 : &Sw->px_cut_x;
-            *ctr += v;  // no other kernel runs meanwhile, and only this workgroup writes the instance's counters
+            count_px(ctr, v);  // no reply awaited
             if (P.kpx) count_px(&P.kpx[kind], v);
         }
     }
