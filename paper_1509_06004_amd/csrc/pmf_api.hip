@@ -418,6 +418,8 @@ int rebuild_worklist(pmf_handle *h) {
     P.t4_count = (int32_t)t4;
     P.t8_count = (int32_t)t8;
     P.nwl = (int32_t)ids.size();
+    P.wl_ident = 1;
+    for (size_t w = 0; w < ids.size(); ++w) P.wl_ident &= ids[w] == (int)w ? 1 : 0;
     if (!ids.empty()) {
         std::vector<int32_t> wl(ids.begin(), ids.end());
         if (hipMemcpyAsync((void *)P.wl_slot, wl.data(), 4 * wl.size(), hipMemcpyHostToDevice, h->stream) !=

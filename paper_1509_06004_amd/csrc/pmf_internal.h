@@ -111,6 +111,7 @@ struct StepParams {
     InstState *st;              // [nslots]
     const int32_t *wl_slot;     // work list: slots of the live instances, 4-connected first
     int32_t nwl;                // entries of wl_slot
+    int32_t wl_ident;           // 1: wl_slot[w] == w for every entry (the kernels then skip the lookup)
     int32_t *ring;              // completion ring: slots in order of completion
     int32_t *ring_count;        // completions so far (ring index = count % ring_cap)
     int32_t ring_cap;

@@ -1207,7 +1207,7 @@ __device__ void cut_tile(const StepParams &P, const InstDesc &D, InstState *S, i
 // ---------------------------------------------------------------------------
 // Returns whether the instance is still running afterwards.
 __device__ bool control_one(const StepParams &P, int w) {
-    const int i = P.wl_slot[w];
+    const int i = P.wl_ident ? w : P.wl_slot[w];
     // The state and the descriptor fields used here are read in one batch:
     // this kernel runs alone after the tile kernels of the superstep, whose
     // writes it sees at the launch boundary.
@@ -1347,7 +1347,7 @@ __device__ __forceinline__ void wave_append(bool want, int2 *list, int32_t *coun
 // the instance's own workgroup, rather than by every visit.
 __device__ void compact_instance(const StepParams &P, int w) {
     __shared__ int s_vote[8];
-    const int slot = __builtin_amdgcn_readfirstlane(P.wl_slot[w]);
+    const int slot = P.wl_ident ? w : __builtin_amdgcn_readfirstlane(P.wl_slot[w]);
     const InstState *S = &P.st[slot];
     const int phase = __builtin_amdgcn_readfirstlane(S->phase);
     const int sub = __builtin_amdgcn_readfirstlane(S->sub);
