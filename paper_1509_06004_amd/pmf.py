@@ -367,24 +367,26 @@ class DeviceInstance:
                          ptr(self.cap_snk0), ptr(self.snk_slope), ptr(self.seed), ptr(self.lambdas))
 
 
-def to_device(insts, device="cuda", share: Optional[Dict[int, torch.Tensor]] = None,
+def to_device(insts, device="cuda", share: Optional[Dict[int, tuple]] = None,
               non_blocking: bool = False) -> List[DeviceInstance]:
     """Upload host instances (objects with the fields of ``workload.Instance``).
     Arrays that are the same numpy object (n-links of one image, shared
-    constant planes) get one device copy."""
+    constant planes) get one device copy.  A ``share`` dict passed in carries
+    that over calls: it holds each uploaded array with its copy (keeping the
+    array alive, so that a later object can never be taken for it)."""
     share = {} if share is None else share
-    keep = []  # the numpy objects behind the keys must outlive this call
 
     def up(a, dt):
         key = id(a)
-        if key not in share:
+        hit = share.get(key)
+        if hit is None or hit[0] is not a:
             c = np.ascontiguousarray(a, dtype=dt)
             h = torch.from_numpy(c if c.flags.writeable else c.copy())
             if non_blocking:
                 h = h.pin_memory()
-            share[key] = h.to(device, non_blocking=non_blocking)
-            keep.append(a)
-        return share[key]
+            hit = (a, h.to(device, non_blocking=non_blocking))
+            share[key] = hit
+        return hit[1]
 
     out = []
     for inst in insts:

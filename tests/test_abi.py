@@ -86,3 +86,21 @@ def test_query_bytes_scales_with_size(lib):
     assert eight >= px * ((8 + 3) * 4 + 2 + 20) + tiles * 384 * 4
     with pytest.raises(pmf.PmfError):
         pmf.pmf_query_bytes([_fake(K=5)])
+
+
+def test_to_device_share_never_returns_another_arrays_copy():
+    """A share dict carried over calls holds each uploaded array with its
+    copy; an entry under the id of a new object but for another array (ids of
+    dead objects are reused) is not taken for the new one."""
+    import torch
+    from paper_1509_06004_amd import pmf, workload
+    inst = workload.config0()[0]
+    share = {}
+    first = pmf.to_device([inst], device="cpu", share=share)[0]
+    assert torch.equal(first.lambdas, torch.from_numpy(inst.lambdas))
+    again = pmf.to_device([inst], device="cpu", share=share)[0]
+    assert again.lambdas is first.lambdas  # same object: one copy
+    other = inst.with_lambdas(inst.lambdas + 1)
+    share[id(other.lambdas)] = (object(), torch.zeros(3, dtype=torch.int32))  # a stale entry under its id
+    got = pmf.to_device([other], device="cpu", share=share)[0]
+    assert torch.equal(got.lambdas, torch.from_numpy(other.lambdas))
