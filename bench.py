@@ -365,7 +365,7 @@ def main():
 
     if args.gpus != 1:
         print("bench.py runs on one GPU only: instances are independent, so more GPUs would each "
-              "run their own copy of this workload (see the sharding note in DESIGN.md); "
+              "take their own share of the instances (a host router, no exchange between GPUs); "
               "--gpus %d is not supported" % args.gpus, file=sys.stderr)
         sys.exit(2)
 
