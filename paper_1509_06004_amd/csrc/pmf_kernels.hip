@@ -309,58 +309,58 @@ __device__ void init_tile(const StepParams &P, const InstDesc &D, InstState *S, 
     constexpr int HP = G::PPT / 2;
 #pragma unroll
     for (int half = 0; half < 2; ++half) {
-    TermIn tin[HP];
-    int nl[HP][K], rv[HP][K];
+        TermIn tin[HP];
+        int nl[HP][K], rv[HP][K];
 #pragma unroll
-    for (int jj = 0; jj < HP; ++jj) {
-        const int j = half * HP + jj;
-        const int gx = min(x0 + lx, W - 1), gy = min(y0 + ly0 + j * G::RPI, H - 1);
-        const int p = gy * W + gx;
-        tin[jj] = load_term(D, p);
+        for (int jj = 0; jj < HP; ++jj) {
+            const int j = half * HP + jj;
+            const int gx = min(x0 + lx, W - 1), gy = min(y0 + ly0 + j * G::RPI, H - 1);
+            const int p = gy * W + gx;
+            tin[jj] = load_term(D, p);
 #pragma unroll
-        for (int k = 0; k < K; ++k) {
-            nl[jj][k] = gp(D.nlink)[(size_t)k * n + p];
-            const int qx = min(max(gx + DXk(k), 0), W - 1), qy = min(max(gy + DYk(k), 0), H - 1);
-            rv[jj][k] = swap ? gp(D.nlink)[(size_t)(k ^ 1) * n + qy * W + qx] : 0;
+            for (int k = 0; k < K; ++k) {
+                nl[jj][k] = gp(D.nlink)[(size_t)k * n + p];
+                const int qx = min(max(gx + DXk(k), 0), W - 1), qy = min(max(gy + DYk(k), 0), H - 1);
+                rv[jj][k] = swap ? gp(D.nlink)[(size_t)(k ^ 1) * n + qy * W + qx] : 0;
+            }
         }
-    }
 #pragma unroll
-    for (int jj = 0; jj < HP; ++jj) {
-        const int j = half * HP + jj;
-        const int ly = ly0 + j * G::RPI;
-        const int gx = x0 + lx, gy = y0 + ly;
-        if (gx >= W || gy >= H) continue;
-        const int p = gy * W + gx;
-        long long cs, ct;
-        terminal_caps(tin[jj], lam0, lamL, cs, ct, err);
-        if (swap) {
-            const long long t = cs;
-            cs = ct;
-            ct = t;
-        }
-        const long long m = cs < ct ? cs : ct;
-        const int e = (int)(cs - m);
-        const int rt = (int)(ct - m);
-        scs += cs;
-        int rm = (rt > 0 ? kRtBit : 0) | (e > 0 ? kEBit : 0);
+        for (int jj = 0; jj < HP; ++jj) {
+            const int j = half * HP + jj;
+            const int ly = ly0 + j * G::RPI;
+            const int gx = x0 + lx, gy = y0 + ly;
+            if (gx >= W || gy >= H) continue;
+            const int p = gy * W + gx;
+            long long cs, ct;
+            terminal_caps(tin[jj], lam0, lamL, cs, ct, err);
+            if (swap) {
+                const long long t = cs;
+                cs = ct;
+                ct = t;
+            }
+            const long long m = cs < ct ? cs : ct;
+            const int e = (int)(cs - m);
+            const int rt = (int)(ct - m);
+            scs += cs;
+            int rm = (rt > 0 ? kRtBit : 0) | (e > 0 ? kEBit : 0);
 #pragma unroll
-        for (int k = 0; k < K; ++k) {
-            const int qx = gx + DXk(k), qy = gy + DYk(k);
-            const bool on = qx >= 0 && qx < W && qy >= 0 && qy < H;
-            int c = nl[jj][k];  // validated here, once per arc
-            if (c < 0 || (!on && c != 0)) err |= 1;
-            if (c > nlmax) err |= 2;
-            if (swap) c = on ? rv[jj][k] : 0;
-            if (!on || c < 0) c = 0;
-            if (c > nlmax) c = nlmax;
-            gp(D.r)[(size_t)k * n + p] = c;
-            if (c > 0) rm |= 1 << k;
+            for (int k = 0; k < K; ++k) {
+                const int qx = gx + DXk(k), qy = gy + DYk(k);
+                const bool on = qx >= 0 && qx < W && qy >= 0 && qy < H;
+                int c = nl[jj][k];  // validated here, once per arc
+                if (c < 0 || (!on && c != 0)) err |= 1;
+                if (c > nlmax) err |= 2;
+                if (swap) c = on ? rv[jj][k] : 0;
+                if (!on || c < 0) c = 0;
+                if (c > nlmax) c = nlmax;
+                gp(D.r)[(size_t)k * n + p] = c;
+                if (c > 0) rm |= 1 << k;
+            }
+            gp(D.e)[p] = e;
+            gp(D.rt)[p] = rt;
+            gp(D.h)[p] = rt > 0 ? 1 : kHInf;
+            gp(D.rmask)[p] = (uint16_t)rm;
         }
-        gp(D.e)[p] = e;
-        gp(D.rt)[p] = rt;
-        gp(D.h)[p] = rt > 0 ? 1 : kHInf;
-        gp(D.rmask)[p] = (uint16_t)rm;
-    }
     }
     for (int i = tid; i < Border<K, TW, TH>::E; i += kThreads)
         gp(D.inbox)[(size_t)tl * Border<K, TW, TH>::E + i] = 0;
