@@ -215,3 +215,42 @@ def test_serving_loop_results_exact(env, chunk):
                 f, m = O.fifo_pr(inst, lam)
                 assert res.flows[k] == f
                 assert ((res.levels > k) == m).all()
+
+
+def test_session_after_batch_on_one_handle(env):
+    """A batch solve, then a session on the same handle: the superstep graph
+    the batch captured stays with the handle and must not serve the session's
+    other work list.  Every session result equals the instance solved alone,
+    and the batch's results equal their own solves alone."""
+    torch, pmf = env
+    o = pmf.pmf_default_options()
+    o.max_supersteps = 400000
+    h = pmf.pmf_create(o, int(torch.cuda.current_stream().cuda_stream))
+    batch = mixed_instances(21, 5)
+    devb = pmf.to_device(batch)
+    fb = torch.full((sum(d.L for d in devb),), -7, dtype=torch.int64, device="cuda")
+    sb = torch.full((len(devb),), -7, dtype=torch.int32, device="cuda")
+    assert pmf.pmf_solve_batch(h, [d.c_struct() for d in devb], int(fb.data_ptr()), int(sb.data_ptr())) == 0
+    torch.cuda.synchronize()
+    off = 0
+    for inst in batch:
+        f, st, _ = alone(env, inst)
+        assert st == 0 and np.array_equal(fb.cpu().numpy()[off:off + inst.L], f)
+        off += inst.L
+    S = Session.__new__(Session)
+    S.torch, S.pmf, S.h, S.keep = torch, pmf, h, {}
+    assert pmf.pmf_session_open(h, 64, 0) == pmf.PMF_OK
+    insts = mixed_instances(22, 6)
+    rc, ids = S.submit(insts)
+    assert rc == pmf.PMF_OK
+    left = set(ids)
+    for _ in range(20000):
+        left -= set(S.step(16))
+        if not left:
+            break
+    assert not left
+    for i, inst in zip(ids, insts):
+        f, st, m, _ = S.result(i)
+        fa, sa, ma = alone(env, inst)
+        assert st == sa == 0 and np.array_equal(f, fa) and np.array_equal(m, ma), i
+    S.close()
