@@ -330,8 +330,10 @@ int pmf_slot_stats(pmf_handle *h, int64_t *out, int32_t max_slots, int32_t *n_sl
  * Sec. 2.1: the minimal source sets are nested as lambda grows and F is
  * concave and piecewise linear in lambda).  Finds every integer lambda c in
  * (lam_lo, lam_hi] with S_min(c) != S_min(c - 1), exactly: intervals whose end
- * sets differ in size are split where the two end pieces of F meet, and all
- * open intervals of a round are solved in one batched call on this handle.
+ * sets differ in size are probed on both sides of the point where the two end
+ * pieces of F meet and at points spread over the interval (up to 64 probes a
+ * round, fewer for images too large for 64 solves in 1 GiB), and all probes
+ * of a round are solved in one batched call on this handle.
  * inst->lambdas and inst->L are ignored; the other fields are as for
  * pmf_solve_batch (device pointers).  Blocking.
  *   bp_out   host, max_bp entries: the change points in increasing order

@@ -998,14 +998,6 @@ int locate(pmf_handle *h, int32_t inst, int32_t lambda_idx, int *slot, int *k) {
     return PMF_OK;
 }
 
-}  // namespace
-
-extern "C" {
-
-}  // extern "C"
-
-namespace {
-
 // pmf_solve_batch, with its state in the arena or in ext_bytes of device
 // memory at ext_base (a solve that allocates nothing).
 int solve_batch(pmf_handle *h, const pmf_instance *inst, int32_t n_inst, int64_t *flows_out, int32_t *status_out,
@@ -1327,16 +1319,27 @@ int pmf_parametric(pmf_handle *h, const pmf_instance *inst, int32_t lam_lo, int3
         (void)hipStreamSynchronize(h->stream);
         h->reserve_tail = 0;
     };
+    // Probes per round: the batched call solves them side by side, so a round
+    // costs about as much as its slowest chunk until the device fills, and
+    // fewer, wider rounds win.  The budget shrinks for large images so that
+    // the round's state stays within 1 GiB.
+    int budget = 64;
+    for (pmf_instance I = base; budget > 2; budget /= 2) {
+        I.L = budget;
+        int64_t subs = 0;
+        if (batch_pool_bytes(&I, 1, 1, h->tw, h->th, h->opt.gap != 0, &subs) <= ((size_t)1 << 30)) break;
+    }
     // Solve the (ascending, distinct) lambdas of `lams` as the schedule of one
     // instance: the batched call splits it into warm-started chunks solved in
     // parallel.  The round's own device data (lambdas, flows, status, mask
-    // statistics, one mask) sit at the end of the handle's arena, which is
-    // first grown to hold them next to the largest layout the call can pick
-    // (every lambda a chunk of its own), so that the call never moves it.
+    // statistics) sit at the end of the handle's arena, which is first grown to
+    // hold them next to the largest layout the call can pick (every lambda a
+    // chunk of its own), so that the call never moves it.  The masks are read
+    // where the solve left them.
     auto solve = [&](const std::vector<int32_t> &lams) -> int {
         const int m = (int)lams.size();
         const size_t o_f = align_up(4 * (size_t)m), o_s = o_f + align_up(8 * (size_t)m), o_st = o_s + align_up(4),
-                     o_m = o_st + align_up(16 * (size_t)m), T = o_m + align_up((size_t)n);
+                     T = o_st + align_up(16 * (size_t)m);
         pmf_instance I = base;
         I.L = m;
         int64_t subs = 0;
@@ -1351,7 +1354,6 @@ int pmf_parametric(pmf_handle *h, const pmf_instance *inst, int32_t lam_lo, int3
         int64_t *df = (int64_t *)(tail + o_f);
         int32_t *ds = (int32_t *)(tail + o_s);
         int64_t *dst = (int64_t *)(tail + o_st);
-        uint8_t *dm = (uint8_t *)(tail + o_m);
         if (hipMemcpyAsync(dl, lams.data(), 4 * (size_t)m, hipMemcpyHostToDevice, h->stream) != hipSuccess ||
             hipMemsetAsync(dst, 0, 16 * (size_t)m, h->stream) != hipSuccess)
             return PMF_EDEVICE;
@@ -1362,10 +1364,12 @@ int pmf_parametric(pmf_handle *h, const pmf_instance *inst, int32_t lam_lo, int3
         if (hipMemcpy(&st, ds, 4, hipMemcpyDeviceToHost) != hipSuccess) return PMF_EDEVICE;
         if (st != PMF_OK) return st;
         for (int i = 0; i < m; ++i) {
-            rc = pmf_extract_cut(h, 0, i, dm);
+            int slot, k;
+            rc = locate(h, 0, i, &slot, &k);
             if (rc != PMF_OK) return rc;
-            if (launch_mask_stats(dm, n, base.snk_slope, base.seed, dst + 2 * i, h->stream) != 0) return PMF_EDEVICE;
-            if (exit_out && launch_exit_min(dm, n, lams[i], exit_out, h->stream) != 0) return PMF_EDEVICE;
+            const uint8_t *mask = (const uint8_t *)(h->base + h->slots[slot].masks + (size_t)k * n);
+            if (launch_mask_stats(mask, n, base.snk_slope, base.seed, dst + 2 * i, h->stream) != 0) return PMF_EDEVICE;
+            if (exit_out && launch_exit_min(mask, n, lams[i], exit_out, h->stream) != 0) return PMF_EDEVICE;
         }
         std::vector<int64_t> f(m), sw(2 * (size_t)m);
         if (hipMemcpyAsync(f.data(), df, 8 * (size_t)m, hipMemcpyDeviceToHost, h->stream) != hipSuccess ||
@@ -1380,6 +1384,42 @@ int pmf_parametric(pmf_handle *h, const pmf_instance *inst, int32_t lam_lo, int3
         }
         return PMF_OK;
     };
+    // Up to k probes strictly inside (a, b), an interval whose end sets differ
+    // (nested sets are equal exactly when their sizes are), into `out`.  When k
+    // covers every integer inside, all of them.  Otherwise first the two
+    // integers around the meeting point x of the end pieces of F,
+    // F(a) + w_a (l - a) and F(b) + w_b (l - b): a single change point c in
+    // (a, b] satisfies c - 1 < x <= c, so ceil(x) - 1 and ceil(x) isolate it
+    // (the midpoint instead when w_a = w_b, which free pixels of slope 0
+    // allow).  The rest are spread over (a, b), geometrically when a > 0, for
+    // intervals that hold several change points.
+    auto probes = [&](int32_t a, int32_t b, int k, std::vector<int32_t> &out) {
+        if ((int64_t)b - a - 1 <= k) {
+            for (int32_t x = a + 1; x < b; ++x) out.push_back(x);
+            return;
+        }
+        std::vector<int32_t> mine;
+        auto add = [&](int64_t x) {
+            x = std::min<int64_t>(std::max<int64_t>(x, (int64_t)a + 1), (int64_t)b - 1);
+            if (std::find(mine.begin(), mine.end(), (int32_t)x) == mine.end()) mine.push_back((int32_t)x);
+        };
+        const Point &pa = pts[a], &pb = pts[b];
+        if (pa.w > pb.w) {
+            const long double x = ((long double)pb.F - pa.F + (long double)pa.w * a - (long double)pb.w * b) /
+                                  (long double)(pa.w - pb.w);
+            const int64_t c = (int64_t)std::ceil(x);
+            add(c);
+            add(c - 1);
+        } else {
+            add((int64_t)a + (b - a) / 2);
+        }
+        const int rest = k - (int)mine.size();
+        for (int j = 1; j <= rest; ++j) {
+            const double t = (double)j / (rest + 1);
+            add(a > 0 ? (int64_t)std::llround(a * std::pow((double)b / a, t)) : (int64_t)a + (int64_t)((b - a) * t));
+        }
+        out.insert(out.end(), mine.begin(), mine.end());
+    };
     std::vector<int32_t> ends = {lam_lo};
     if (lam_hi > lam_lo) ends.push_back(lam_hi);
     int rc = solve(ends);
@@ -1387,38 +1427,24 @@ int pmf_parametric(pmf_handle *h, const pmf_instance *inst, int32_t lam_lo, int3
         release();
         return rc;
     }
-    // Intervals whose end sets differ hold a change point (nested sets are
-    // equal exactly when their sizes are).  Each is split where the two
-    // end-pieces of F, F(a) + w_a (x - a) and F(b) + w_b (x - b), meet: with
-    // a single change point in between, that point c satisfies c - 1 < x <= c,
-    // and two more solves isolate it.
+    // Open intervals: consecutive solved lambdas whose sets differ.  One of
+    // length 1 is a change point; the others share the round's probe budget.
     std::vector<std::pair<int32_t, int32_t>> open;
     if (lam_hi > lam_lo && pts[lam_lo].size != pts[lam_hi].size) open.push_back({lam_lo, lam_hi});
     std::vector<int32_t> changes;
     while (!open.empty()) {
-        std::vector<int32_t> mids;
-        std::vector<std::pair<int32_t, int32_t>> wait;
+        std::vector<std::pair<int32_t, int32_t>> live;
         for (const auto &iv : open) {
-            const int32_t a = iv.first, b = iv.second;
-            if (b - a == 1) {
-                changes.push_back(b);
-                continue;
-            }
-            const Point &pa = pts[a], &pb = pts[b];
-            int64_t mid = a + (b - a) / 2;
-            if (pa.w > pb.w) {
-                // x = (F(b) - F(a) + w_a a - w_b b) / (w_a - w_b), rounded up
-                const long double x = ((long double)pb.F - pa.F + (long double)pa.w * a - (long double)pb.w * b) /
-                                      (long double)(pa.w - pb.w);
-                mid = (int64_t)std::ceil(x);
-            }
-            mid = std::min<int64_t>(std::max<int64_t>(mid, (int64_t)a + 1), (int64_t)b - 1);
-            if (pts.count((int32_t)mid)) mid = a + (b - a) / 2;  // already solved: plain bisection
-            mids.push_back((int32_t)mid);
-            wait.push_back(iv);
+            if (iv.second - iv.first == 1)
+                changes.push_back(iv.second);
+            else
+                live.push_back(iv);
         }
         open.clear();
-        if (mids.empty()) break;
+        if (live.empty()) break;
+        const int k = std::max(2, budget / (int)live.size());
+        std::vector<int32_t> mids;
+        for (const auto &iv : live) probes(iv.first, iv.second, k, mids);
         std::sort(mids.begin(), mids.end());
         mids.erase(std::unique(mids.begin(), mids.end()), mids.end());
         rc = solve(mids);
@@ -1426,8 +1452,8 @@ int pmf_parametric(pmf_handle *h, const pmf_instance *inst, int32_t lam_lo, int3
             release();
             return rc;
         }
-        for (const auto &iv : wait) {
-            // the solved lambdas strictly inside (a, b) cut it into pieces
+        for (const auto &iv : live) {
+            // the solved lambdas inside (a, b) cut it into pieces
             auto it = pts.upper_bound(iv.first);
             int32_t prev = iv.first;
             for (; it != pts.end() && it->first <= iv.second; ++it) {

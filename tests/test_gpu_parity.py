@@ -428,6 +428,13 @@ def test_parametric_breakpoints(pmf):
         Wd, Hd = int(rng.integers(2, 12)), int(rng.integers(2, 12))
         inst = W.tiny_random(rng, Wd, Hd, 4 if i % 2 else 8, cmax=40, L=1, p_seed=0.1)
         cases.append((inst, int(rng.integers(0, 5)), int(rng.integers(20, 90))))
+    # ranges wider than one round's probes: the meeting-point pair and the
+    # spread probes decide which intervals stay open
+    rng2 = np.random.default_rng(98)
+    for i in range(6):
+        Wd, Hd = int(rng2.integers(3, 17)), int(rng2.integers(3, 17))
+        inst = W.tiny_random(rng2, Wd, Hd, 4 if i % 2 else 8, cmax=200, L=1, p_seed=0.05)
+        cases.append((inst, int(rng2.integers(0, 5)), int(rng2.integers(300, 900))))
     cases.append((W.config0()[0], 0, 250))
     s = pmf.Solver()
     for ci, (inst, lo, hi) in enumerate(cases):

@@ -9,6 +9,10 @@
   (F equals the cost of the returned cut, recomputed from the original
   capacities, so both are optimal) and by nesting across lambda; the first,
   middle and last lambda of every instance are compared with oracle solves.
+* All breakpoints of seeds of the benchmark workload over lambda 1..2000:
+  oracle solves at both ends of the range and on both sides of every
+  reported change point prove the list complete (the sets are nested in
+  lambda, so equal sets at both ends of a gap leave no change inside it).
 * The int32 headroom: n-links at the largest admitted capacity next to
   INF seeds, where excess reaches INF + K * PMF_NLINK_MAX(K).
 
@@ -117,6 +121,41 @@ def test_config3_full_size(pmf):
         for c, f, i, k in cert:
             assert c.result() == f, ("certificate", i, k, c.result(), f)
     say("config3: all %d solves pass the certificate and nesting, %d match the oracle" % (n_solves, len(checks)))
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("K,seed", [(4, 0), (8, 12)])
+def test_parametric_full_size(pmf, K, seed):
+    """Every integer breakpoint in 1..2000 of one 500x375 seed instance of
+    the benchmark workload, F there and each pixel's exit lambda."""
+    import torch
+    inst = W.config2(K=K)[seed]
+    lo, hi = 1, 2000
+    dev = pmf.to_device([inst])[0]
+    s = pmf.Solver()
+    say("parametric full size K=%d seed %d range %d..%d" % (K, seed, lo, hi))
+    bp, f, ex = pmf.pmf_parametric(s.handle, dev, lo, hi)
+    torch.cuda.synchronize()
+    ex = ex.cpu().numpy()
+    s.close()
+    bp = [int(b) for b in bp]
+    say("%d change points; oracle on both sides of each" % len(bp))
+    assert bp == sorted(set(bp)) and all(lo < b <= hi for b in bp)
+    lams = sorted({lo, hi} | {b for b in bp} | {b - 1 for b in bp})
+    sols = dict(zip(lams, O.solve_many([(inst, lam) for lam in lams], threads=host_threads())))
+    mask = {lam: np.asarray(m, dtype=bool).reshape(inst.H, inst.W) for lam, (_, m) in sols.items()}
+    assert int(f[0]) == sols[lo][0]
+    for b, fb in zip(bp, f[1:]):
+        assert int(fb) == sols[b][0], ("F", b)
+        assert (mask[b] != mask[b - 1]).any(), ("not a change point", b)
+    # no change inside a gap: equal sets at both of its ends
+    starts, ends = [lo] + bp, [b - 1 for b in bp] + [hi]
+    for a, z in zip(starts, ends):
+        assert (mask[a] == mask[z]).all(), ("change inside", a, z)
+    exp = np.full((inst.H, inst.W), hi + 1, dtype=np.int64)
+    for lam in reversed([lo] + bp):
+        exp[~mask[lam]] = lam
+    assert (ex == exp).all(), int((ex != exp).sum())
 
 
 @pytest.mark.parametrize("orientation", [0, 3])
