@@ -28,6 +28,13 @@
  *   seed[p] == 2 (background): cs = 0,   ct = INF
  *   seed[p] == 0 (free):       cs = cap_src[p], ct = cap_snk0[p] + slope[p]*lambda
  * with INF = 2^30.  nlink[k*n + p] is the capacity of the arc p -> p + d_k.
+ *
+ * A rational parameter value lambda = num / den (den >= 1) is solved on the
+ * network with every capacity multiplied by den (INF included): there the
+ * sink capacity of a free pixel is cap_snk0*den + slope*num, an integer.
+ * Scaling all capacities by den scales every cut by den, so the minimum cuts
+ * are the same sets and the flow value is den * F(num / den)
+ * (oracle_fifo_pr_rational).
  */
 #include <stdint.h>
 #include <stdlib.h>
@@ -42,19 +49,20 @@ typedef struct {
     int W, H, K;
     const int32_t *nlink, *cap_src, *cap_snk0, *slope;
     const uint8_t *seed;
+    int64_t den; /* every capacity is multiplied by den; lambda is then the numerator */
 } orc_grid;
 
 static void terminal_caps(const orc_grid *g, int64_t lambda, int p, int64_t *cs, int64_t *ct) {
     uint8_t s = g->seed[p];
     if (s == 1) {
-        *cs = ORC_INF;
+        *cs = ORC_INF * g->den;
         *ct = 0;
     } else if (s == 2) {
         *cs = 0;
-        *ct = ORC_INF;
+        *ct = ORC_INF * g->den;
     } else {
-        *cs = g->cap_src[p];
-        *ct = (int64_t)g->cap_snk0[p] + (int64_t)g->slope[p] * lambda;
+        *cs = (int64_t)g->cap_src[p] * g->den;
+        *ct = (int64_t)g->cap_snk0[p] * g->den + (int64_t)g->slope[p] * lambda;
     }
 }
 
@@ -126,8 +134,8 @@ static int graph_build(const orc_grid *g, int64_t lambda, orc_graph *G) {
             int q = neighbour(g, p, k);
             if (q < 0) continue;
             /* opposite of direction k is k^1 */
-            ADD_PAIR(p, q, (int64_t)g->nlink[(size_t)k * n + p],
-                     (int64_t)g->nlink[(size_t)(k ^ 1) * n + q]);
+            ADD_PAIR(p, q, (int64_t)g->nlink[(size_t)k * n + p] * g->den,
+                     (int64_t)g->nlink[(size_t)(k ^ 1) * n + q] * g->den);
         }
         int64_t cs, ct;
         terminal_caps(g, lambda, p, &cs, &ct);
@@ -193,10 +201,28 @@ static int csr_source_side(const orc_graph *G, int s, int t, int n, uint8_t *mas
  * Returns 0 on success, -1 out of memory, -2 internal check failed (the final
  * state is not a flow, or t is still reachable from s).
  */
+static int fifo_pr(const orc_grid *gp, int64_t lambda, int64_t *flow_out, uint8_t *mask_out, int64_t *stats);
+
 int oracle_fifo_pr(int W, int H, int K, const int32_t *nlink, const int32_t *cap_src,
                    const int32_t *cap_snk0, const int32_t *slope, const uint8_t *seed,
                    int64_t lambda, int64_t *flow_out, uint8_t *mask_out, int64_t *stats) {
-    orc_grid g = {W, H, K, nlink, cap_src, cap_snk0, slope, seed};
+    orc_grid g = {W, H, K, nlink, cap_src, cap_snk0, slope, seed, 1};
+    return fifo_pr(&g, lambda, flow_out, mask_out, stats);
+}
+
+/* lambda = num / den: *flow_out = den * F(num / den); the mask is S_min there.
+ * Returns -3 for den < 1. */
+int oracle_fifo_pr_rational(int W, int H, int K, const int32_t *nlink, const int32_t *cap_src,
+                            const int32_t *cap_snk0, const int32_t *slope, const uint8_t *seed,
+                            int64_t num, int64_t den, int64_t *flow_out, uint8_t *mask_out, int64_t *stats) {
+    if (den < 1) return -3;
+    orc_grid g = {W, H, K, nlink, cap_src, cap_snk0, slope, seed, den};
+    return fifo_pr(&g, num, flow_out, mask_out, stats);
+}
+
+static int fifo_pr(const orc_grid *gp, int64_t lambda, int64_t *flow_out, uint8_t *mask_out, int64_t *stats) {
+    const orc_grid g = *gp;
+    const int W = g.W, H = g.H;
     orc_graph G;
     memset(&G, 0, sizeof(G));
     if (graph_build(&g, lambda, &G)) {
@@ -307,7 +333,7 @@ done:
 int oracle_ek(int W, int H, int K, const int32_t *nlink, const int32_t *cap_src,
               const int32_t *cap_snk0, const int32_t *slope, const uint8_t *seed,
               int64_t lambda, int64_t *flow_out, uint8_t *mask_out, int64_t *stats) {
-    orc_grid g = {W, H, K, nlink, cap_src, cap_snk0, slope, seed};
+    orc_grid g = {W, H, K, nlink, cap_src, cap_snk0, slope, seed, 1};
     int n = W * H;
     /* residual of p->p+d_k, of s->p, of p->s, of p->t (t->p is never useful
      * for an s-t path: t is the target and is never left) */
@@ -421,7 +447,7 @@ done:
 int64_t oracle_cut_cost(int W, int H, int K, const int32_t *nlink, const int32_t *cap_src,
                         const int32_t *cap_snk0, const int32_t *slope, const uint8_t *seed,
                         int64_t lambda, const uint8_t *mask) {
-    orc_grid g = {W, H, K, nlink, cap_src, cap_snk0, slope, seed};
+    orc_grid g = {W, H, K, nlink, cap_src, cap_snk0, slope, seed, 1};
     int n = W * H;
     int64_t cost = 0;
     for (int p = 0; p < n; ++p) {

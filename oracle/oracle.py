@@ -19,6 +19,7 @@ Definitions followed (paper Sec. 2 and 2.1):
 Functions:
 
 * :func:`fifo_pr`      -- FIFO push-relabel with exact BFS relabelling (C).
+* :func:`fifo_pr_rational` -- the same at a rational lambda (capacities scaled by its denominator).
 * :func:`ek`           -- Edmonds-Karp shortest augmenting paths (C).
 * :func:`cut_cost`     -- cost of a given cut from the original capacities (numpy).
 * :func:`brute_force`  -- enumeration of every source set, grids of <= 16 pixels.
@@ -69,6 +70,9 @@ def _load():
                 fn.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, P, P, P, P, P,
                                ctypes.c_int64, P, P, P]
                 fn.restype = ctypes.c_int
+            lib.oracle_fifo_pr_rational.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, P, P, P, P, P,
+                                                    ctypes.c_int64, ctypes.c_int64, P, P, P]
+            lib.oracle_fifo_pr_rational.restype = ctypes.c_int
             lib.oracle_cut_cost.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, P, P, P,
                                             P, P, ctypes.c_int64, P]
             lib.oracle_cut_cost.restype = ctypes.c_int64
@@ -104,6 +108,23 @@ def fifo_pr(inst, lam: int) -> Tuple[int, np.ndarray]:
     """Max-flow value and minimal source side by FIFO push-relabel (int64)."""
     f, m, _ = _call("oracle_fifo_pr", inst, lam)
     return f, m
+
+
+def fifo_pr_rational(inst, num: int, den: int) -> Tuple[int, np.ndarray]:
+    """At lambda = num / den: (den * F(num / den), S_min), by FIFO push-relabel
+    on the network with every capacity multiplied by den (INF included), whose
+    minimum cuts are the same sets."""
+    lib = _load()
+    W, H, K, nl, cs, c0, sl, sd = _arrays(inst)
+    mask = np.zeros((H, W), dtype=np.uint8)
+    flow = ctypes.c_int64(0)
+    stats = np.zeros(4, dtype=np.int64)
+    rc = lib.oracle_fifo_pr_rational(W, H, K, nl.ctypes.data, cs.ctypes.data, c0.ctypes.data, sl.ctypes.data,
+                                     sd.ctypes.data, int(num), int(den), ctypes.addressof(flow), mask.ctypes.data,
+                                     stats.ctypes.data)
+    if rc != 0:
+        raise RuntimeError("oracle_fifo_pr_rational failed with code %d" % rc)
+    return int(flow.value), mask.astype(bool)
 
 
 def ek(inst, lam: int) -> Tuple[int, np.ndarray]:

@@ -327,3 +327,69 @@ def test_int32_headroom_brute_force():
                 f, m = fn(inst, lam)
                 assert f == F and (m == S).all(), (i, fn.__name__, lam)
     assert biggest >= (1 << 31) - 8  # some optimal cuts cost about INF + K * PMF_NLINK_MAX(K)
+
+
+def _envelope_enumeration(inst):
+    """Every source set of a grid of at most 12 pixels as a line in lambda:
+    cost(S, lambda) = A_S + w_S * lambda (Sec. 2.1, monotone case), written
+    out from the cut definition with Python integers.  Returns the sets
+    (bool [2^n, n]) and A, w (object arrays of ints)."""
+    Wd, Hd, K = inst.W, inst.H, inst.K
+    n = Wd * Hd
+    assert n <= 12
+    nl = np.asarray(inst.nlink).reshape(K, Hd, Wd)
+    cs = np.asarray(inst.cap_src).reshape(-1)
+    c0 = np.asarray(inst.cap_snk0).reshape(-1)
+    sl = np.asarray(inst.snk_slope).reshape(-1)
+    sd = np.asarray(inst.seed).reshape(-1)
+    sets = ((np.arange(1 << n)[:, None] >> np.arange(n)[None, :]) & 1).astype(bool)
+    A, w = [], []
+    for T in sets:
+        a = b = 0
+        for p in range(n):
+            if sd[p] == 1:
+                a += 0 if T[p] else O.INF
+            elif sd[p] == 2:
+                a += O.INF if T[p] else 0
+            elif T[p]:
+                a += int(c0[p])
+                b += int(sl[p])
+            else:
+                a += int(cs[p])
+        for k in range(K):
+            for y in range(Hd):
+                for x in range(Wd):
+                    qx, qy = x + O._DX[k], y + O._DY[k]
+                    if 0 <= qx < Wd and 0 <= qy < Hd and T[y * Wd + x] and not T[qy * Wd + qx]:
+                        a += int(nl[k, y, x])
+        A.append(a)
+        w.append(b)
+    return sets, A, w
+
+
+def test_rational_lambda_brute_force():
+    """At rational lambda = num/den the scaled solve gives den * F and S_min
+    exactly as the enumeration of every source set in exact rational
+    arithmetic; den = 1 is the integer solve."""
+    from fractions import Fraction
+    rng = np.random.default_rng(515)
+    checked = 0
+    for i, inst in enumerate(_random_tiny(33, 60)):
+        if inst.W * inst.H > 12:
+            continue
+        sets, A, w = _envelope_enumeration(inst)
+        for _ in range(4):
+            den = int(rng.integers(1, 8))
+            num = int(rng.integers(0, 30 * den))
+            lam = Fraction(num, den)
+            cost = [a + b * lam for a, b in zip(A, w)]
+            F = min(cost)
+            smin = np.logical_and.reduce(sets[[c == F for c in cost]], axis=0)
+            f, m = O.fifo_pr_rational(inst, num, den)
+            assert f == F * den, (i, num, den)
+            assert (m.reshape(-1) == smin).all(), (i, num, den)
+            if den == 1:
+                f1, m1 = O.fifo_pr(inst, num)
+                assert f1 == f and (m1 == m).all()
+            checked += 1
+    assert checked >= 150
