@@ -350,6 +350,42 @@ int pmf_slot_stats(pmf_handle *h, int64_t *out, int32_t max_slots, int32_t *n_sl
 int pmf_parametric(pmf_handle *h, const pmf_instance *inst, int32_t lam_lo, int32_t lam_hi, int32_t *bp_out,
                    int64_t *f_out, int32_t max_bp, int32_t *n_bp, int32_t *exit_out);
 
+/* Every real breakpoint of one instance over [lam_lo, lam_hi] (paper
+ * Sec. 2.1: F is the lower envelope of the lines c(S) + w(S) * lambda of the
+ * source sets S, concave and piecewise linear, and the minimal source sets are
+ * nested as lambda grows), exactly, as fractions: the lambdas x in
+ * (lam_lo, lam_hi] at which S_min changes, i.e. the kinks of F.  The integer
+ * search of pmf_parametric first finds each unit interval (c - 1, c] that
+ * holds a change; the problem is then contracted to the pixels that change
+ * inside it (those of S_min(c) joined to the source, those outside
+ * S_min(c - 1) to the sink, as in the parametric algorithm of Gallo,
+ * Grigoriadis and Tarjan), and each pair of known lines is probed where they
+ * meet, x = p / q, by solving the contracted problem with every capacity
+ * multiplied by q at lambda = p: F(x) on both lines confirms a breakpoint,
+ * otherwise S_min(x) gives a new line between them.  All probes of a round are
+ * solved in one batched call on this handle.  inst->lambdas and inst->L are
+ * ignored; the other fields are as for pmf_solve_batch (device pointers).
+ * Blocking.
+ *   bp_num, bp_den  host, max_bp entries each: breakpoint j is
+ *            bp_num[j] / bp_den[j] (lowest terms), increasing
+ *   piece_a, piece_w  host, max_bp + 1 entries each: on piece j (from
+ *            breakpoint j - 1, or lam_lo, to breakpoint j, or lam_hi),
+ *            F(lambda) = piece_a[j] + piece_w[j] * lambda; piece_w[j] is the
+ *            sink-slope sum of the free pixels of that piece's minimal set
+ *   n_bp     the number of breakpoints (even when larger than max_bp)
+ *   exit_out device, W*H int32, required: per pixel (row-major) the index
+ *            of the first piece whose minimal set lacks it (0 if never in
+ *            S_min, n_bp + 1 if it never leaves); also the working map of
+ *            the search, so undefined after an error
+ * Returns PMF_OK, PMF_ERANGE when more than max_bp breakpoints exist (the
+ * first max_bp are written) or when a probe's scaled capacities would leave
+ * the solver's int32 limits (q * capacity above PMF_INF or PMF_NLINK_MAX(K)),
+ * an instance status (PMF_EINVAL, PMF_EOVERFLOW, PMF_ETIMEOUT) or PMF_ENOMEM
+ * / PMF_EDEVICE.  Replaces the handle's last solve. */
+int pmf_breakpoints(pmf_handle *h, const pmf_instance *inst, int32_t lam_lo, int32_t lam_hi, int64_t *bp_num,
+                    int64_t *bp_den, int64_t *piece_a, int64_t *piece_w, int32_t max_bp, int32_t *n_bp,
+                    int32_t *exit_out);
+
 /* Counters of the last solve. */
 int pmf_get_stats(pmf_handle *h, pmf_stats *out);
 

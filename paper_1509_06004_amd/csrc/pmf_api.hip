@@ -20,6 +20,7 @@
 
 #include "pmf.h"
 #include "pmf_internal.h"
+#include "pmf_contract.h"
 
 using namespace pmf;
 
@@ -1069,6 +1070,183 @@ int solve_batch(pmf_handle *h, const pmf_instance *inst, int32_t n_inst, int64_t
 
 }  // namespace
 
+namespace {
+
+// One solved lambda of a breakpoint search: its flow, |S_min| and slope sum
+// w(S_min) (the derivative of F on the piece where S_min is optimal).
+struct BpPoint {
+    int64_t F = 0, size = 0, w = 0;
+};
+
+// Every integer change point c in (lam_lo, lam_hi] of `base` (one instance,
+// schedule unused), in increasing order, with every solved lambda in pts;
+// exit_out (device, may be null) receives each pixel's first lambda outside
+// S_min (lam_lo if never in it, lam_hi + 1 if it never leaves).  Leaves the
+// arena tail in use: the caller releases it.
+int integer_breakpoints(pmf_handle *h, const pmf_instance &base, int32_t lam_lo, int32_t lam_hi,
+                        std::map<int32_t, BpPoint> &pts, std::vector<int32_t> &changes, int32_t *exit_out) {
+    const int n = base.W * base.H;
+    // the exit map is a running minimum over the solved lambdas: the smallest
+    // solved lambda whose set lacks the pixel (every change point is solved,
+    // and the set is constant between change points, so it is exact)
+    if (exit_out && launch_fill_i32(exit_out, n, lam_hi + 1, h->stream) != 0) return PMF_EDEVICE;
+    // Probes per round: the batched call solves them side by side, so a round
+    // costs about as much as its slowest chunk until the device fills, and
+    // fewer, wider rounds win.  The budget shrinks for large images so that
+    // the round's state stays within 1 GiB.
+    int budget = 64;
+    for (pmf_instance I = base; budget > 2; budget /= 2) {
+        I.L = budget;
+        int64_t subs = 0;
+        if (batch_pool_bytes(&I, 1, 1, h->tw, h->th, h->opt.gap != 0, &subs) <= ((size_t)1 << 30)) break;
+    }
+    // Solve the (ascending, distinct) lambdas of `lams` as the schedule of one
+    // instance: the batched call splits it into warm-started chunks solved in
+    // parallel.  The round's own device data (lambdas, flows, status, mask
+    // statistics) sit at the end of the handle's arena, which is first grown to
+    // hold them next to the largest layout the call can pick (every lambda a
+    // chunk of its own), so that the call never moves it.  The masks are read
+    // where the solve left them.
+    auto solve = [&](const std::vector<int32_t> &lams) -> int {
+        const int m = (int)lams.size();
+        const size_t o_f = align_up(4 * (size_t)m), o_s = o_f + align_up(8 * (size_t)m), o_st = o_s + align_up(4),
+                     T = o_st + align_up(16 * (size_t)m);
+        pmf_instance I = base;
+        I.L = m;
+        int64_t subs = 0;
+        const size_t pool1 = batch_pool_bytes(&I, 1, 1, h->tw, h->th, h->opt.gap != 0, &subs);
+        const size_t need = control_bytes((int)subs, worklist_cap((int)subs, pool1)) + pool1;
+        h->reserve_tail = 0;
+        int rc = ensure_arena(h, need + T);
+        if (rc != PMF_OK) return rc;
+        h->reserve_tail = T;
+        char *tail = h->arena + h->arena_bytes - T;
+        int32_t *dl = (int32_t *)tail;
+        int64_t *df = (int64_t *)(tail + o_f);
+        int32_t *ds = (int32_t *)(tail + o_s);
+        int64_t *dst = (int64_t *)(tail + o_st);
+        if (hipMemcpyAsync(dl, lams.data(), 4 * (size_t)m, hipMemcpyHostToDevice, h->stream) != hipSuccess ||
+            hipMemsetAsync(dst, 0, 16 * (size_t)m, h->stream) != hipSuccess)
+            return PMF_EDEVICE;
+        I.lambdas = dl;
+        rc = pmf_solve_batch(h, &I, 1, df, ds);
+        if (rc != PMF_OK) return rc;
+        int32_t st = PMF_OK;
+        if (hipMemcpy(&st, ds, 4, hipMemcpyDeviceToHost) != hipSuccess) return PMF_EDEVICE;
+        if (st != PMF_OK) return st;
+        for (int i = 0; i < m; ++i) {
+            int slot, k;
+            rc = locate(h, 0, i, &slot, &k);
+            if (rc != PMF_OK) return rc;
+            const uint8_t *mask = (const uint8_t *)(h->base + h->slots[slot].masks + (size_t)k * n);
+            if (launch_mask_stats(mask, n, base.snk_slope, base.seed, dst + 2 * i, h->stream) != 0) return PMF_EDEVICE;
+            if (exit_out && launch_exit_min(mask, n, lams[i], exit_out, h->stream) != 0) return PMF_EDEVICE;
+        }
+        std::vector<int64_t> f(m), sw(2 * (size_t)m);
+        if (hipMemcpyAsync(f.data(), df, 8 * (size_t)m, hipMemcpyDeviceToHost, h->stream) != hipSuccess ||
+            hipMemcpyAsync(sw.data(), dst, 16 * (size_t)m, hipMemcpyDeviceToHost, h->stream) != hipSuccess ||
+            hipStreamSynchronize(h->stream) != hipSuccess)
+            return PMF_EDEVICE;
+        for (int i = 0; i < m; ++i) {
+            BpPoint &q = pts[lams[i]];
+            q.F = f[i];
+            q.size = sw[2 * i];
+            q.w = sw[2 * i + 1];
+        }
+        return PMF_OK;
+    };
+    // Up to k probes strictly inside (a, b), an interval whose end sets differ
+    // (nested sets are equal exactly when their sizes are), into `out`.  When k
+    // covers every integer inside, all of them.  Otherwise first the two
+    // integers around the meeting point x of the end pieces of F,
+    // F(a) + w_a (l - a) and F(b) + w_b (l - b): a single change point c in
+    // (a, b] satisfies c - 1 < x <= c, so ceil(x) - 1 and ceil(x) isolate it
+    // (the midpoint instead when w_a = w_b, which free pixels of slope 0
+    // allow).  The rest are spread over (a, b), geometrically when a > 0, for
+    // intervals that hold several change points.
+    auto probes = [&](int32_t a, int32_t b, int k, std::vector<int32_t> &out) {
+        if ((int64_t)b - a - 1 <= k) {
+            for (int32_t x = a + 1; x < b; ++x) out.push_back(x);
+            return;
+        }
+        std::vector<int32_t> mine;
+        auto add = [&](int64_t x) {
+            x = std::min<int64_t>(std::max<int64_t>(x, (int64_t)a + 1), (int64_t)b - 1);
+            if (std::find(mine.begin(), mine.end(), (int32_t)x) == mine.end()) mine.push_back((int32_t)x);
+        };
+        const BpPoint &pa = pts[a], &pb = pts[b];
+        if (pa.w > pb.w) {
+            const long double x = ((long double)pb.F - pa.F + (long double)pa.w * a - (long double)pb.w * b) /
+                                  (long double)(pa.w - pb.w);
+            const int64_t c = (int64_t)std::ceil(x);
+            add(c);
+            add(c - 1);
+        } else {
+            add((int64_t)a + (b - a) / 2);
+        }
+        const int rest = k - (int)mine.size();
+        for (int j = 1; j <= rest; ++j) {
+            const double t = (double)j / (rest + 1);
+            add(a > 0 ? (int64_t)std::llround(a * std::pow((double)b / a, t)) : (int64_t)a + (int64_t)((b - a) * t));
+        }
+        out.insert(out.end(), mine.begin(), mine.end());
+    };
+    std::vector<int32_t> ends = {lam_lo};
+    if (lam_hi > lam_lo) ends.push_back(lam_hi);
+    int rc = solve(ends);
+    if (rc != PMF_OK) return rc;
+    // Open intervals: consecutive solved lambdas whose sets differ.  One of
+    // length 1 is a change point; the others share the round's probe budget.
+    std::vector<std::pair<int32_t, int32_t>> open;
+    if (lam_hi > lam_lo && pts[lam_lo].size != pts[lam_hi].size) open.push_back({lam_lo, lam_hi});
+    changes.clear();
+    while (!open.empty()) {
+        std::vector<std::pair<int32_t, int32_t>> live;
+        for (const auto &iv : open) {
+            if (iv.second - iv.first == 1)
+                changes.push_back(iv.second);
+            else
+                live.push_back(iv);
+        }
+        open.clear();
+        if (live.empty()) break;
+        const int k = std::max(2, budget / (int)live.size());
+        std::vector<int32_t> mids;
+        for (const auto &iv : live) probes(iv.first, iv.second, k, mids);
+        std::sort(mids.begin(), mids.end());
+        mids.erase(std::unique(mids.begin(), mids.end()), mids.end());
+        rc = solve(mids);
+        if (rc != PMF_OK) return rc;
+        for (const auto &iv : live) {
+            // the solved lambdas inside (a, b) cut it into pieces
+            auto it = pts.upper_bound(iv.first);
+            int32_t prev = iv.first;
+            for (; it != pts.end() && it->first <= iv.second; ++it) {
+                if (pts[prev].size != it->second.size) open.push_back({prev, it->first});
+                prev = it->first;
+            }
+        }
+    }
+    std::sort(changes.begin(), changes.end());
+    changes.erase(std::unique(changes.begin(), changes.end()), changes.end());
+    return PMF_OK;
+}
+
+// The instance of a breakpoint search: one lambda, its schedule supplied by
+// the search (only the pointer's presence is checked here).
+int breakpoint_base(const pmf_instance *inst, int32_t lam_lo, int32_t lam_hi, pmf_instance *base) {
+    if (!inst || lam_lo < 0 || lam_hi < lam_lo) return PMF_EINVAL;
+    if (lam_hi == INT32_MAX) return PMF_EINVAL;  // lam_hi + 1 marks pixels that never leave
+    *base = *inst;
+    base->L = 1;
+    base->lambdas = nullptr;
+    pmf_instance chk = *base;
+    chk.lambdas = &lam_lo;
+    return check_instance(chk) != PMF_OK ? PMF_EINVAL : PMF_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 int pmf_solve_batch(pmf_handle *h, const pmf_instance *inst, int32_t n_inst, int64_t *flows_out,
@@ -1292,186 +1470,338 @@ int64_t pmf_get_trace(pmf_handle *h, int64_t *out, int64_t max_rows) {
 
 int pmf_parametric(pmf_handle *h, const pmf_instance *inst, int32_t lam_lo, int32_t lam_hi, int32_t *bp_out,
                    int64_t *f_out, int32_t max_bp, int32_t *n_bp, int32_t *exit_out) {
-    if (!h || !inst || !n_bp || max_bp < 0 || (max_bp > 0 && !bp_out) || lam_lo < 0 || lam_hi < lam_lo)
-        return PMF_EINVAL;
+    if (!h || !inst || !n_bp || max_bp < 0 || (max_bp > 0 && !bp_out)) return PMF_EINVAL;
+    pmf_instance base;
+    if (breakpoint_base(inst, lam_lo, lam_hi, &base) != PMF_OK) return PMF_EINVAL;
     (void)finish_async(h);
-    if (lam_hi == INT32_MAX) return PMF_EINVAL;  // lam_hi + 1 marks pixels that never leave
     *n_bp = 0;
-    pmf_instance base = *inst;
-    base.L = 1;
-    base.lambdas = nullptr;
-    {
-        pmf_instance chk = base;  // the schedule is made here: only its pointer's presence is checked
-        chk.lambdas = &lam_lo;
-        if (check_instance(chk) != PMF_OK) return PMF_EINVAL;
-    }
-    const int n = base.W * base.H;
-    // every solved lambda: its flow, |S_min| and slope sum w(S_min)
-    struct Point {
-        int64_t F = 0, size = 0, w = 0;
-    };
-    std::map<int32_t, Point> pts;
-    // the exit map is a running minimum over the solved lambdas: the smallest
-    // solved lambda whose set lacks the pixel (every change point is solved,
-    // and the set is constant between change points, so it is exact)
-    if (exit_out && launch_fill_i32(exit_out, n, lam_hi + 1, h->stream) != 0) return PMF_EDEVICE;
-    auto release = [&]() {
-        (void)hipStreamSynchronize(h->stream);
-        h->reserve_tail = 0;
-    };
-    // Probes per round: the batched call solves them side by side, so a round
-    // costs about as much as its slowest chunk until the device fills, and
-    // fewer, wider rounds win.  The budget shrinks for large images so that
-    // the round's state stays within 1 GiB.
-    int budget = 64;
-    for (pmf_instance I = base; budget > 2; budget /= 2) {
-        I.L = budget;
-        int64_t subs = 0;
-        if (batch_pool_bytes(&I, 1, 1, h->tw, h->th, h->opt.gap != 0, &subs) <= ((size_t)1 << 30)) break;
-    }
-    // Solve the (ascending, distinct) lambdas of `lams` as the schedule of one
-    // instance: the batched call splits it into warm-started chunks solved in
-    // parallel.  The round's own device data (lambdas, flows, status, mask
-    // statistics) sit at the end of the handle's arena, which is first grown to
-    // hold them next to the largest layout the call can pick (every lambda a
-    // chunk of its own), so that the call never moves it.  The masks are read
-    // where the solve left them.
-    auto solve = [&](const std::vector<int32_t> &lams) -> int {
-        const int m = (int)lams.size();
-        const size_t o_f = align_up(4 * (size_t)m), o_s = o_f + align_up(8 * (size_t)m), o_st = o_s + align_up(4),
-                     T = o_st + align_up(16 * (size_t)m);
-        pmf_instance I = base;
-        I.L = m;
-        int64_t subs = 0;
-        const size_t pool1 = batch_pool_bytes(&I, 1, 1, h->tw, h->th, h->opt.gap != 0, &subs);
-        const size_t need = control_bytes((int)subs, worklist_cap((int)subs, pool1)) + pool1;
-        h->reserve_tail = 0;
-        int rc = ensure_arena(h, need + T);
-        if (rc != PMF_OK) return rc;
-        h->reserve_tail = T;
-        char *tail = h->arena + h->arena_bytes - T;
-        int32_t *dl = (int32_t *)tail;
-        int64_t *df = (int64_t *)(tail + o_f);
-        int32_t *ds = (int32_t *)(tail + o_s);
-        int64_t *dst = (int64_t *)(tail + o_st);
-        if (hipMemcpyAsync(dl, lams.data(), 4 * (size_t)m, hipMemcpyHostToDevice, h->stream) != hipSuccess ||
-            hipMemsetAsync(dst, 0, 16 * (size_t)m, h->stream) != hipSuccess)
-            return PMF_EDEVICE;
-        I.lambdas = dl;
-        rc = pmf_solve_batch(h, &I, 1, df, ds);
-        if (rc != PMF_OK) return rc;
-        int32_t st = PMF_OK;
-        if (hipMemcpy(&st, ds, 4, hipMemcpyDeviceToHost) != hipSuccess) return PMF_EDEVICE;
-        if (st != PMF_OK) return st;
-        for (int i = 0; i < m; ++i) {
-            int slot, k;
-            rc = locate(h, 0, i, &slot, &k);
-            if (rc != PMF_OK) return rc;
-            const uint8_t *mask = (const uint8_t *)(h->base + h->slots[slot].masks + (size_t)k * n);
-            if (launch_mask_stats(mask, n, base.snk_slope, base.seed, dst + 2 * i, h->stream) != 0) return PMF_EDEVICE;
-            if (exit_out && launch_exit_min(mask, n, lams[i], exit_out, h->stream) != 0) return PMF_EDEVICE;
-        }
-        std::vector<int64_t> f(m), sw(2 * (size_t)m);
-        if (hipMemcpyAsync(f.data(), df, 8 * (size_t)m, hipMemcpyDeviceToHost, h->stream) != hipSuccess ||
-            hipMemcpyAsync(sw.data(), dst, 16 * (size_t)m, hipMemcpyDeviceToHost, h->stream) != hipSuccess ||
-            hipStreamSynchronize(h->stream) != hipSuccess)
-            return PMF_EDEVICE;
-        for (int i = 0; i < m; ++i) {
-            Point &q = pts[lams[i]];
-            q.F = f[i];
-            q.size = sw[2 * i];
-            q.w = sw[2 * i + 1];
-        }
-        return PMF_OK;
-    };
-    // Up to k probes strictly inside (a, b), an interval whose end sets differ
-    // (nested sets are equal exactly when their sizes are), into `out`.  When k
-    // covers every integer inside, all of them.  Otherwise first the two
-    // integers around the meeting point x of the end pieces of F,
-    // F(a) + w_a (l - a) and F(b) + w_b (l - b): a single change point c in
-    // (a, b] satisfies c - 1 < x <= c, so ceil(x) - 1 and ceil(x) isolate it
-    // (the midpoint instead when w_a = w_b, which free pixels of slope 0
-    // allow).  The rest are spread over (a, b), geometrically when a > 0, for
-    // intervals that hold several change points.
-    auto probes = [&](int32_t a, int32_t b, int k, std::vector<int32_t> &out) {
-        if ((int64_t)b - a - 1 <= k) {
-            for (int32_t x = a + 1; x < b; ++x) out.push_back(x);
-            return;
-        }
-        std::vector<int32_t> mine;
-        auto add = [&](int64_t x) {
-            x = std::min<int64_t>(std::max<int64_t>(x, (int64_t)a + 1), (int64_t)b - 1);
-            if (std::find(mine.begin(), mine.end(), (int32_t)x) == mine.end()) mine.push_back((int32_t)x);
-        };
-        const Point &pa = pts[a], &pb = pts[b];
-        if (pa.w > pb.w) {
-            const long double x = ((long double)pb.F - pa.F + (long double)pa.w * a - (long double)pb.w * b) /
-                                  (long double)(pa.w - pb.w);
-            const int64_t c = (int64_t)std::ceil(x);
-            add(c);
-            add(c - 1);
-        } else {
-            add((int64_t)a + (b - a) / 2);
-        }
-        const int rest = k - (int)mine.size();
-        for (int j = 1; j <= rest; ++j) {
-            const double t = (double)j / (rest + 1);
-            add(a > 0 ? (int64_t)std::llround(a * std::pow((double)b / a, t)) : (int64_t)a + (int64_t)((b - a) * t));
-        }
-        out.insert(out.end(), mine.begin(), mine.end());
-    };
-    std::vector<int32_t> ends = {lam_lo};
-    if (lam_hi > lam_lo) ends.push_back(lam_hi);
-    int rc = solve(ends);
-    if (rc != PMF_OK) {
-        release();
-        return rc;
-    }
-    // Open intervals: consecutive solved lambdas whose sets differ.  One of
-    // length 1 is a change point; the others share the round's probe budget.
-    std::vector<std::pair<int32_t, int32_t>> open;
-    if (lam_hi > lam_lo && pts[lam_lo].size != pts[lam_hi].size) open.push_back({lam_lo, lam_hi});
+    std::map<int32_t, BpPoint> pts;
     std::vector<int32_t> changes;
-    while (!open.empty()) {
-        std::vector<std::pair<int32_t, int32_t>> live;
-        for (const auto &iv : open) {
-            if (iv.second - iv.first == 1)
-                changes.push_back(iv.second);
-            else
-                live.push_back(iv);
-        }
-        open.clear();
-        if (live.empty()) break;
-        const int k = std::max(2, budget / (int)live.size());
-        std::vector<int32_t> mids;
-        for (const auto &iv : live) probes(iv.first, iv.second, k, mids);
-        std::sort(mids.begin(), mids.end());
-        mids.erase(std::unique(mids.begin(), mids.end()), mids.end());
-        rc = solve(mids);
-        if (rc != PMF_OK) {
-            release();
-            return rc;
-        }
-        for (const auto &iv : live) {
-            // the solved lambdas inside (a, b) cut it into pieces
-            auto it = pts.upper_bound(iv.first);
-            int32_t prev = iv.first;
-            for (; it != pts.end() && it->first <= iv.second; ++it) {
-                if (pts[prev].size != it->second.size) open.push_back({prev, it->first});
-                prev = it->first;
-            }
-        }
-    }
-    std::sort(changes.begin(), changes.end());
-    changes.erase(std::unique(changes.begin(), changes.end()), changes.end());
+    const int rc = integer_breakpoints(h, base, lam_lo, lam_hi, pts, changes, exit_out);
+    (void)hipStreamSynchronize(h->stream);
+    h->reserve_tail = 0;
+    if (rc != PMF_OK) return rc;
     *n_bp = (int32_t)changes.size();
     for (int i = 0; i < (int)changes.size() && i < max_bp; ++i) bp_out[i] = changes[i];
     if (f_out) {
         f_out[0] = pts[lam_lo].F;
         for (int i = 0; i < (int)changes.size() && i < max_bp; ++i) f_out[i + 1] = pts[changes[i]].F;
     }
-    release();
     return (int)changes.size() > max_bp ? PMF_ERANGE : PMF_OK;
+}
+
+int pmf_breakpoints(pmf_handle *h, const pmf_instance *inst, int32_t lam_lo, int32_t lam_hi, int64_t *bp_num,
+                    int64_t *bp_den, int64_t *piece_a, int64_t *piece_w, int32_t max_bp, int32_t *n_bp,
+                    int32_t *exit_out) {
+    if (!h || !inst || !n_bp || !exit_out || !piece_a || !piece_w || max_bp < 0 ||
+        (max_bp > 0 && (!bp_num || !bp_den)))
+        return PMF_EINVAL;
+    pmf_instance base;
+    if (breakpoint_base(inst, lam_lo, lam_hi, &base) != PMF_OK) return PMF_EINVAL;
+    (void)finish_async(h);
+    *n_bp = 0;
+    auto release = [&](int code) {
+        (void)hipStreamSynchronize(h->stream);
+        h->reserve_tail = 0;
+        return code;
+    };
+    // 1. every integer change point c (S_min(c - 1) != S_min(c)), with the
+    // integer exit map in exit_out: S_min(l) = {p : exit[p] > l} for every
+    // integer l of the range
+    std::map<int32_t, BpPoint> pts;
+    std::vector<int32_t> changes;
+    int rc = integer_breakpoints(h, base, lam_lo, lam_hi, pts, changes, exit_out);
+    if (rc != PMF_OK) return release(rc);
+    (void)hipStreamSynchronize(h->stream);
+    h->reserve_tail = 0;
+    struct Line {  // cut cost a + w * lambda of one source set
+        int64_t a, w;
+    };
+    auto line_at = [&](int32_t lam, Line *out) {
+        const auto it = pts.find(lam);
+        if (it == pts.end()) return false;
+        *out = Line{it->second.F - it->second.w * (int64_t)lam, it->second.w};
+        return true;
+    };
+    const int W = base.W, H = base.H, K = base.K, n = W * H, k = (int)changes.size();
+    Line first;
+    if (!line_at(lam_lo, &first)) return release(PMF_EDEVICE);
+    piece_a[0] = first.a;
+    piece_w[0] = first.w;
+    if (k == 0) {
+        if (launch_exit_pieces_init(exit_out, n, lam_lo, lam_hi, 1, h->stream) != 0) return release(PMF_EDEVICE);
+        return release(PMF_OK);
+    }
+    // 2. the box of D_c = S_min(c - 1) \ S_min(c) = {p : exit[p] == c}
+    std::vector<int32_t> box(4 * (size_t)k);
+    {
+        const size_t o_box = align_up(4 * (size_t)k), T = o_box + align_up(16 * (size_t)k);
+        rc = ensure_arena(h, T);
+        if (rc != PMF_OK) return release(rc);
+        char *tail = h->arena + h->arena_bytes - T;
+        if (hipMemcpyAsync(tail, changes.data(), 4 * (size_t)k, hipMemcpyHostToDevice, h->stream) != hipSuccess ||
+            launch_change_boxes(exit_out, W, H, (const int32_t *)tail, k, (int32_t *)(tail + o_box), h->stream) != 0 ||
+            hipMemcpyAsync(box.data(), tail + o_box, 16 * (size_t)k, hipMemcpyDeviceToHost, h->stream) != hipSuccess ||
+            hipStreamSynchronize(h->stream) != hipSuccess)
+            return release(PMF_EDEVICE);
+    }
+    struct Interval {
+        int32_t c;
+        int x0, y0, w, h;
+        int64_t a;
+        size_t o_planes, o_ep, o_eq, o_stats;
+        int64_t st[kCsCount];
+        Line fix;  // full-problem line = contracted line + fix
+    };
+    std::vector<Interval> iv(k);
+    size_t P = 0;
+    int64_t amax = 0;
+    int wmax = 0, hmax = 0;
+    for (int i = 0; i < k; ++i) {
+        Interval &I = iv[i];
+        I.c = changes[i];
+        I.x0 = box[4 * i];
+        I.y0 = box[4 * i + 1];
+        if (box[4 * i + 2] < I.x0 || box[4 * i + 3] < I.y0) return release(PMF_EDEVICE);  // D is never empty
+        I.w = box[4 * i + 2] - I.x0 + 1;
+        I.h = box[4 * i + 3] - I.y0 + 1;
+        I.a = (int64_t)I.w * I.h;
+        I.o_planes = P;
+        P = align_up(P + 4 * (size_t)(K + 3) * I.a);
+        I.o_ep = P;
+        P = align_up(P + 4 * (size_t)I.a);
+        I.o_eq = P;
+        P = align_up(P + 4 * (size_t)I.a);
+        I.o_stats = P;
+        P = align_up(P + 8 * (size_t)kCsCount);
+        amax = std::max(amax, I.a);
+        wmax = std::max(wmax, I.w);
+        hmax = std::max(hmax, I.h);
+    }
+    // 3. device memory: the contracted problems (kept to the end), then per
+    // round up to R scaled copies with their lambdas, flows, statuses and set
+    // statistics, and the pool of a batch of R probes of the largest box
+    const size_t probe_planes = align_up(4 * (size_t)(K + 2) * amax);
+    auto round_pool = [&](int m) {
+        pmf_instance M = base;
+        M.W = wmax;
+        M.H = hmax;
+        std::vector<pmf_instance> v((size_t)m, M);
+        int64_t subs = 0;
+        const size_t pool = batch_pool_bytes(v.data(), m, 1, h->tw, h->th, h->opt.gap != 0, &subs);
+        return control_bytes((int)subs, worklist_cap((int)subs, pool)) + pool;
+    };
+    auto round_scratch = [&](int m) {
+        return (size_t)m * probe_planes + align_up(4 * (size_t)m) + align_up(8 * (size_t)m) +
+               align_up(4 * (size_t)m) + align_up(16 * (size_t)m);
+    };
+    int R = 64;
+    while (R > 1 && round_pool(R) + round_scratch(R) > ((size_t)1 << 30)) R /= 2;
+    const size_t T = P + round_scratch(R);
+    rc = ensure_arena(h, round_pool(R) + T);
+    if (rc != PMF_OK) return release(rc);
+    h->reserve_tail = T;
+    char *pers = h->arena + h->arena_bytes - T, *scr = pers + P;
+    const size_t o_l = (size_t)R * probe_planes, o_f = o_l + align_up(4 * (size_t)R),
+                 o_s = o_f + align_up(8 * (size_t)R), o_st = o_s + align_up(4 * (size_t)R);
+    int32_t *dl = (int32_t *)(scr + o_l), *ds = (int32_t *)(scr + o_s);
+    int64_t *df = (int64_t *)(scr + o_f), *dst = (int64_t *)(scr + o_st);
+    // 4. contract each interval's problem to its changing pixels
+    for (int i = 0; i < k; ++i) {
+        Interval &I = iv[i];
+        if (launch_contract(base.nlink, base.cap_src, base.cap_snk0, base.snk_slope, base.seed, W, H, K, exit_out,
+                            I.c, I.x0, I.y0, I.w, I.h, (int32_t *)(pers + I.o_planes), (int32_t *)(pers + I.o_ep),
+                            (int32_t *)(pers + I.o_eq), (int64_t *)(pers + I.o_stats), h->stream) != 0 ||
+            hipMemcpyAsync(I.st, pers + I.o_stats, 8 * (size_t)kCsCount, hipMemcpyDeviceToHost, h->stream) !=
+                hipSuccess)
+            return release(PMF_EDEVICE);
+    }
+    if (hipStreamSynchronize(h->stream) != hipSuccess) return release(PMF_EDEVICE);
+    // the two end lines of an interval in the contracted problem: all of D
+    // in the source set (cost sum c0 + lambda * sum slope) and none of it
+    // (cost sum cs); the pixels fixed by the contraction add the same line
+    // to every set, read off the full problem's lines at c - 1 and c
+    struct Pair {
+        int iv;
+        Line L, R;       // L optimal left of the meeting point, R right of it
+        int64_t rp, rq;  // R is optimal at rp / rq
+    };
+    struct Found {
+        int iv;
+        int64_t p, q;
+        Line L, R;
+    };
+    std::vector<Pair> pend;
+    std::vector<Found> found;
+    for (int i = 0; i < k; ++i) {
+        Interval &I = iv[i];
+        if (I.st[kCsSeeds] != 0) return release(PMF_ERANGE);  // capacities at INF: no finite contraction
+        const Line Lc{I.st[kCsSumC0], I.st[kCsSumSl]}, Rc{I.st[kCsSumCs], 0};
+        Line Lf, Rf;
+        if (!line_at(I.c - 1, &Lf) || !line_at(I.c, &Rf)) return release(PMF_EDEVICE);
+        I.fix = Line{Lf.a - Lc.a, Lf.w - Lc.w};
+        if (Rf.a != Rc.a + I.fix.a || Rf.w != Rc.w + I.fix.w) return release(PMF_EDEVICE);
+        pend.push_back(Pair{i, Lc, Rc, I.c, 1});
+    }
+    // 5. rounds: each pending pair (L, R) meets at x = p / q; if F(x) is on
+    // both lines, x is the only breakpoint between them, else the minimal
+    // set at x gives a new line M and the pairs (L, M) and (M, R).  F(x) and
+    // S_min(x) come from the contracted problem with every capacity
+    // multiplied by q, solved at the integer lambda p.
+    struct Probe {
+        Pair pr;
+        int32_t p, q;
+    };
+    int64_t probes_total = 0;
+    while (!pend.empty()) {
+        std::vector<Probe> todo;
+        for (const Pair &pr : pend) {
+            const int64_t num = pr.R.a - pr.L.a, den = pr.L.w - pr.R.w;
+            if (den <= 0 || num <= 0) return release(PMF_EDEVICE);
+            const int64_t g = std::gcd(num, den), p = num / g, q = den / g;
+            const Interval &I = iv[pr.iv];
+            if ((__int128)p <= (__int128)(I.c - 1) * q || (__int128)p > (__int128)I.c * q)
+                return release(PMF_EDEVICE);
+            if ((__int128)p * pr.rq == (__int128)pr.rp * q) {  // at R's own point: F(x) is known
+                found.push_back(Found{pr.iv, p, q, pr.L, pr.R});
+                continue;
+            }
+            const __int128 lim = PMF_INF;
+            if (p > INT32_MAX || q > lim || (__int128)q * I.st[kCsMaxCs] > lim ||
+                (__int128)q * I.st[kCsMaxNl] > PMF_NLINK_MAX(K) ||
+                (__int128)q * I.st[kCsMaxC0] + (__int128)I.st[kCsMaxSl] * p > lim)
+                return release(PMF_ERANGE);
+            todo.push_back(Probe{pr, (int32_t)p, (int32_t)q});
+        }
+        probes_total += (int64_t)todo.size();
+        if (probes_total > ((int64_t)1 << 22)) return release(PMF_ETIMEOUT);
+        std::vector<Pair> next;
+        for (size_t b0 = 0; b0 < todo.size(); b0 += (size_t)R) {
+            const int m = (int)std::min<size_t>((size_t)R, todo.size() - b0);
+            std::vector<pmf_instance> pi((size_t)m);
+            std::vector<int32_t> lam((size_t)m), sts((size_t)m);
+            for (int j = 0; j < m; ++j) {
+                const Probe &pb = todo[b0 + j];
+                const Interval &I = iv[pb.pr.iv];
+                const int32_t *src = (const int32_t *)(pers + I.o_planes);
+                int32_t *dstp = (int32_t *)(scr + (size_t)j * probe_planes);
+                if (launch_scale(src, (int64_t)(K + 2) * I.a, pb.q, dstp, h->stream) != 0)
+                    return release(PMF_EDEVICE);
+                pmf_instance &Q = pi[j];
+                Q = base;
+                Q.W = I.w;
+                Q.H = I.h;
+                Q.L = 1;
+                Q.nlink = dstp;
+                Q.cap_src = dstp + (size_t)K * I.a;
+                Q.cap_snk0 = dstp + (size_t)(K + 1) * I.a;
+                Q.snk_slope = src + (size_t)(K + 2) * I.a;
+                Q.seed = nullptr;
+                Q.lambdas = dl + j;
+                lam[j] = pb.p;
+            }
+            {
+                // the batch must fit in front of the tail: a larger arena
+                // would be a new allocation, and the tail would move
+                int64_t subs = 0;
+                const size_t pool = batch_pool_bytes(pi.data(), m, 1, h->tw, h->th, h->opt.gap != 0, &subs);
+                if (control_bytes((int)subs, worklist_cap((int)subs, pool)) + pool + T > h->arena_bytes)
+                    return release(PMF_ENOMEM);
+            }
+            if (hipMemcpyAsync(dl, lam.data(), 4 * (size_t)m, hipMemcpyHostToDevice, h->stream) != hipSuccess ||
+                hipMemsetAsync(dst, 0, 16 * (size_t)m, h->stream) != hipSuccess)
+                return release(PMF_EDEVICE);
+            rc = pmf_solve_batch(h, pi.data(), m, df, ds);
+            if (rc != PMF_OK) return release(rc);
+            if (hipMemcpy(sts.data(), ds, 4 * (size_t)m, hipMemcpyDeviceToHost) != hipSuccess)
+                return release(PMF_EDEVICE);
+            for (int j = 0; j < m; ++j)
+                if (sts[j] != PMF_OK) return release(sts[j]);
+            for (int j = 0; j < m; ++j) {
+                const Probe &pb = todo[b0 + j];
+                const Interval &I = iv[pb.pr.iv];
+                int slot, kk;
+                rc = locate(h, j, 0, &slot, &kk);
+                if (rc != PMF_OK) return release(rc);
+                const uint8_t *mask = (const uint8_t *)(h->base + h->slots[slot].masks + (size_t)kk * I.a);
+                if (launch_mask_stats(mask, (int)I.a, pi[j].snk_slope, nullptr, dst + 2 * j, h->stream) != 0 ||
+                    launch_exit_rational(mask, (int)I.a, pb.p, pb.q, (int32_t *)(pers + I.o_ep),
+                                         (int32_t *)(pers + I.o_eq), h->stream) != 0)
+                    return release(PMF_EDEVICE);
+            }
+            std::vector<int64_t> f((size_t)m), sw(2 * (size_t)m);
+            if (hipMemcpyAsync(f.data(), df, 8 * (size_t)m, hipMemcpyDeviceToHost, h->stream) != hipSuccess ||
+                hipMemcpyAsync(sw.data(), dst, 16 * (size_t)m, hipMemcpyDeviceToHost, h->stream) != hipSuccess ||
+                hipStreamSynchronize(h->stream) != hipSuccess)
+                return release(PMF_EDEVICE);
+            for (int j = 0; j < m; ++j) {
+                const Probe &pb = todo[b0 + j];
+                const Pair &pr = pb.pr;
+                const __int128 on_l = (__int128)pb.q * pr.L.a + (__int128)pr.L.w * pb.p;
+                if (f[j] == on_l) {
+                    found.push_back(Found{pr.iv, pb.p, pb.q, pr.L, pr.R});
+                } else if (f[j] < on_l) {
+                    const int64_t wm = sw[2 * j + 1];
+                    const __int128 am = (__int128)f[j] - (__int128)wm * pb.p;
+                    if (am % pb.q != 0) return release(PMF_EDEVICE);
+                    const Line M{(int64_t)(am / pb.q), wm};
+                    next.push_back(Pair{pr.iv, pr.L, M, pb.p, pb.q});
+                    next.push_back(Pair{pr.iv, M, pr.R, pr.rp, pr.rq});
+                } else {
+                    return release(PMF_EDEVICE);  // a cut cheaper than the minimum
+                }
+            }
+        }
+        pend.swap(next);
+    }
+    // 6. the breakpoints in increasing order, each piece's line in the full
+    // problem, and every pixel's exit piece
+    std::sort(found.begin(), found.end(), [](const Found &x, const Found &y) {
+        if (x.iv != y.iv) return x.iv < y.iv;
+        return (__int128)x.p * y.q < (__int128)y.p * x.q;
+    });
+    const int nb = (int)found.size();
+    Line cur = first;
+    std::vector<int64_t> table(2 * (size_t)nb);
+    std::vector<int> start(k + 1, 0);
+    for (int j = 0; j < nb; ++j) {
+        const Found &fd = found[j];
+        const Line &fx = iv[fd.iv].fix;
+        const Line Lf{fd.L.a + fx.a, fd.L.w + fx.w}, Rf{fd.R.a + fx.a, fd.R.w + fx.w};
+        if (Lf.a != cur.a || Lf.w != cur.w) return release(PMF_EDEVICE);
+        if (j < max_bp) {
+            bp_num[j] = fd.p;
+            bp_den[j] = fd.q;
+            piece_a[j + 1] = Rf.a;
+            piece_w[j + 1] = Rf.w;
+        }
+        table[2 * j] = fd.p;
+        table[2 * j + 1] = fd.q;
+        start[fd.iv + 1] = j + 1;
+        cur = Rf;
+    }
+    for (int i = 0; i < k; ++i) start[i + 1] = std::max(start[i + 1], start[i]);
+    *n_bp = nb;
+    if (launch_exit_pieces_init(exit_out, n, lam_lo, lam_hi, nb + 1, h->stream) != 0) return release(PMF_EDEVICE);
+    // each interval's breakpoints go to the start of the round area before
+    // its placement kernel (stream order keeps the previous one's reads)
+    const size_t room = (size_t)R * probe_planes;
+    size_t at = 0;
+    for (int i = 0; i < k; ++i) {
+        const Interval &I = iv[i];
+        const int cnt = start[i + 1] - start[i];
+        const size_t bytes = 16 * (size_t)cnt;
+        if (at + bytes > room) at = 0;
+        if (bytes > room) return release(PMF_ENOMEM);
+        int64_t *dtab = (int64_t *)(scr + at);
+        if (hipMemcpyAsync(dtab, table.data() + 2 * (size_t)start[i], bytes, hipMemcpyHostToDevice, h->stream) !=
+                hipSuccess ||
+            launch_exit_place((const int32_t *)(pers + I.o_ep), (const int32_t *)(pers + I.o_eq), I.x0, I.y0, I.w,
+                              I.h, W, dtab, cnt, start[i], exit_out, h->stream) != 0)
+            return release(PMF_EDEVICE);
+        at = align_up(at + bytes);
+    }
+    return release(nb > max_bp ? PMF_ERANGE : PMF_OK);
 }
 
 int pmf_destroy(pmf_handle *h) {

@@ -149,6 +149,8 @@ def load_library() -> ctypes.CDLL:
         "pmf_get_trace": (ctypes.c_int64, [P, P, ctypes.c_int64]),
         "pmf_parametric": (ctypes.c_int, [P, ctypes.POINTER(InstanceC), ctypes.c_int32, ctypes.c_int32, P, P,
                                           ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), P]),
+        "pmf_breakpoints": (ctypes.c_int, [P, ctypes.POINTER(InstanceC), ctypes.c_int32, ctypes.c_int32, P, P, P,
+                                           P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), P]),
         "pmf_extract_levels": (ctypes.c_int, [P, ctypes.c_int32, P]),
         "pmf_session_open": (ctypes.c_int, [P, ctypes.c_int32, ctypes.c_size_t]),
         "pmf_session_submit": (ctypes.c_int, [P, ctypes.POINTER(InstanceC), ctypes.c_int32, P, P,
@@ -285,6 +287,28 @@ def pmf_parametric(handle, inst: "DeviceInstance", lam_lo: int, lam_hi: int, max
         raise PmfError(rc, "pmf_parametric")
     n = nbp.value
     return bp[:n].copy(), fo[:n + 1].copy(), ex
+
+
+def pmf_breakpoints(handle, inst: "DeviceInstance", lam_lo: int, lam_hi: int, max_bp: int = 4096):
+    """Every real breakpoint of one instance over [lam_lo, lam_hi] (see the C
+    declaration).  Returns (numerators int64, denominators int64, piece
+    intercepts int64 [n + 1], piece slopes int64 [n + 1], per-pixel exit piece
+    (int32 H x W device tensor))."""
+    m = max(max_bp, 1)
+    num = np.zeros(m, dtype=np.int64)
+    den = np.zeros(m, dtype=np.int64)
+    pa = np.zeros(m + 1, dtype=np.int64)
+    pw = np.zeros(m + 1, dtype=np.int64)
+    nbp = ctypes.c_int32(0)
+    ex = torch.empty((inst.H, inst.W), dtype=torch.int32, device=inst.cap_src.device)
+    c = inst.c_struct()
+    rc = load_library().pmf_breakpoints(handle, ctypes.byref(c), int(lam_lo), int(lam_hi), num.ctypes.data,
+                                        den.ctypes.data, pa.ctypes.data, pw.ctypes.data, int(max_bp),
+                                        ctypes.byref(nbp), int(ex.data_ptr()))
+    if rc != PMF_OK:
+        raise PmfError(rc, "pmf_breakpoints")
+    n = nbp.value
+    return num[:n].copy(), den[:n].copy(), pa[:n + 1].copy(), pw[:n + 1].copy(), ex
 
 
 def pmf_get_trace(handle) -> np.ndarray:

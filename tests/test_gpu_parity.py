@@ -7,6 +7,8 @@ previous lambda's preflow, so agreement also checks the warm start.
 
 import sys
 
+from fractions import Fraction
+
 import numpy as np
 import pytest
 
@@ -452,4 +454,59 @@ def test_parametric_breakpoints(pmf):
         assert int(f[0]) == fs[0], ci
         assert [int(x) for x in f[1:]] == [fs[b - lo] for b in exp_bp], ci
         assert (ex.cpu().numpy() == exp_exit).all(), ci
+    s.close()
+
+
+def test_breakpoints_exact_enumeration(pmf):
+    """Every real breakpoint of grids of at most 12 pixels equals the lower
+    envelope of the lines of all their source sets, in exact rational
+    arithmetic: the breakpoints, each piece's line and each pixel's exit piece."""
+    from helpers import envelope, source_set_lines
+    rng = np.random.default_rng(1509)
+    s = pmf.Solver()
+    nbps = 0
+    for ci in range(48):
+        while True:
+            Wd, Hd = int(rng.integers(1, 5)), int(rng.integers(1, 5))
+            if Wd * Hd <= 12:
+                break
+        inst = W.tiny_random(rng, Wd, Hd, 4 if ci % 2 else 8, cmax=int(rng.choice([5, 20, 60])), L=1,
+                             p_seed=float(rng.uniform(0, 0.2)))
+        lo, hi = int(rng.integers(0, 4)), int(rng.integers(20, 120))
+        sets, A, w = source_set_lines(inst)
+        bps, pieces, psets = envelope(sets, A, w, lo, hi)
+        dev = pmf.to_device([inst])[0]
+        say("breakpoints enumeration case", ci, Wd, Hd, inst.K, "range", lo, hi, "breakpoints", len(bps))
+        num, den, pa, pw, ex = pmf.pmf_breakpoints(s.handle, dev, lo, hi)
+        got = [Fraction(int(a), int(b)) for a, b in zip(num, den)]
+        assert got == bps, (ci, got, bps)
+        assert [(int(a), int(b)) for a, b in zip(pa, pw)] == [(int(a), int(b)) for a, b in pieces], ci
+        exm = ex.cpu().numpy().reshape(-1)
+        for j, ps in enumerate(psets):
+            assert ((exm > j) == ps).all(), (ci, j)
+        nbps += len(bps)
+    assert nbps >= 20
+    s.close()
+
+
+def test_breakpoints_against_rational_oracle(pmf):
+    """Real breakpoints of larger grids proven exact with oracle solves at
+    rational lambdas (F on the pieces' lines at both ends of every piece and
+    the minimal sets inside and at the ends of every piece), including wide
+    ranges whose unit intervals hold several breakpoints."""
+    from helpers import check_breakpoints_oracle, host_threads
+    rng = np.random.default_rng(1510)
+    cases = []
+    for i in range(4):
+        Wd, Hd = int(rng.integers(6, 20)), int(rng.integers(6, 20))
+        inst = W.tiny_random(rng, Wd, Hd, 4 if i % 2 else 8, cmax=200, L=1, p_seed=0.05)
+        cases.append((inst, int(rng.integers(0, 5)), int(rng.integers(300, 700))))
+    cases.append((W.config0()[0], 0, 250))
+    s = pmf.Solver()
+    for ci, (inst, lo, hi) in enumerate(cases):
+        dev = pmf.to_device([inst])[0]
+        num, den, pa, pw, ex = pmf.pmf_breakpoints(s.handle, dev, lo, hi)
+        say("breakpoints oracle case", ci, inst.W, inst.H, inst.K, "range", lo, hi, "breakpoints", len(num),
+            "largest denominator", int(den.max()) if len(den) else 1)
+        check_breakpoints_oracle(inst, lo, hi, num, den, pa, pw, ex.cpu().numpy(), host_threads())
     s.close()

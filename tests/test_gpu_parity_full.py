@@ -13,6 +13,8 @@
   oracle solves at both ends of the range and on both sides of every
   reported change point prove the list complete (the sets are nested in
   lambda, so equal sets at both ends of a gap leave no change inside it).
+* All real breakpoints of the same seeds, proven with oracle solves at
+  rational lambdas.
 * The int32 headroom: n-links at the largest admitted capacity next to
   INF seeds, where excess reaches INF + K * PMF_NLINK_MAX(K).
 
@@ -156,6 +158,26 @@ def test_parametric_full_size(pmf, K, seed):
     for lam in reversed([lo] + bp):
         exp[~mask[lam]] = lam
     assert (ex == exp).all(), int((ex != exp).sum())
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("K,seed", [(4, 0), (8, 12)])
+def test_real_breakpoints_full_size(pmf, K, seed):
+    """Every real breakpoint in [1, 2000] of one 500x375 seed instance of the
+    benchmark workload, proven exact with oracle solves at rational lambdas
+    (each breakpoint and each piece's midpoint)."""
+    import torch
+    from helpers import check_breakpoints_oracle
+    inst = W.config2(K=K)[seed]
+    dev = pmf.to_device([inst])[0]
+    s = pmf.Solver()
+    say("real breakpoints full size K=%d seed %d" % (K, seed))
+    num, den, pa, pw, ex = pmf.pmf_breakpoints(s.handle, dev, 1, 2000)
+    torch.cuda.synchronize()
+    ex = ex.cpu().numpy()
+    s.close()
+    say("%d breakpoints, largest denominator %d; oracle proof" % (len(num), int(den.max()) if len(den) else 1))
+    check_breakpoints_oracle(inst, 1, 2000, num, den, pa, pw, ex, host_threads())
 
 
 @pytest.mark.parametrize("orientation", [0, 3])

@@ -19,7 +19,7 @@ import pytest
 from oracle import oracle as O
 from paper_1509_06004_amd import workload as W
 
-from helpers import golden_instances
+from helpers import golden_instances, source_set_lines
 
 
 @pytest.mark.parametrize("name,inst,flows,masks", golden_instances(),
@@ -329,44 +329,6 @@ def test_int32_headroom_brute_force():
     assert biggest >= (1 << 31) - 8  # some optimal cuts cost about INF + K * PMF_NLINK_MAX(K)
 
 
-def _envelope_enumeration(inst):
-    """Every source set of a grid of at most 12 pixels as a line in lambda:
-    cost(S, lambda) = A_S + w_S * lambda (Sec. 2.1, monotone case), written
-    out from the cut definition with Python integers.  Returns the sets
-    (bool [2^n, n]) and A, w (object arrays of ints)."""
-    Wd, Hd, K = inst.W, inst.H, inst.K
-    n = Wd * Hd
-    assert n <= 12
-    nl = np.asarray(inst.nlink).reshape(K, Hd, Wd)
-    cs = np.asarray(inst.cap_src).reshape(-1)
-    c0 = np.asarray(inst.cap_snk0).reshape(-1)
-    sl = np.asarray(inst.snk_slope).reshape(-1)
-    sd = np.asarray(inst.seed).reshape(-1)
-    sets = ((np.arange(1 << n)[:, None] >> np.arange(n)[None, :]) & 1).astype(bool)
-    A, w = [], []
-    for T in sets:
-        a = b = 0
-        for p in range(n):
-            if sd[p] == 1:
-                a += 0 if T[p] else O.INF
-            elif sd[p] == 2:
-                a += O.INF if T[p] else 0
-            elif T[p]:
-                a += int(c0[p])
-                b += int(sl[p])
-            else:
-                a += int(cs[p])
-        for k in range(K):
-            for y in range(Hd):
-                for x in range(Wd):
-                    qx, qy = x + O._DX[k], y + O._DY[k]
-                    if 0 <= qx < Wd and 0 <= qy < Hd and T[y * Wd + x] and not T[qy * Wd + qx]:
-                        a += int(nl[k, y, x])
-        A.append(a)
-        w.append(b)
-    return sets, A, w
-
-
 def test_rational_lambda_brute_force():
     """At rational lambda = num/den the scaled solve gives den * F and S_min
     exactly as the enumeration of every source set in exact rational
@@ -377,7 +339,7 @@ def test_rational_lambda_brute_force():
     for i, inst in enumerate(_random_tiny(33, 60)):
         if inst.W * inst.H > 12:
             continue
-        sets, A, w = _envelope_enumeration(inst)
+        sets, A, w = source_set_lines(inst)
         for _ in range(4):
             den = int(rng.integers(1, 8))
             num = int(rng.integers(0, 30 * den))
@@ -393,3 +355,29 @@ def test_rational_lambda_brute_force():
                 assert f1 == f and (m1 == m).all()
             checked += 1
     assert checked >= 150
+
+
+def test_envelope_of_enumeration_passes_the_oracle_check():
+    """The two checks of a breakpoint list agree: the lower envelope of every
+    source set's line, turned into breakpoints, pieces and exit pieces, passes
+    the oracle-based proof at rational lambdas."""
+    from helpers import check_breakpoints_oracle, envelope
+    rng = np.random.default_rng(616)
+    total = 0
+    for i in range(60):
+        Wd, Hd = int(rng.integers(1, 4)), int(rng.integers(1, 5))
+        inst = W.tiny_random(rng, Wd, Hd, 4 if i % 2 else 8, cmax=int(rng.choice([5, 20, 60])), L=1,
+                             p_seed=float(rng.uniform(0, 0.2)))
+        lo, hi = int(rng.integers(0, 4)), int(rng.integers(20, 120))
+        sets, A, w = source_set_lines(inst)
+        bps, pieces, psets = envelope(sets, A, w, lo, hi)
+        ex = np.full(Wd * Hd, len(bps) + 1, dtype=np.int64)
+        for j in range(len(psets) - 1, -1, -1):
+            ex[~psets[j]] = j
+        num = np.array([b.numerator for b in bps], dtype=np.int64)
+        den = np.array([b.denominator for b in bps], dtype=np.int64)
+        pa = np.array([a for a, _ in pieces], dtype=np.int64)
+        pw = np.array([b for _, b in pieces], dtype=np.int64)
+        check_breakpoints_oracle(inst, lo, hi, num, den, pa, pw, ex.reshape(Hd, Wd), 4)
+        total += len(bps)
+    assert total >= 25
