@@ -17,7 +17,8 @@ HBM before timing starts.  The same run also reports
 * the 8-connected variant of the same workload,
 * the uneven workload: 256 images of 64..640 x 64..480, mixed connectivity,
   1..16 seeds, 10..30 lambdas each (about 42 000 solves in one call),
-* all breakpoints of one seed over lambda in 1..2000,
+* all breakpoints of one seed over lambda in 1..2000 (integer change points,
+  then every real breakpoint),
 * the serving loop under Poisson arrivals at 50, 200 and 800 requests/s,
 * the CPU oracle on every one of the 500 solves (host cores, one solve per
   thread), which also verifies every GPU flow and mask bit for bit,
@@ -565,11 +566,23 @@ def main():
         bps, bfl, _ = pmf.pmf_parametric(bsolver.handle, binst, 1, 2000)
         torch.cuda.synchronize()
         tb = time.perf_counter() - t0
+        pmf.pmf_breakpoints(bsolver.handle, binst, 1, 2000)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rnum, rden, _, _, _ = pmf.pmf_breakpoints(bsolver.handle, binst, 1, 2000)
+        torch.cuda.synchronize()
+        tr = time.perf_counter() - t0
         bsolver.close()
         out["breakpoints"] = {"range": [1, 2000], "change_points": int(len(bps)), "ms": round(tb * 1e3, 2),
                               "workload": "seed 0 of the headline workload: all integer lambdas in 1..2000 at "
-                                          "which S_min changes, F there and each pixel's exit lambda"}
-        log("breakpoints: %d in %.1f ms" % (len(bps), tb * 1e3))
+                                          "which S_min changes, F there and each pixel's exit lambda",
+                              "real": {"breakpoints": int(len(rnum)),
+                                       "largest_denominator": int(rden.max()) if len(rden) else 1,
+                                       "ms": round(tr * 1e3, 2),
+                                       "workload": "the same instance and range: every real breakpoint as a "
+                                                   "fraction, the line of F on each piece, each pixel's exit piece"}}
+        log("breakpoints: %d integer change points in %.1f ms, %d real breakpoints in %.1f ms"
+            % (len(bps), tb * 1e3, len(rnum), tr * 1e3))
 
     if not args.no_serve:
         rates = args.serve_qps or [50.0, 200.0, 800.0]
