@@ -148,3 +148,65 @@ def test_same_shape_batches_on_one_handle(pmf):
                 assert np.array_equal(got, np.asarray(mo, dtype=bool).reshape(inst.H, inst.W)), (seed, i, k)
             off += inst.L
         say("batch", seed, "equals the oracle; supersteps", s.stats()["supersteps"])
+
+
+def _two_pixel_instance(nl_cap):
+    """Two free pixels joined both ways by n-links of capacity nl_cap, source
+    capacity 5 each, sink slopes 1 and 2: while nl_cap binds them, F is
+    min(10, 3 lambda) with its only breakpoint at 10/3."""
+    nl = np.zeros((4, 1, 2), dtype=np.int32)
+    nl[0, 0, 0] = nl_cap  # (0,0) -> (1,0)
+    nl[1, 0, 1] = nl_cap  # (1,0) -> (0,0)
+    return W.Instance(W=2, H=1, K=4, nlink=nl, cap_src=np.full((1, 2), 5, dtype=np.int32),
+                      cap_snk0=np.zeros((1, 2), dtype=np.int32), snk_slope=np.array([[1, 2]], dtype=np.int32),
+                      seed=np.zeros((1, 2), dtype=np.uint8), lambdas=np.array([0], dtype=np.int32))
+
+
+def test_breakpoints_edge_cases(pmf):
+    """pmf_breakpoints: a range of one lambda, a range without change, a list
+    longer than max_bp (PMF_ERANGE), a probe whose scaled capacities would
+    leave int32 (PMF_ERANGE rather than an inexact answer), and the same
+    answer in a caller workspace as in library memory, with a budget too
+    small reported as PMF_ENOMEM."""
+    import torch
+    from fractions import Fraction
+    s = pmf.Solver()
+    inst = _two_pixel_instance(100)
+    dev = pmf.to_device([inst])[0]
+    num, den, pa, pw, ex = pmf.pmf_breakpoints(s.handle, dev, 0, 10)
+    assert [Fraction(int(a), int(b)) for a, b in zip(num, den)] == [Fraction(10, 3)]
+    assert list(pa) == [0, 10] and list(pw) == [3, 0]
+    assert (ex.cpu().numpy() == 1).all()  # both pixels leave at the one breakpoint
+    # one lambda (both pixels stay: exit piece 1 = never leaves), and a range
+    # with no change (neither pixel is ever in S_min: exit piece 0)
+    for lo, hi, a, w, e in ((2, 2, 0, 3, 1), (5, 9, 10, 0, 0)):
+        num, den, pa, pw, ex = pmf.pmf_breakpoints(s.handle, dev, lo, hi)
+        assert len(num) == 0 and list(pa) == [a] and list(pw) == [w], (lo, hi)
+        assert (ex.cpu().numpy() == e).all(), (lo, hi)
+    # more breakpoints than max_bp
+    big = W.config0()[0]
+    bdev = pmf.to_device([big])[0]
+    num, den, pa, pw, ex = pmf.pmf_breakpoints(s.handle, bdev, 0, 250)
+    assert len(num) >= 2
+    with pytest.raises(pmf.PmfError) as e:
+        pmf.pmf_breakpoints(s.handle, bdev, 0, 250, max_bp=1)
+    assert e.value.code == pmf.PMF_ERANGE
+    # n-links so large that 3 times them leave the solver's bound
+    hdev = pmf.to_device([_two_pixel_instance(((1 << 30) - 1) // 4)])[0]  # PMF_NLINK_MAX(4)
+    with pytest.raises(pmf.PmfError) as e:
+        pmf.pmf_breakpoints(s.handle, hdev, 0, 10)
+    assert e.value.code == pmf.PMF_ERANGE
+    s.close()
+    # a caller workspace gives the same answer; a budget too small is reported
+    ws = torch.empty(256 << 20, dtype=torch.uint8, device="cuda")
+    w = pmf.Solver(workspace=ws)
+    num1, den1, pa1, pw1, ex1 = pmf.pmf_breakpoints(w.handle, bdev, 0, 250)
+    torch.cuda.synchronize()
+    assert list(num1) == list(num) and list(den1) == list(den)
+    assert list(pa1) == list(pa) and list(pw1) == list(pw) and torch.equal(ex1, ex)
+    w.close()
+    small = pmf.Solver(mem_budget=1 << 16)
+    with pytest.raises(pmf.PmfError) as e:
+        pmf.pmf_breakpoints(small.handle, bdev, 0, 250)
+    assert e.value.code == pmf.PMF_ENOMEM
+    small.close()
