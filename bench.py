@@ -337,6 +337,9 @@ def main():
     ap.add_argument("--opt", action="append", default=[], metavar="NAME=VALUE",
                     help="solver option override (repeatable), e.g. --opt persist_tiles=0")
     ap.add_argument("--defaults", action="store_true", help="ignore the tuner cache; library defaults")
+    ap.add_argument("--tune-8conn", action="store_true",
+                    help="autotune the 8-connected variant of the workload first and store the result in the "
+                         "package's tuner cache (its bench leg then uses it)")
     ap.add_argument("--tune", action="store_true",
                     help="autotune the speed knobs on this workload first and store the result in the "
                          "package's tuner cache (results must not change)")
@@ -381,21 +384,31 @@ def main():
     n_solves = sum(i.L for i in insts)
     dev = pmf.to_device(insts)
 
+    def tune_and_store(tinsts, tdev, what):
+        # coordinate descent over the speed knobs on this workload; the result
+        # goes to the package's tuner cache under the workload's class
+        from paper_1509_06004_amd import tune as T
+        t0 = time.perf_counter()
+        res = T.tune(tdev, log=log)
+        if res["rejected"]:
+            raise SystemExit("autotuner found configurations with different results: %s" % res["rejected"])
+        key = T.workload_key(tinsts, torch.cuda.get_device_name(0))
+        cache = T.load_cache(T.PACKAGE_CACHE)
+        cache[key] = {"options": res["options"], "seconds": res["seconds"], "trials": len(res["trials"]),
+                      "confirmed": res["confirmed"], "tuned_on": what}
+        T.save_cache(cache, T.PACKAGE_CACHE)
+        return key, res, round(time.perf_counter() - t0, 1)
+
+    if args.tune_8conn:
+        insts8 = workload.config2(K=8)
+        tune_and_store(insts8, pmf.to_device(insts8), "500x375 8-connected, 25 seeds x 20 lambdas")
+
     tuned = None
     overrides = {}
     if args.tune:
-        from paper_1509_06004_amd import tune as T
-        t0 = time.perf_counter()
-        res = T.tune(dev, log=log)
-        if res["rejected"]:
-            raise SystemExit("autotuner found configurations with different results: %s" % res["rejected"])
-        key = T.workload_key(insts, torch.cuda.get_device_name(0))
-        cache = T.load_cache(T.PACKAGE_CACHE)
-        cache[key] = {"options": res["options"], "seconds": res["seconds"], "trials": len(res["trials"]),
-                      "confirmed": res["confirmed"], "tuned_on": "500x375 4-connected, 25 seeds x 20 lambdas"}
-        T.save_cache(cache, T.PACKAGE_CACHE)
+        key, res, secs = tune_and_store(insts, dev, "500x375 4-connected, 25 seeds x 20 lambdas")
         tuned = {"source": "tuned in this run", "key": key, "options": res["options"],
-                 "tune_seconds": round(time.perf_counter() - t0, 1), "trials": len(res["trials"])}
+                 "tune_seconds": secs, "trials": len(res["trials"])}
         overrides = dict(res["options"])
     elif not args.defaults:
         key, opts, entry = tuned_options(insts, log)
