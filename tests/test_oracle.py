@@ -355,6 +355,24 @@ def test_rational_lambda_brute_force():
                 assert f1 == f and (m1 == m).all()
             checked += 1
     assert checked >= 150
+    # capacities near INF (n-links at PMF_NLINK_MAX next to INF seeds): a
+    # cut through an INF arc competes with finite ones only if INF is scaled
+    # with everything else
+    from helpers import headroom_instance
+    big = 0
+    for i in range(12):
+        inst = headroom_instance(rng, 3, int(rng.integers(3, 5)), 4 if i % 2 else 8, 1)
+        sets, A, w = source_set_lines(inst)
+        for den in (2, 3, 5):
+            num = int(rng.integers(0, 1000 * den))
+            lam = Fraction(num, den)
+            cost = [a + b * lam for a, b in zip(A, w)]
+            F = min(cost)
+            smin = np.logical_and.reduce(sets[[c == F for c in cost]], axis=0)
+            f, m = O.fifo_pr_rational(inst, num, den)
+            assert f == F * den and (m.reshape(-1) == smin).all(), (i, num, den)
+            big = max(big, f)
+    assert big > (1 << 31)  # scaled cuts well above INF: INF must scale with them
 
 
 def test_envelope_of_enumeration_passes_the_oracle_check():
