@@ -210,3 +210,29 @@ def test_breakpoints_edge_cases(pmf):
         pmf.pmf_breakpoints(small.handle, bdev, 0, 250)
     assert e.value.code == pmf.PMF_ENOMEM
     small.close()
+
+
+def test_breakpoints_do_not_depend_on_options(pmf):
+    """The real breakpoints, piece lines and exit pieces are the same under
+    every speed option that changes how the probes are solved: tile shape,
+    orientation policy, gap heuristic, persistent launch, timing mode."""
+    rng = np.random.default_rng(79)
+    cases = [(W.config0()[0], 0, 250),
+             (W.tiny_random(rng, 16, 13, 8, cmax=200, L=1, p_seed=0.05), 2, 600)]
+    variants = [{}, {"tile_w": 64, "tile_h": 16}, {"orientation": 0}, {"orientation": 3}, {"gap": 1},
+                {"persist_tiles": 1 << 20}, {"timing": 2}]
+    for ci, (inst, lo, hi) in enumerate(cases):
+        dev = pmf.to_device([inst])[0]
+        ref = None
+        for opts in variants:
+            s = pmf.Solver(**opts)
+            num, den, pa, pw, ex = pmf.pmf_breakpoints(s.handle, dev, lo, hi)
+            got = (list(num), list(den), list(pa), list(pw), ex.cpu().numpy())
+            s.close()
+            say("breakpoints case", ci, "options", opts, "breakpoints", len(num))
+            if ref is None:
+                ref = got
+                assert len(num) >= 3, ci
+                continue
+            assert got[:4] == ref[:4], (ci, opts)
+            assert (got[4] == ref[4]).all(), (ci, opts)
