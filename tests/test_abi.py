@@ -30,6 +30,17 @@ def test_header_declares_the_four_calls():
         assert n in names
 
 
+def test_header_is_plain_c_and_cxx(tmp_path):
+    """The header compiles as C99 and as C++ (callers from either language)."""
+    import subprocess
+    src = tmp_path / "use.c"
+    src.write_text('#include "pmf.h"\nint main(void) { pmf_options o; pmf_default_options(&o); return (int)o.tile_w; }\n')
+    for cmd in (["gcc", "-std=c99", "-Wall", "-Werror", "-fsyntax-only", "-I", os.path.dirname(HEADER), str(src)],
+                ["g++", "-std=c++17", "-Wall", "-Werror", "-fsyntax-only", "-x", "c++", "-I", os.path.dirname(HEADER),
+                 str(src)]):
+        subprocess.run(cmd, check=True)
+
+
 def test_every_declared_symbol_is_exported(lib):
     names = declared_functions()
     assert len(names) >= 9
