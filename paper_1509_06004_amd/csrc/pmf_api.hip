@@ -289,7 +289,9 @@ int ensure_arena(pmf_handle *h, size_t need) {
     if (!h->own_arena) return PMF_ENOMEM;
     if (h->opt.mem_budget > 0 && (int64_t)need > h->opt.mem_budget) return PMF_ENOMEM;
     if (h->arena) {
+        // the last solve's or session's state lived there: it is gone
         (void)hipStreamSynchronize(h->stream);
+        h->open = false;
         (void)hipFree(h->arena);
         h->arena = nullptr;
         h->arena_bytes = 0;
