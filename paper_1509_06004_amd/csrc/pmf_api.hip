@@ -1664,6 +1664,7 @@ int pmf_breakpoints(pmf_handle *h, const pmf_instance *inst, int32_t lam_lo, int
             const Interval &I = iv[pr.iv];
             if ((__int128)p <= (__int128)(I.c - 1) * q || (__int128)p > (__int128)I.c * q)
                 return release(PMF_EDEVICE);
+            if ((__int128)p * pr.rq > (__int128)pr.rp * q) return release(PMF_EDEVICE);  // past R's point
             if ((__int128)p * pr.rq == (__int128)pr.rp * q) {  // at R's own point: F(x) is known
                 found.push_back(Found{pr.iv, p, q, pr.L, pr.R});
                 continue;
