@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpmf.so")
-SOURCES = [os.path.join(CSRC, f) for f in ("pmf_kernels.hip", "pmf_contract.hip", "pmf_api.hip")]
+SOURCES = [os.path.join(CSRC, f) for f in ("pmf_kernels.hip", "pmf_parametric.hip", "pmf_api.hip")]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

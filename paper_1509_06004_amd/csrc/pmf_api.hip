@@ -20,7 +20,7 @@
 
 #include "pmf.h"
 #include "pmf_internal.h"
-#include "pmf_contract.h"
+#include "pmf_parametric.h"
 
 using namespace pmf;
 

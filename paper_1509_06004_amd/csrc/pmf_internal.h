@@ -178,15 +178,6 @@ int launch_levels(const uint8_t *masks, int L, int n, uint8_t *out, bool accumul
 // user i owns chunks [first[i], first[i+1]) and flows [flow_off[i], +L[i]).
 // The merged status is EINVAL, else EOVERFLOW, else ETIMEOUT, else OK; an
 // invalid instance gets flows -1 throughout.
-// out[0] += |S|, out[1] += sum of the sink slopes of the free pixels in S, for
-// a row-major mask of n pixels (out zeroed by the caller).
-int launch_mask_stats(const uint8_t *mask, int n, const int32_t *slope, const uint8_t *seed, int64_t *out,
-                      void *stream);
-
-// out[p] = min(out[p], lam) where mask[p] == 0 (n pixels); out[p] = v.
-int launch_exit_min(const uint8_t *mask, int n, int32_t lam, int32_t *out, void *stream);
-int launch_fill_i32(int32_t *out, int n, int32_t v, void *stream);
-
 int launch_finalize(const int32_t *sub_status, const int64_t *meta, int n_user, int64_t *flows,
                     int32_t *status_out, void *stream);
 

@@ -1693,58 +1693,6 @@ __global__ __launch_bounds__(kThreads) void k_finalize(const int32_t *sub_status
     if (status_out) status_out[i] = st;
 }
 
-// Size |S| and slope sum w(S) = sum of the sink slopes of the free pixels in
-// S (the derivative dF/dlambda on the piece of F where S is optimal) of a
-// row-major mask of n pixels, added into out[0], out[1].
-__global__ __launch_bounds__(kThreads) void k_mask_stats(const uint8_t *mask, int n, const int32_t *slope,
-                                                         const uint8_t *seed, unsigned long long *out) {
-    __shared__ unsigned long long s_sum;
-    const int p = blockIdx.x * kThreads + threadIdx.x;
-    long long in = 0, w = 0;
-    if (p < n && mask[p]) {
-        in = 1;
-        if (!seed || seed[p] == 0) w = slope ? slope[p] : 1;
-    }
-    const long long tin = block_sum_i64(in, &s_sum);
-    const long long tw = block_sum_i64(w, &s_sum);
-    if (threadIdx.x == 0) {
-        if (tin) atomicAdd(&out[0], (unsigned long long)tin);
-        if (tw) atomicAdd(&out[1], (unsigned long long)tw);
-    }
-}
-
-int launch_mask_stats(const uint8_t *mask, int n, const int32_t *slope, const uint8_t *seed, int64_t *out,
-                      void *stream) {
-    hipLaunchKernelGGL(k_mask_stats, dim3((n + kThreads - 1) / kThreads), dim3(kThreads), 0, (hipStream_t)stream,
-                       mask, n, slope, seed, (unsigned long long *)out);
-    return hipGetLastError() == hipSuccess ? 0 : -1;
-}
-
-// out[p] = min(out[p], lam) for every pixel p that `mask` (n bytes) does not
-// hold.  Applied to the masks of several lambdas it leaves, per pixel, the
-// smallest of those lambdas whose minimal source set lacks the pixel.
-__global__ __launch_bounds__(kThreads) void k_exit_min(const uint8_t *mask, int n, int32_t lam, int32_t *out) {
-    const int p = blockIdx.x * kThreads + threadIdx.x;
-    if (p < n && !mask[p] && lam < out[p]) out[p] = lam;
-}
-
-__global__ __launch_bounds__(kThreads) void k_fill_i32(int32_t *out, int n, int32_t v) {
-    const int p = blockIdx.x * kThreads + threadIdx.x;
-    if (p < n) out[p] = v;
-}
-
-int launch_exit_min(const uint8_t *mask, int n, int32_t lam, int32_t *out, void *stream) {
-    hipLaunchKernelGGL(k_exit_min, dim3((n + kThreads - 1) / kThreads), dim3(kThreads), 0, (hipStream_t)stream,
-                       mask, n, lam, out);
-    return hipGetLastError() == hipSuccess ? 0 : -1;
-}
-
-int launch_fill_i32(int32_t *out, int n, int32_t v, void *stream) {
-    hipLaunchKernelGGL(k_fill_i32, dim3((n + kThreads - 1) / kThreads), dim3(kThreads), 0, (hipStream_t)stream,
-                       out, n, v);
-    return hipGetLastError() == hipSuccess ? 0 : -1;
-}
-
 int launch_finalize(const int32_t *sub_status, const int64_t *meta, int n_user, int64_t *flows,
                     int32_t *status_out, void *stream) {
     hipLaunchKernelGGL(k_finalize, dim3((n_user + kThreads - 1) / kThreads), dim3(kThreads), 0,

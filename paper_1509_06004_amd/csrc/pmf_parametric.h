@@ -1,4 +1,5 @@
-// Kernels of the exact real-lambda breakpoint search (pmf_breakpoints):
+// Kernels of the breakpoint searches (pmf_parametric, pmf_breakpoints): set
+// statistics and exit maps of the integer search; for the real-lambda search,
 // graph contraction of the pixels that leave the minimal source set inside
 // one unit lambda interval, scaling of a contracted problem to a rational
 // lambda, and the per-pixel exit bookkeeping.
@@ -7,6 +8,15 @@
 #include <stdint.h>
 
 namespace pmf {
+
+// out[0] += |S|, out[1] += sum of the sink slopes of the free pixels in S, for
+// a row-major mask of n pixels (out zeroed by the caller).
+int launch_mask_stats(const uint8_t *mask, int n, const int32_t *slope, const uint8_t *seed, int64_t *out,
+                      void *stream);
+
+// out[p] = min(out[p], lam) where mask[p] == 0 (n pixels); out[p] = v.
+int launch_exit_min(const uint8_t *mask, int n, int32_t lam, int32_t *out, void *stream);
+int launch_fill_i32(int32_t *out, int n, int32_t v, void *stream);
 
 // Per-interval statistics written by launch_contract (int64 each).
 enum ContractStat : int {

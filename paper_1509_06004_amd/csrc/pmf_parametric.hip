@@ -1,16 +1,21 @@
-// Kernels of the exact real-lambda breakpoint search: contraction of one unit
-// lambda interval's changing pixels (Sec. 2.1: the minimal source sets are
-// nested in lambda, so between two nested sets the outer pixels are fixed to
-// the sink and the inner ones to the source, as in the parametric algorithm
-// of Gallo, Grigoriadis and Tarjan), scaling to a rational lambda, and the
-// per-pixel exit bookkeeping.
+// Kernels of the breakpoint searches: the size and slope sum of a minimal
+// source set and the running exit map of the integer search, and for the
+// exact real-lambda search the contraction of one unit lambda interval's
+// changing pixels (Sec. 2.1: the minimal source sets are nested in lambda, so
+// between two nested sets the outer pixels are fixed to the sink and the
+// inner ones to the source, as in the parametric algorithm of Gallo,
+// Grigoriadis and Tarjan), scaling to a rational lambda, and the per-pixel
+// exit bookkeeping.  All are one pass over a mask or a box, bound by memory
+// latency; the reductions combine a wave's lanes by shuffles before any
+// atomic.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <climits>
 
 #include "pmf.h"
 #include "pmf_border.h"
-#include "pmf_contract.h"
+#include "pmf_parametric.h"
 
 namespace pmf {
 
@@ -30,25 +35,95 @@ __global__ __launch_bounds__(kBlock) void k_fill_boxes(int32_t *boxes, int k) {
     }
 }
 
+// A wave's lanes that hold pixels of the same change point combine their
+// boxes by shuffles first (neighbouring pixels mostly leave together), so a
+// change point of many pixels costs one set of atomics per wave, not per pixel.
 __global__ __launch_bounds__(kBlock) void k_change_boxes(const int32_t *exit, int W, int n, const int32_t *changes,
                                                          int k, int32_t *boxes) {
     const int p = blockIdx.x * kBlock + threadIdx.x;
-    if (p >= n) return;
-    const int32_t e = exit[p];
-    int lo = 0, hi = k;  // first change >= e
-    while (lo < hi) {
-        const int mid = (lo + hi) >> 1;
-        if (changes[mid] < e)
-            lo = mid + 1;
-        else
-            hi = mid;
+    int idx = -1;
+    if (p < n) {
+        const int32_t e = exit[p];
+        int lo = 0, hi = k;  // first change >= e
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (changes[mid] < e)
+                lo = mid + 1;
+            else
+                hi = mid;
+        }
+        if (lo < k && changes[lo] == e) idx = lo;
     }
-    if (lo == k || changes[lo] != e) return;
-    const int x = p % W, y = p / W;
-    atomicMin(&boxes[4 * lo], x);
-    atomicMin(&boxes[4 * lo + 1], y);
-    atomicMax(&boxes[4 * lo + 2], x);
-    atomicMax(&boxes[4 * lo + 3], y);
+    const int x = p % W, y = p / W, lane = (int)(threadIdx.x & 63);
+    unsigned long long left = __ballot(idx >= 0);
+    while (left) {  // wave-uniform
+        const int leader = __ffsll((long long)left) - 1;
+        const int li = __shfl(idx, leader);
+        const bool mine = idx == li;
+        int x0 = mine ? x : INT_MAX, y0 = mine ? y : INT_MAX, x1 = mine ? x : -1, y1 = mine ? y : -1;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+            x0 = min(x0, __shfl_xor(x0, off));
+            y0 = min(y0, __shfl_xor(y0, off));
+            x1 = max(x1, __shfl_xor(x1, off));
+            y1 = max(y1, __shfl_xor(y1, off));
+        }
+        if (lane == leader) {
+            atomicMin(&boxes[4 * li], x0);
+            atomicMin(&boxes[4 * li + 1], y0);
+            atomicMax(&boxes[4 * li + 2], x1);
+            atomicMax(&boxes[4 * li + 3], y1);
+        }
+        left &= ~__ballot(mine);
+    }
+}
+
+// Size and slope sum of a mask: a grid-stride pass, the lanes' sums combined
+// by shuffles, then the waves' in LDS, one pair of atomics per workgroup.
+__global__ __launch_bounds__(kBlock) void k_mask_stats(const uint8_t *mask, int n, const int32_t *slope,
+                                                       const uint8_t *seed, unsigned long long *out) {
+    __shared__ long long s_in[kBlock / 64], s_w[kBlock / 64];
+    long long in = 0, w = 0;
+    for (int p = blockIdx.x * kBlock + threadIdx.x; p < n; p += gridDim.x * kBlock) {
+        if (mask[p]) {
+            in += 1;
+            if (!seed || seed[p] == 0) w += slope ? slope[p] : 1;
+        }
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        in += __shfl_xor(in, off);
+        w += __shfl_xor(w, off);
+    }
+    const int wv = (int)(threadIdx.x >> 6);
+    if ((threadIdx.x & 63) == 0) {
+        s_in[wv] = in;
+        s_w[wv] = w;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        long long ti = 0, tw = 0;
+#pragma unroll
+        for (int i = 0; i < kBlock / 64; ++i) {
+            ti += s_in[i];
+            tw += s_w[i];
+        }
+        if (ti) atomicAdd(&out[0], (unsigned long long)ti);
+        if (tw) atomicAdd(&out[1], (unsigned long long)tw);
+    }
+}
+
+// out[p] = min(out[p], lam) for every pixel p that `mask` (n bytes) does not
+// hold.  Applied to the masks of several lambdas it leaves, per pixel, the
+// smallest of those lambdas whose minimal source set lacks the pixel.
+__global__ __launch_bounds__(kBlock) void k_exit_min(const uint8_t *mask, int n, int32_t lam, int32_t *out) {
+    const int p = blockIdx.x * kBlock + threadIdx.x;
+    if (p < n && !mask[p] && lam < out[p]) out[p] = lam;
+}
+
+__global__ __launch_bounds__(kBlock) void k_fill_i32(int32_t *out, int n, int32_t v) {
+    const int p = blockIdx.x * kBlock + threadIdx.x;
+    if (p < n) out[p] = v;
 }
 
 __global__ __launch_bounds__(kBlock) void k_zero_i64(int64_t *out, int n) {
@@ -182,6 +257,23 @@ __global__ __launch_bounds__(kBlock) void k_exit_place(const int32_t *ep, const 
 inline int launched() { return hipGetLastError() == hipSuccess ? 0 : -1; }
 
 }  // namespace
+
+int launch_mask_stats(const uint8_t *mask, int n, const int32_t *slope, const uint8_t *seed, int64_t *out,
+                      void *stream) {
+    hipLaunchKernelGGL(k_mask_stats, dim3(std::min(blocks(n), 256)), dim3(kBlock), 0, (hipStream_t)stream, mask, n,
+                       slope, seed, (unsigned long long *)out);
+    return launched();
+}
+
+int launch_exit_min(const uint8_t *mask, int n, int32_t lam, int32_t *out, void *stream) {
+    hipLaunchKernelGGL(k_exit_min, dim3(blocks(n)), dim3(kBlock), 0, (hipStream_t)stream, mask, n, lam, out);
+    return launched();
+}
+
+int launch_fill_i32(int32_t *out, int n, int32_t v, void *stream) {
+    hipLaunchKernelGGL(k_fill_i32, dim3(blocks(n)), dim3(kBlock), 0, (hipStream_t)stream, out, n, v);
+    return launched();
+}
 
 int launch_change_boxes(const int32_t *exit, int W, int H, const int32_t *changes, int k, int32_t *boxes,
                         void *stream) {
