@@ -510,3 +510,30 @@ def test_breakpoints_against_rational_oracle(pmf):
             "largest denominator", int(den.max()) if len(den) else 1)
         check_breakpoints_oracle(inst, lo, hi, num, den, pa, pw, ex.cpu().numpy(), host_threads())
     s.close()
+
+
+def test_breakpoints_agree_with_integer_search(pmf):
+    """The two searches describe the same function: the integer change points
+    are the ceilings of the real breakpoints, F at each of them lies on the
+    piece that holds it, and each pixel's integer exit lambda is the ceiling
+    of its real exit breakpoint (lam_lo and lam_hi + 1 for pixels never in,
+    or never leaving, the minimal set)."""
+    import math
+    rng = np.random.default_rng(2718)
+    cases = [(W.config0()[0], 0, 250), (W.tiny_random(rng, 14, 11, 4, cmax=200, L=1, p_seed=0.05), 1, 700)]
+    s = pmf.Solver()
+    for ci, (inst, lo, hi) in enumerate(cases):
+        dev = pmf.to_device([inst])[0]
+        bp, f, ex_i = pmf.pmf_parametric(s.handle, dev, lo, hi)
+        num, den, pa, pw, ex_r = pmf.pmf_breakpoints(s.handle, dev, lo, hi)
+        xs = [Fraction(int(a), int(b)) for a, b in zip(num, den)]
+        say("integer vs real case", ci, "change points", len(bp), "breakpoints", len(xs))
+        assert sorted({math.ceil(x) for x in xs}) == [int(c) for c in bp], ci
+        # F at lam_lo and at each change point c, on the piece holding c
+        for c, fc in zip([lo] + [int(c) for c in bp], f):
+            j = sum(1 for x in xs if x <= c)
+            assert int(fc) == int(pa[j]) + int(pw[j]) * c, (ci, c)
+        exi, exr = ex_i.cpu().numpy(), ex_r.cpu().numpy()
+        ceil_of = np.array([lo] + [math.ceil(x) for x in xs] + [hi + 1], dtype=np.int64)
+        assert (ceil_of[exr] == exi).all(), ci
+    s.close()
