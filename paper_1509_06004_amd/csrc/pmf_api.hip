@@ -1476,6 +1476,8 @@ int pmf_parametric(pmf_handle *h, const pmf_instance *inst, int32_t lam_lo, int3
     pmf_instance base;
     if (breakpoint_base(inst, lam_lo, lam_hi, &base) != PMF_OK) return PMF_EINVAL;
     (void)finish_async(h);
+    (void)hipStreamSynchronize(h->stream);
+    h->open = false;  // the search's own buffers overwrite the last solve's memory
     *n_bp = 0;
     std::map<int32_t, BpPoint> pts;
     std::vector<int32_t> changes;
@@ -1501,6 +1503,8 @@ int pmf_breakpoints(pmf_handle *h, const pmf_instance *inst, int32_t lam_lo, int
     pmf_instance base;
     if (breakpoint_base(inst, lam_lo, lam_hi, &base) != PMF_OK) return PMF_EINVAL;
     (void)finish_async(h);
+    (void)hipStreamSynchronize(h->stream);
+    h->open = false;  // the search's own buffers overwrite the last solve's memory
     *n_bp = 0;
     auto release = [&](int code) {
         (void)hipStreamSynchronize(h->stream);
