@@ -346,7 +346,7 @@ int pmf_slot_stats(pmf_handle *h, int64_t *out, int32_t max_slots, int32_t *n_sl
  * Returns PMF_OK, PMF_ERANGE when more than max_bp change points exist (the
  * first max_bp are written), an instance status (PMF_EINVAL, PMF_EOVERFLOW,
  * PMF_ETIMEOUT) or PMF_ENOMEM / PMF_EDEVICE.  Replaces the handle's last
- * solve. */
+ * solve, also when it fails. */
 int pmf_parametric(pmf_handle *h, const pmf_instance *inst, int32_t lam_lo, int32_t lam_hi, int32_t *bp_out,
                    int64_t *f_out, int32_t max_bp, int32_t *n_bp, int32_t *exit_out);
 
@@ -381,10 +381,11 @@ int pmf_parametric(pmf_handle *h, const pmf_instance *inst, int32_t lam_lo, int3
  * first max_bp are written) or when a probe's scaled capacities would leave
  * the solver's int32 limits (q * capacity above PMF_INF or PMF_NLINK_MAX(K)),
  * an instance status (PMF_EINVAL, PMF_EOVERFLOW, PMF_ETIMEOUT) or PMF_ENOMEM
- * / PMF_EDEVICE.  Replaces the handle's last solve.  Device memory: that of
- * pmf_parametric, then (K + 5) * 4 bytes per pixel of the bounding box of
- * each unit interval's changing pixels, kept for the whole refinement, plus
- * one round of up to 64 scaled probes of the largest box and their solve. */
+ * / PMF_EDEVICE.  Replaces the handle's last solve, also when it fails.
+ * Device memory: that of pmf_parametric, then (K + 5) * 4 bytes per pixel of
+ * the bounding box of each unit interval's changing pixels, kept for the
+ * whole refinement, plus one round of up to 64 scaled probes of the largest
+ * box and their solve. */
 int pmf_breakpoints(pmf_handle *h, const pmf_instance *inst, int32_t lam_lo, int32_t lam_hi, int64_t *bp_num,
                     int64_t *bp_den, int64_t *piece_a, int64_t *piece_w, int32_t max_bp, int32_t *n_bp,
                     int32_t *exit_out);
