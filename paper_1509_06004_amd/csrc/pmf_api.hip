@@ -1718,7 +1718,12 @@ int pmf_breakpoints(pmf_handle *h, const pmf_instance *inst, int32_t lam_lo, int
             if (hipMemcpyAsync(dl, lam.data(), 4 * (size_t)m, hipMemcpyHostToDevice, h->stream) != hipSuccess ||
                 hipMemsetAsync(dst, 0, 16 * (size_t)m, h->stream) != hipSuccess)
                 return release(PMF_EDEVICE);
+            // the contracted probes hold no seeds and are solved as given (the
+            // orientation rule is tuned for seeded images)
+            const int32_t orient = h->opt.orientation;
+            h->opt.orientation = kOrientAsGiven;
             rc = pmf_solve_batch(h, pi.data(), m, df, ds);
+            h->opt.orientation = orient;
             if (rc != PMF_OK) return release(rc);
             if (hipMemcpy(sts.data(), ds, 4 * (size_t)m, hipMemcpyDeviceToHost) != hipSuccess)
                 return release(PMF_EDEVICE);
