@@ -399,3 +399,46 @@ def test_envelope_of_enumeration_passes_the_oracle_check():
         check_breakpoints_oracle(inst, lo, hi, num, den, pa, pw, ex.reshape(Hd, Wd), 4)
         total += len(bps)
     assert total >= 25
+
+
+def test_breakpoint_check_rejects_planted_mistakes():
+    """The oracle-based proof of a breakpoint list fails on a list with a
+    breakpoint dropped, a breakpoint moved, a piece's slope changed, or a
+    pixel's exit piece changed."""
+    from helpers import check_breakpoints_oracle, envelope
+    rng = np.random.default_rng(31)
+    for _ in range(200):
+        Wd, Hd = int(rng.integers(2, 4)), int(rng.integers(2, 4))
+        inst = W.tiny_random(rng, Wd, Hd, 4, cmax=60, L=1, p_seed=0.0)
+        sets, A, w = source_set_lines(inst)
+        bps, pieces, psets = envelope(sets, A, w, 0, 100)
+        if len(bps) >= 2:
+            break
+    assert len(bps) >= 2
+    ex = np.full(Wd * Hd, len(bps) + 1, dtype=np.int64)
+    for j in range(len(psets) - 1, -1, -1):
+        ex[~psets[j]] = j
+    num = [b.numerator for b in bps]
+    den = [b.denominator for b in bps]
+    pa = [a for a, _ in pieces]
+    pw = [b for _, b in pieces]
+    good = (num, den, pa, pw, ex)
+
+    def check(num, den, pa, pw, ex):
+        check_breakpoints_oracle(inst, 0, 100, np.array(num, dtype=np.int64), np.array(den, dtype=np.int64),
+                                 np.array(pa, dtype=np.int64), np.array(pw, dtype=np.int64),
+                                 np.asarray(ex).reshape(Hd, Wd), 2)
+
+    check(*good)
+    bad = [
+        (num[1:], den[1:], pa[1:], pw[1:], np.maximum(ex - 1, 0)),   # first breakpoint dropped
+        ([num[0] + 1] + num[1:], den, pa, pw, ex),                     # first breakpoint moved
+        (num, den, pa, [pw[0] + 1] + pw[1:], ex),                      # a slope changed
+    ]
+    moved = ex.copy()
+    i = int(np.argmax((ex > 0) & (ex <= len(bps))))
+    moved[i] = ex[i] - 1 if ex[i] > 0 else ex[i] + 1
+    bad.append((num, den, pa, pw, moved))                              # one exit piece changed
+    for b in bad:
+        with pytest.raises(AssertionError):
+            check(*b)
